@@ -1,0 +1,191 @@
+"""Benchmark: one training step of the layered-mesh renderer on one MI355X.
+
+Step = rasterise every layer in every view from scratch (visibility), shade
+and blend the image (forward), and the texture adjoint of the RGB L2 loss
+against a seeded target (backward, fused loss gradient), including zeroing
+the texture gradients.  Workload: the k = 7 displaced-shell scene (101,760
+triangles per layer, 1024^2 RGBA f32 textures) seen from 64 ring views at
+1024 x 1024.  Inputs are seeded synthetic data already resident in HBM.
+
+Prints one JSON line.  Metric: shaded pixel-layers per second, where the
+number of shaded pixel-layers is the number of covered visibility slots
+(implementation independent: visibility is bit-exact).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "shaded px·layers/s fwd+bwd (k=7, 1024², 64 views); % HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def byte_model(scene, n_views, P_v, U):
+    """Algorithmic bytes per launch of each kernel (byte model)."""
+    k = scene.k
+    P = n_views * P_v
+    G = sum(12 * m.n_vert + 8 * m.n_vert + 12 * m.n_tri for m in scene.layers)
+    tex_bytes = sum(16 * int(u) for u in U)
+    grad_planes = sum(16 * t.shape[0] * t.shape[1] for t in scene.textures)
+    return {
+        "raster": 8 * k * P + G * n_views,                     # vis write + geometry per view
+        "shade_fwd": 8 * k * P + 16 * P + tex_bytes + G,       # vis read, RGBA write, texels, geometry
+        "shade_bwd": 8 * k * P + 16 * P + tex_bytes + 2 * grad_planes + G,  # vis, target, texels, grad RMW
+        "grad_zero": grad_planes,
+    }
+
+
+def cpu_baseline(scene, n_threads):
+    """The oracle as it stands, one view per thread (ctypes releases the GIL)."""
+    import concurrent.futures as cf
+
+    import oracle as O
+    cams = scene.cameras[:n_threads]
+
+    def one(v):
+        cam = scene.cameras[v]
+        vis = O.raster_layers(scene.layers, cam)
+        O.shade(scene.layers, scene.textures, cam, vis)
+        O.backward(scene.layers, scene.textures, cam, vis, target=scene.targets[v])
+        return int((vis != np.uint64(0xFFFFFFFFFFFFFFFF)).sum())
+
+    O.build(force=False)
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(n_threads) as ex:
+        covered = sum(ex.map(one, range(len(cams))))
+    dt = time.perf_counter() - t0
+    return {"value": covered / dt, "unit": "px*layers/s", "cores": n_threads, "kind": "oracle",
+            "sample": f"{len(cams)} of the 64 views (full 1024x1024, k=7), raster+shade+adjoint, one view per "
+                      f"thread, {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--views", type=int, default=64)
+    ap.add_argument("--res", type=int, default=1024)
+    ap.add_argument("--bin", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=8)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only; --gpus must be 1 (views would shard across GPUs, "
+              "with one all-reduce of the texture gradients per step)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2409_02482_amd as P
+    import scenes as S
+
+    log("[bench] building scene")
+    scene = S.make_config(6, n_views=args.views, resolution=(args.res, args.res))
+    k = scene.k
+    nv = len(scene.cameras)
+    P_v = args.res * args.res
+    dev = "cuda"
+    layers = P.Layers(scene.layers, dev)
+    views = P.Views(scene.cameras, dev)
+    tex = [torch.from_numpy(t).to(dev) for t in scene.textures]
+    target = torch.from_numpy(np.concatenate([t.reshape(-1, 4) for t in scene.targets])).to(dev)
+    grads = [torch.zeros_like(t) for t in tex]
+    out = torch.empty(views.total_pixels, 4, dtype=torch.float32, device=dev)
+    vis = torch.empty(k * views.total_pixels, dtype=torch.int64, device=dev)
+    ws = P.alloc_workspace(layers, views, args.bin, dev)
+    loss_scale = 1.0 / (views.total_pixels * 3)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        P.raster(layers, views, vis, ws, bin=args.bin)
+        if ev is not None:
+            ev[1].record(stream)
+        P.render(layers, tex, views, vis, ws, out=out)
+        if ev is not None:
+            ev[2].record(stream)
+        for g in grads:
+            g.zero_()
+        if ev is not None:
+            ev[3].record(stream)
+        P.render_backward(layers, tex, views, vis, ws, grad_tex=grads, target=target, loss_scale=loss_scale)
+        if ev is not None:
+            ev[4].record(stream)
+
+    log("[bench] warmup")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    st = P.read_status(ws)
+    visn = vis.view(torch.uint64) if hasattr(torch, "uint64") else None
+    covered = int((vis != -1).sum().item())
+    # distinct texels touched per layer (for the byte model), from the visibility of this run
+    U = [int(t.shape[0] * t.shape[1]) for t in scene.textures]  # upper bound: every texel
+    log(f"[bench] covered slots {covered} status {st}")
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(evs[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    phase = np.array([[evs[s][i].elapsed_time(evs[s][i + 1]) for i in range(4)] for s in range(args.steps)])
+    ms_phase = phase.mean(0)
+    ms_step = float(phase.sum(1).mean())
+    ms_wall = wall / args.steps * 1e3
+    bm = byte_model(scene, nv, P_v, U)
+    names = ["raster", "shade_fwd", "grad_zero", "shade_bwd"]
+    dom = int(np.argmax(ms_phase))
+    dom_name = names[dom]
+    achieved = bm[dom_name] / (ms_phase[dom] * 1e-3) / 1e9
+    value = covered / (ms_wall * 1e-3)
+    tri_total = sum(m.n_tri for m in scene.layers) * nv
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "px*layers/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_wall,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"k={k} displaced shells (101,760 tris/layer), {nv} ring views at "
+                               f"{args.res}x{args.res}, 1024^2 f32 RGBA textures, raster+shade+adjoint (L2)",
+                   "views": nv, "k": k, "resolution": [args.res, args.res], "covered_px_layers": covered,
+                   "bin": args.bin},
+        "phases_ms": {n: float(m) for n, m in zip(names, ms_phase)},
+        "triangles_per_s": tri_total / (ms_phase[0] * 1e-3),
+        "alg_bytes_per_step": int(sum(bm[n] for n in names)),
+        "alg_frac_of_peak_step": sum(bm[n] for n in names) / (ms_wall * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        n = max(1, min(args.cpu_threads, os.cpu_count() or 1, nv))
+        res["cpu_baseline"] = cpu_baseline(scene, n)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,221 @@
+/*
+ * vs.h -- C ABI of the MI355X (gfx950) layered-mesh renderer.
+ *
+ * The library renders k nested, semi-transparent, UV-textured triangle-mesh
+ * shells in a fixed order with no sorting, and differentiates the result with
+ * respect to the textures (Volumetric Surfaces, arXiv 2409.02482):
+ *
+ *   mesh shells + UV textures + cameras  ->  image
+ *
+ * Per layer the triangles are rasterised to find the first intersection of
+ * each pixel ray with that shell (Fig. 2c; sampling locations found by
+ * rasterisation, Sec. 1), the UVs are interpolated, the layer's RGBA texture
+ * is read bilinearly from the four surrounding texel centres (Fig. 5,
+ * Sec. 4.3 "Texturing Meshes"), and the layers are alpha-blended front to
+ * back from the outermost shell inward (Sec. 4.2, Eq. 6, read with the
+ * product over the layers in front of layer i, j < i).  The adjoint returns
+ * texture gradients only: geometry is fixed while textures are fit
+ * (Sec. 4.3).
+ *
+ * Conventions
+ *   - Layer 0 is the OUTERMOST shell.  Layers are independent: each keeps its
+ *     own nearest hit, and there is no depth test across layers.
+ *   - Cameras: OpenCV pinhole, world->camera (R row-major, t), x right,
+ *     y down, z forward; pixel (i, j) has its centre at (i + 1/2, j + 1/2).
+ *   - Screen positions snap to 1/256 pixel (round half to even); a triangle
+ *     with a vertex at or in front of z_near, beyond +-2^16 pixels, or not
+ *     finite, is culled (no clipping) and counted in the status block.
+ *   - Fill rule: a pixel centre on an edge belongs to the triangle only if
+ *     the edge is a top or a left edge.
+ *   - Visibility key of a slot = (bits of float(z) << 32) | triangle id, z the
+ *     perspective-correct camera depth; the slot keeps the minimum key
+ *     (nearest, ties to the smaller id).  VS_EMPTY where nothing covers.
+ *   - Textures: f32 straight (not premultiplied) RGBA, [H][W][4]; texel (i, j)
+ *     centred at ((i+1/2)/W, (j+1/2)/H); row 0 holds v in [0, 1/H).
+ *   - Output: f32 [sum_v H_v W_v][4], RGB over black, A = 1 - transmittance.
+ *
+ * Memory and streams
+ *   - Every buffer is owned by the caller.  Pointers documented "device" must
+ *     be device memory of the current HIP device; "host" pointers are read
+ *     during the call only.  The library never allocates device memory.
+ *   - All work is enqueued on the caller's stream; no call synchronises the
+ *     host except vs_read_status and vs_autotune.  No call records a memset
+ *     node, so a sequence of calls can be captured in a HIP graph (the host
+ *     arrays are read at enqueue time; replays reuse the captured values).
+ *
+ * Errors
+ *   - Every call returns a vs_status.  VS_OK = 0.  Arguments are validated on
+ *     the host before anything is enqueued; on error nothing is enqueued and
+ *     vs_last_error() (thread-local) holds a message.  Conditions only the
+ *     device can see (culled triangles, out-of-range triangle ids found in a
+ *     visibility buffer) are counted in the status block inside the
+ *     workspace; read it with vs_read_status.
+ */
+#ifndef VS_H_
+#define VS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t vs_status;
+enum {
+  VS_OK = 0,
+  VS_ERR_ARG = 1,          /* null pointer, bad count, inconsistent view table */
+  VS_ERR_SIZE = 2,         /* a size outside the documented limits */
+  VS_ERR_WORKSPACE = 3,    /* workspace missing or too small */
+  VS_ERR_HIP = 4,          /* a HIP runtime call failed */
+  VS_ERR_UNSUPPORTED = 5   /* option value not supported */
+};
+
+#define VS_MAX_LAYERS 16
+#define VS_MAX_VIEW_DIM 8192
+#define VS_MAX_TEX_DIM 16384
+#define VS_EMPTY 0xFFFFFFFFFFFFFFFFull
+
+/* One shell.  Device pointers.  xyz f32 [n_vert][3] world positions,
+ * uv f32 [n_vert][2], tri i32 [n_tri][3] vertex ids.  1 <= n_tri < 2^31. */
+typedef struct vs_mesh {
+  const float* xyz;
+  const float* uv;
+  const int32_t* tri;
+  int32_t n_vert;
+  int32_t n_tri;
+} vs_mesh;
+
+/* One layer texture.  Device pointer, f32 [height][width][4] straight RGBA. */
+typedef struct vs_texture {
+  const float* rgba;
+  int32_t width;
+  int32_t height;
+} vs_texture;
+
+/* A pinhole camera (host record). */
+typedef struct vs_camera {
+  int32_t width, height;      /* pixels, 1..VS_MAX_VIEW_DIM */
+  double fx, fy, cx, cy;      /* pixels */
+  double R[9];                /* world->camera rotation, row-major */
+  double t[3];                /* world->camera translation */
+  double z_near;              /* > 0 */
+} vs_camera;
+
+/* A view record: the camera plus the offsets that place the view in the
+ * batched buffers.  Built by vs_views_prepare; copy the same bytes to the
+ * device.  The array has n_views + 1 records: the last one holds the totals
+ * (pix_offset = total pixels, tile_offset[s] = total tiles). */
+typedef struct vs_view {
+  vs_camera cam;
+  int64_t pix_offset;         /* sum_{u<v} W_u H_u */
+  int64_t tile_offset[4];     /* sum_{u<v} ceil(W_u/S) ceil(H_u/S) for S = 8, 16, 32, 64 */
+} vs_view;
+
+/* The views of one batched call: host and device copies of the same
+ * vs_views_prepare output (n_views + 1 records each). */
+typedef struct vs_views {
+  const vs_view* host;
+  const vs_view* dev;
+  int32_t n_views;
+} vs_views;
+
+/* Raster options.  bin: screen-tile edge in pixels, one of 8, 16, 32, 64, or
+ * 0 for the library default; the result is bit-identical for every value.
+ * flags: VS_RASTER_COUNT_FRAGMENTS counts covered (triangle, pixel) pairs in
+ * the status block (costs extra atomics). */
+#define VS_RASTER_COUNT_FRAGMENTS 1
+typedef struct vs_raster_opts {
+  int32_t bin;
+  int32_t flags;
+} vs_raster_opts;
+
+/* Shading options.
+ * eps_T:  a pixel stops reading layers once every pixel of its wavefront has
+ *         transmittance below eps_T (0 = always read all k layers).  The
+ *         colour changes by at most eps_T * max|c|.
+ * wrap:   0 = repeat (the OpenGL default), 1 = clamp to edge.
+ * target: device f32 [sum_v H_v W_v][4] or NULL.  When set, the backward
+ *         pass uses the RGB L2 loss  loss_scale * sum_p ||RGB_p - target_p||^2
+ *         instead of grad_rgba (A of the target is ignored).
+ * loss_scale: multiplies the fused L2 loss (e.g. 1/number of pixels). */
+typedef struct vs_shade_opts {
+  float eps_T;
+  int32_t wrap;
+  const float* target;
+  float loss_scale;
+  int32_t reserved;
+} vs_shade_opts;
+
+/* Status block counters (vs_read_status). */
+enum {
+  VS_STAT_CULLED_INVALID = 0,   /* triangles with a vertex behind z_near, beyond the guard band or NaN */
+  VS_STAT_CULLED_DEGENERATE = 1,/* zero-area triangles after snapping */
+  VS_STAT_BAD_INDEX = 2,        /* vertex ids outside [0, n_vert) */
+  VS_STAT_FRAGMENTS = 3,        /* covered (triangle, pixel) pairs tested by the raster */
+  VS_STAT_BAD_KEY = 4,          /* visibility keys naming a triangle id >= n_tri */
+  VS_STAT_BIN_OVERFLOW = 5,     /* reserved */
+  VS_STAT_COUNT = 8
+};
+
+/* Library version string. */
+const char* vs_version(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* vs_last_error(void);
+
+/* Name of a status code. */
+const char* vs_status_string(vs_status s);
+
+/* Fill n_views + 1 view records (host memory, out[n_views + 1]) from
+ * n_views cameras (host).  Validates each camera. */
+vs_status vs_views_prepare(const vs_camera* cams, int32_t n_views, vs_view* out);
+
+/* Workspace needed by vs_raster_layers for these layers and views (bytes).
+ * The same workspace is then passed to vs_render / vs_render_backward: it
+ * carries the projected vertices and the status block. */
+size_t vs_raster_workspace_bytes(const vs_mesh* layers, int32_t k, const vs_views* views,
+                                 const vs_raster_opts* opts);
+
+/* Rasterise every layer in every view (visibility, steps 1-3).
+ * layers: host array [k] of device meshes, layer 0 outermost.  1 <= k <= 16.
+ * vis:    device u64 [sum_v k H_v W_v], written in full.  Slot of (view v,
+ *         layer l, pixel (x, y)) = k * pix_offset[v] + l * H_v W_v + y W_v + x.
+ * ws:     device workspace of at least vs_raster_workspace_bytes bytes,
+ *         256-byte aligned.  Its status block is reset by this call.
+ * opts:   may be NULL (defaults). */
+vs_status vs_raster_layers(const vs_mesh* layers, int32_t k, const vs_views* views, uint64_t* vis, void* ws,
+                           size_t ws_bytes, const vs_raster_opts* opts, void* stream);
+
+/* Shade and blend (forward, step 4).
+ * tex:  host array [k] of device textures.
+ * vis:  the visibility buffer of vs_raster_layers for the same layers/views.
+ * ws:   the workspace that vs_raster_layers filled for the same layers/views.
+ * out_rgba: device f32 [sum_v H_v W_v][4]. */
+vs_status vs_render(const vs_mesh* layers, const vs_texture* tex, int32_t k, const vs_views* views,
+                    const uint64_t* vis, const void* ws, size_t ws_bytes, float* out_rgba,
+                    const vs_shade_opts* opts, void* stream);
+
+/* Texture adjoint (step 5).
+ * grad_rgba: device f32 [sum_v H_v W_v][4] = dL/d(out_rgba); ignored (may be
+ *            NULL) when opts->target is set (fused L2 loss).
+ * grad_tex:  host array [k] of device pointers, f32 [H_l][W_l][4] each,
+ *            ACCUMULATED into (+=).  Summation order is not fixed (atomics).
+ * out_rgba:  optional device f32 [sum_v H_v W_v][4]: when non-NULL the
+ *            forward image is written too (same values as vs_render).
+ * sse:       optional device f64 [1]: when non-NULL and opts->target is set,
+ *            sum_p ||RGB_p - target_p||^2 is ACCUMULATED into it. */
+vs_status vs_render_backward(const vs_mesh* layers, const vs_texture* tex, int32_t k, const vs_views* views,
+                             const uint64_t* vis, const void* ws, size_t ws_bytes, const float* grad_rgba,
+                             float* const* grad_tex, float* out_rgba, double* sse, const vs_shade_opts* opts,
+                             void* stream);
+
+/* Copy the status block (VS_STAT_COUNT int64 counters) to host memory.
+ * Synchronises the stream. */
+vs_status vs_read_status(const void* ws, size_t ws_bytes, int64_t* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VS_H_ */

@@ -1,0 +1,12 @@
+"""MI355X (gfx950) renderer for layered semi-transparent textured mesh shells.
+
+Hot path of Volumetric Surfaces (arXiv 2409.02482): fixed-order, sorting-free
+rendering of k nested UV-textured mesh shells and its texture adjoint, as
+hand-written HIP kernels behind a C ABI (include/vs.h).
+"""
+from ._lib import LIB_PATH, VsError, load  # noqa: F401
+from .render import (Layers, Renderer, Views, alloc_workspace, raster, read_status, render,  # noqa: F401
+                     render_backward, workspace_bytes)
+
+__all__ = ["Layers", "Views", "Renderer", "raster", "render", "render_backward", "read_status",
+           "workspace_bytes", "alloc_workspace", "load", "VsError", "LIB_PATH"]

@@ -1,0 +1,156 @@
+// Device-side data layout and exact arithmetic shared by the gfx950 kernels.
+//
+// The visibility computation is specified in integer arithmetic plus a fixed
+// FP64 recipe so that it is reproducible bit for bit; this file holds that
+// recipe.  It is compiled with -ffp-contract=off: no multiply-add may fuse
+// in the projection and depth expressions below.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vs.h"
+
+namespace vs {
+
+constexpr int kMaxLayers = VS_MAX_LAYERS;
+constexpr uint64_t kEmpty = VS_EMPTY;
+constexpr int32_t kInvalidX = INT32_MIN;
+constexpr int kWrapClamp = 1;   // vs_shade_opts::wrap value for clamp-to-edge (0 = repeat)
+
+// Per-layer mesh table, passed by value as a kernel argument.
+struct LayerTable {
+  const float* xyz[kMaxLayers];
+  const float* uv[kMaxLayers];
+  const int32_t* tri[kMaxLayers];
+  int32_t n_vert[kMaxLayers];
+  int32_t n_tri[kMaxLayers];
+  int64_t vert_off[kMaxLayers + 1];  // prefix of n_vert: layer l's vertices in one view's projected block
+  int64_t tri_off[kMaxLayers + 1];   // prefix of n_tri
+  int32_t k;
+};
+
+// Per-layer texture table (and gradient planes), passed by value.
+struct TexTable {
+  const float4* tex[kMaxLayers];
+  float* grad[kMaxLayers];
+  int32_t w[kMaxLayers];
+  int32_t h[kMaxLayers];
+};
+
+// Projected vertex: snapped screen position in 1/256 px and w = 1/z.
+// X == kInvalidX marks a vertex that invalidates its triangles.
+struct alignas(16) ProjVert {
+  int32_t X, Y;
+  double w;
+};
+
+// Workspace layout (offsets in bytes from the 256-aligned workspace base).
+struct WsLayout {
+  size_t status;     // VS_STAT_COUNT u64 counters
+  size_t proj;       // ProjVert [n_views][sum n_vert]
+  size_t total;
+};
+
+__host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ------------------------------------------------------------------ step 1
+// Camera transform, projection and snapping to 1/256 px (round half to even),
+// w = 1/z.  FP64, left to right, unfused.
+__device__ inline ProjVert project_vertex(const float* p, const vs_camera& c) {
+  ProjVert o;
+  o.X = kInvalidX;
+  o.Y = kInvalidX;
+  o.w = 0.0;
+  const double px = p[0], py = p[1], pz = p[2];
+  const double xc = ((c.R[0] * px + c.R[1] * py) + c.R[2] * pz) + c.t[0];
+  const double yc = ((c.R[3] * px + c.R[4] * py) + c.R[5] * pz) + c.t[1];
+  const double zc = ((c.R[6] * px + c.R[7] * py) + c.R[8] * pz) + c.t[2];
+  if (!(__builtin_isfinite(xc) && __builtin_isfinite(yc) && __builtin_isfinite(zc))) return o;
+  if (!(zc > c.z_near)) return o;
+  const double xs = c.fx * (xc / zc) + c.cx;
+  const double ys = c.fy * (yc / zc) + c.cy;
+  if (!(__builtin_fabs(xs) < 65536.0 && __builtin_fabs(ys) < 65536.0)) return o;
+  o.X = (int32_t)__builtin_rint(xs * 256.0);
+  o.Y = (int32_t)__builtin_rint(ys * 256.0);
+  o.w = 1.0 / zc;
+  return o;
+}
+
+// ------------------------------------------------------------------ step 2
+// Triangle after orientation normalisation.  Screen coordinates are integers
+// below 2^25 in magnitude, so every edge-function value (< 2^51) is exact in
+// FP64; the kernels evaluate edge functions in doubles.
+struct TriSetup {
+  double X[3], Y[3];
+  double w[3];
+  int32_t vid[3];
+  double area2;      // > 0
+  double th[3];      // inside iff E_e >= th_e: 0 for an owned (top/left) edge, 1 otherwise
+};
+
+enum { kTriOk = 0, kTriInvalid = 1, kTriDegenerate = 2, kTriBadIndex = 3 };
+
+// Top-left ownership of directed edge P->Q, y down: going up, or horizontal going right.
+__device__ inline bool top_left(double px, double py, double qx, double qy) {
+  const double dy = qy - py, dx = qx - px;
+  return dy < 0.0 || (dy == 0.0 && dx > 0.0);
+}
+
+// ids are the three vertex ids of the triangle; pv the projected vertices of
+// its layer in this view.
+__device__ inline int setup_triangle(const int32_t* ids, int32_t n_vert, const ProjVert* pv, TriSetup& T) {
+  int32_t id[3] = {ids[0], ids[1], ids[2]};
+  if ((uint32_t)id[0] >= (uint32_t)n_vert || (uint32_t)id[1] >= (uint32_t)n_vert ||
+      (uint32_t)id[2] >= (uint32_t)n_vert)
+    return kTriBadIndex;
+  ProjVert a = pv[id[0]], b = pv[id[1]], c = pv[id[2]];
+  if (a.X == kInvalidX || b.X == kInvalidX || c.X == kInvalidX) return kTriInvalid;
+  double area2 = ((double)b.X - (double)a.X) * ((double)c.Y - (double)a.Y) -
+                 ((double)b.Y - (double)a.Y) * ((double)c.X - (double)a.X);
+  if (area2 == 0.0) return kTriDegenerate;
+  if (area2 < 0.0) {
+    const ProjVert t = b; b = c; c = t;
+    const int32_t ti = id[1]; id[1] = id[2]; id[2] = ti;
+    area2 = -area2;
+  }
+  T.X[0] = a.X; T.Y[0] = a.Y; T.w[0] = a.w;
+  T.X[1] = b.X; T.Y[1] = b.Y; T.w[1] = b.w;
+  T.X[2] = c.X; T.Y[2] = c.Y; T.w[2] = c.w;
+  T.vid[0] = id[0]; T.vid[1] = id[1]; T.vid[2] = id[2];
+  T.area2 = area2;
+  T.th[0] = top_left(T.X[1], T.Y[1], T.X[2], T.Y[2]) ? 0.0 : 1.0;
+  T.th[1] = top_left(T.X[2], T.Y[2], T.X[0], T.Y[0]) ? 0.0 : 1.0;
+  T.th[2] = top_left(T.X[0], T.Y[0], T.X[1], T.Y[1]) ? 0.0 : 1.0;
+  return kTriOk;
+}
+
+// Edge functions at sample point (px, py) (1/256 px units):
+// E0 = cross(c-b, P-b), E1 = cross(a-c, P-c), E2 = cross(b-a, P-a).
+__device__ inline void edge_values(const TriSetup& T, double px, double py, double E[3]) {
+  E[0] = (T.X[2] - T.X[1]) * (py - T.Y[1]) - (T.Y[2] - T.Y[1]) * (px - T.X[1]);
+  E[1] = (T.X[0] - T.X[2]) * (py - T.Y[2]) - (T.Y[0] - T.Y[2]) * (px - T.X[2]);
+  E[2] = (T.X[1] - T.X[0]) * (py - T.Y[0]) - (T.Y[1] - T.Y[0]) * (px - T.X[0]);
+}
+
+// Visibility key: bits of float(z) in the high word, triangle id in the low
+// word; z = area2 / (E0 wa + E1 wb + E2 wc), the perspective-correct depth.
+__device__ inline uint64_t depth_key(const TriSetup& T, double E0, double E1, double E2, uint32_t t) {
+  const double s = (E0 * T.w[0] + E1 * T.w[1]) + E2 * T.w[2];
+  const double z = T.area2 / s;
+  const float zf = (float)z;
+  return ((uint64_t)__float_as_uint(zf) << 32) | (uint64_t)t;
+}
+
+// Binary search of the view that owns flat index g in a prefix array read
+// with stride (records of vs_view).  Returns v with off(v) <= g < off(v+1).
+__device__ inline int find_view_tile(const vs_view* views, int n_views, int64_t g, int slot) {
+  int lo = 0, hi = n_views;  // invariant: off(lo) <= g < off(hi)
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (views[mid].tile_offset[slot] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace vs

@@ -1,0 +1,230 @@
+"""PyTorch-facing binding of the gfx950 renderer.
+
+Torch supplies device memory and the stream; every step of the render runs
+in the HIP kernels behind the C ABI (include/vs.h).  The classes here only
+marshal tensors into the C structs:
+
+  Layers    k meshes on the device (layer 0 outermost)
+  Views     batched cameras (host + device view tables)
+  raster / render / render_backward   thin wrappers of the three entry points
+  Renderer  owns the visibility buffer and workspace of a fixed scene and
+            exposes a differentiable ``__call__(*textures) -> rgba``
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as C
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, what: str) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return t
+
+
+class Layers:
+    """k meshes on the device.  ``meshes``: objects with xyz [V,3], uv [V,2], tri [T,3] (numpy or torch)."""
+
+    def __init__(self, meshes, device="cuda"):
+        self.k = len(meshes)
+        if not 1 <= self.k <= C.VS_MAX_LAYERS:
+            raise ValueError(f"k = {self.k} outside 1..{C.VS_MAX_LAYERS}")
+        self.tensors = []
+        self.c = (C.VsMesh * self.k)()
+        for l, m in enumerate(meshes):
+            xyz = torch.as_tensor(np.asarray(m.xyz, np.float32)).to(device).contiguous()
+            uv = torch.as_tensor(np.asarray(m.uv, np.float32)).to(device).contiguous()
+            tri = torch.as_tensor(np.asarray(m.tri, np.int32)).to(device).contiguous()
+            self.tensors.append((xyz, uv, tri))
+            self.c[l] = C.VsMesh(xyz.data_ptr(), uv.data_ptr(), tri.data_ptr(), xyz.shape[0], tri.shape[0])
+        self.n_tri = [int(t[2].shape[0]) for t in self.tensors]
+
+
+def camera_struct(cam) -> C.VsCamera:
+    c = C.VsCamera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    R = np.asarray(cam.R, np.float64).reshape(9)
+    t = np.asarray(cam.t, np.float64).reshape(3)
+    for i in range(9):
+        c.R[i] = float(R[i])
+    for i in range(3):
+        c.t[i] = float(t[i])
+    c.z_near = float(getattr(cam, "z_near", 0.01))
+    return c
+
+
+class Views:
+    """Batched cameras: the host view table (vs_views_prepare) and its device copy."""
+
+    def __init__(self, cameras: Sequence, device="cuda"):
+        n = len(cameras)
+        cams = (C.VsCamera * n)(*[camera_struct(c) for c in cameras])
+        self.host = (C.VsView * (n + 1))()
+        C.check(C.load().vs_views_prepare(ctypes.addressof(cams), n, ctypes.addressof(self.host)),
+                "vs_views_prepare")
+        raw = np.frombuffer(bytes(self.host), np.uint8).copy()
+        self.dev = torch.from_numpy(raw).to(device)
+        self.c = C.VsViews(ctypes.addressof(self.host), self.dev.data_ptr(), n)
+        self.n = n
+        self.sizes = [(int(c.height), int(c.width)) for c in cameras]
+        self.pix_offset = [int(self.host[v].pix_offset) for v in range(n + 1)]
+        self.total_pixels = self.pix_offset[n]
+
+    def image(self, flat: torch.Tensor, v: int) -> torch.Tensor:
+        """View v of a flat [sum_v H_v W_v, C] buffer as [H, W, C]."""
+        h, w = self.sizes[v]
+        return flat[self.pix_offset[v]:self.pix_offset[v + 1]].view(h, w, -1)
+
+    def vis_planes(self, vis: torch.Tensor, k: int, v: int) -> torch.Tensor:
+        """View v of a visibility buffer as [k, H, W] (int64 storage of the u64 keys)."""
+        h, w = self.sizes[v]
+        o = k * self.pix_offset[v]
+        return vis[o:o + k * h * w].view(k, h, w)
+
+
+def textures_struct(textures: Sequence[torch.Tensor]):
+    arr = (C.VsTexture * len(textures))()
+    for l, t in enumerate(textures):
+        _dev(t, torch.float32, f"texture {l}")
+        if t.dim() != 3 or t.shape[2] != 4:
+            raise ValueError(f"texture {l} must be [H, W, 4]")
+        arr[l] = C.VsTexture(t.data_ptr(), t.shape[1], t.shape[0])
+    return arr
+
+
+def workspace_bytes(layers: Layers, views: Views, bin: int = 0) -> int:
+    opts = C.VsRasterOpts(bin, 0)
+    n = C.load().vs_raster_workspace_bytes(ctypes.addressof(layers.c), layers.k, ctypes.byref(views.c),
+                                           ctypes.byref(opts))
+    if n == 0:
+        C.check(C.VS_ERR_ARG, "vs_raster_workspace_bytes")
+    return int(n)
+
+
+def alloc_workspace(layers: Layers, views: Views, bin: int = 0, device="cuda") -> torch.Tensor:
+    return torch.empty(workspace_bytes(layers, views, bin), dtype=torch.uint8, device=device)
+
+
+def raster(layers: Layers, views: Views, vis: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+           bin: int = 0, count_fragments: bool = False, stream=None):
+    """vs_raster_layers: returns (vis int64[sum_v k H_v W_v] holding u64 keys, workspace)."""
+    dev = views.dev.device
+    if vis is None:
+        vis = torch.empty(layers.k * views.total_pixels, dtype=torch.int64, device=dev)
+    if ws is None:
+        ws = alloc_workspace(layers, views, bin, dev)
+    _dev(vis, torch.int64, "vis")
+    opts = C.VsRasterOpts(bin, C.VS_RASTER_COUNT_FRAGMENTS if count_fragments else 0)
+    C.check(C.load().vs_raster_layers(ctypes.addressof(layers.c), layers.k, ctypes.byref(views.c), vis.data_ptr(),
+                                      ws.data_ptr(), ws.numel(), ctypes.byref(opts), _stream(stream)),
+            "vs_raster_layers")
+    return vis, ws
+
+
+def _shade_opts(eps_T=0.0, wrap=0, target=None, loss_scale=1.0):
+    return C.VsShadeOpts(float(eps_T), int(wrap), 0 if target is None else target.data_ptr(), float(loss_scale), 0)
+
+
+def render(layers: Layers, textures, views: Views, vis: torch.Tensor, ws: torch.Tensor,
+           out: Optional[torch.Tensor] = None, eps_T: float = 0.0, wrap: int = 0, stream=None) -> torch.Tensor:
+    """vs_render: [sum_v H_v W_v, 4] RGBA (A = 1 - transmittance)."""
+    if out is None:
+        out = torch.empty(views.total_pixels, 4, dtype=torch.float32, device=vis.device)
+    _dev(out, torch.float32, "out")
+    tex = textures_struct(textures)
+    opts = _shade_opts(eps_T, wrap)
+    C.check(C.load().vs_render(ctypes.addressof(layers.c), ctypes.addressof(tex), layers.k, ctypes.byref(views.c),
+                               vis.data_ptr(), ws.data_ptr(), ws.numel(), out.data_ptr(), ctypes.byref(opts),
+                               _stream(stream)), "vs_render")
+    return out
+
+
+def render_backward(layers: Layers, textures, views: Views, vis: torch.Tensor, ws: torch.Tensor,
+                    grad_rgba: Optional[torch.Tensor] = None, grad_tex: Optional[List[torch.Tensor]] = None,
+                    target: Optional[torch.Tensor] = None, loss_scale: float = 1.0,
+                    out: Optional[torch.Tensor] = None, sse: Optional[torch.Tensor] = None, wrap: int = 0,
+                    stream=None) -> List[torch.Tensor]:
+    """vs_render_backward: accumulates dL/dtexture into grad_tex (zeros if None) and returns it."""
+    if grad_tex is None:
+        grad_tex = [torch.zeros_like(t) for t in textures]
+    for l, g in enumerate(grad_tex):
+        _dev(g, torch.float32, f"grad_tex[{l}]")
+    if grad_rgba is not None:
+        _dev(grad_rgba, torch.float32, "grad_rgba")
+    if target is not None:
+        _dev(target, torch.float32, "target")
+    if out is not None:
+        _dev(out, torch.float32, "out")
+    if sse is not None:
+        _dev(sse, torch.float64, "sse")
+    tex = textures_struct(textures)
+    gp = (ctypes.c_void_p * layers.k)(*[g.data_ptr() for g in grad_tex])
+    opts = _shade_opts(0.0, wrap, target, loss_scale)
+    C.check(C.load().vs_render_backward(
+        ctypes.addressof(layers.c), ctypes.addressof(tex), layers.k, ctypes.byref(views.c), vis.data_ptr(),
+        ws.data_ptr(), ws.numel(), None if grad_rgba is None else grad_rgba.data_ptr(), ctypes.addressof(gp),
+        None if out is None else out.data_ptr(), None if sse is None else sse.data_ptr(), ctypes.byref(opts),
+        _stream(stream)), "vs_render_backward")
+    return grad_tex
+
+
+def read_status(ws: torch.Tensor, stream=None) -> dict:
+    out = (ctypes.c_int64 * C.VS_STAT_COUNT)()
+    C.check(C.load().vs_read_status(ws.data_ptr(), ws.numel(), ctypes.addressof(out), _stream(stream)),
+            "vs_read_status")
+    return {n: int(out[i]) for i, n in enumerate(C.STAT_NAMES)}
+
+
+class _RenderFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, renderer, *textures):
+        ctx.renderer = renderer
+        ctx.save_for_backward(*textures)
+        return render(renderer.layers, textures, renderer.views, renderer.vis, renderer.ws,
+                      eps_T=renderer.eps_T, wrap=renderer.wrap)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        r = ctx.renderer
+        textures = ctx.saved_tensors
+        grads = render_backward(r.layers, textures, r.views, r.vis, r.ws, grad_rgba=grad_out.contiguous(),
+                                wrap=r.wrap)
+        return (None, *grads)
+
+
+class Renderer:
+    """A fixed scene (meshes + cameras): rasterised once, then differentiable in the textures.
+
+    Geometry and cameras receive no gradient: textures are fit on fixed meshes.
+    """
+
+    def __init__(self, meshes, cameras, device="cuda", bin: int = 0, eps_T: float = 0.0, wrap: int = 0):
+        self.layers = meshes if isinstance(meshes, Layers) else Layers(meshes, device)
+        self.views = cameras if isinstance(cameras, Views) else Views(cameras, device)
+        self.eps_T, self.wrap, self.bin = eps_T, wrap, bin
+        self.vis, self.ws = raster(self.layers, self.views, bin=bin)
+
+    def rasterize(self):
+        raster(self.layers, self.views, self.vis, self.ws, bin=self.bin)
+        return self.vis
+
+    def __call__(self, *textures: torch.Tensor) -> torch.Tensor:
+        return _RenderFn.apply(self, *textures)
+
+    def status(self) -> dict:
+        return read_status(self.ws)

@@ -1,0 +1,167 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+struct layouts agree with the C compiler, and host-side validation rejects bad
+arguments before anything is enqueued (no GPU needed)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import scenes as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def C():
+    from paper_2409_02482_amd import _lib
+    _lib.load()
+    return _lib
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "vs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vs_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(C):
+    lib = C.load()
+    names = _declared_symbols()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), f"libvs.so does not export {n}"
+        assert n in C.SIGNATURES, f"binding has no signature for {n}"
+    out = subprocess.run(["nm", "-D", "--defined-only", C.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (vs_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_struct_layouts_match_c(C, tmp_path):
+    prog = tmp_path / "sz.c"
+    prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "vs.h"\nint main(void){'
+                    'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(vs_mesh), sizeof(vs_texture),'
+                    'sizeof(vs_camera), sizeof(vs_view), sizeof(vs_views), sizeof(vs_raster_opts),'
+                    'sizeof(vs_shade_opts), offsetof(vs_view, pix_offset), offsetof(vs_shade_opts, target));'
+                    'return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    want = [ctypes.sizeof(C.VsMesh), ctypes.sizeof(C.VsTexture), ctypes.sizeof(C.VsCamera),
+            ctypes.sizeof(C.VsView), ctypes.sizeof(C.VsViews), ctypes.sizeof(C.VsRasterOpts),
+            ctypes.sizeof(C.VsShadeOpts), C.VsView.pix_offset.offset, C.VsShadeOpts.target.offset]
+    assert got == want
+
+
+def _cams(sizes):
+    from paper_2409_02482_amd.render import camera_struct
+    cams = S.ring_cameras(3, len(sizes), sizes)
+    return (C_lib().VsCamera * len(cams))(*[camera_struct(c) for c in cams]), cams
+
+
+def C_lib():
+    from paper_2409_02482_amd import _lib
+    return _lib
+
+
+def test_views_prepare_offsets(C):
+    sizes = [(512, 512), (640, 480), (37, 53), (1920, 1080), (1, 1)]
+    arr, cams = _cams(sizes)
+    out = (C.VsView * (len(sizes) + 1))()
+    assert C.load().vs_views_prepare(ctypes.addressof(arr), len(sizes), ctypes.addressof(out)) == C.VS_OK
+    pix, tiles = 0, [0, 0, 0, 0]
+    for v, (w, h) in enumerate(sizes + [(0, 0)]):
+        assert out[v].pix_offset == pix
+        assert list(out[v].tile_offset) == tiles
+        pix += w * h
+        tiles = [t + (-(-w // s)) * (-(-h // s)) for t, s in zip(tiles, (8, 16, 32, 64))]
+    assert out[0].cam.width == 512 and abs(out[3].cam.fy - cams[3].fy) == 0
+
+
+def test_views_prepare_rejects_bad_camera(C):
+    arr, _ = _cams([(64, 64), (64, 64)])
+    out = (C.VsView * 3)()
+    arr[1].width = 0
+    assert C.load().vs_views_prepare(ctypes.addressof(arr), 2, ctypes.addressof(out)) == C.VS_ERR_SIZE
+    arr[1].width = 64
+    arr[1].z_near = 0.0
+    assert C.load().vs_views_prepare(ctypes.addressof(arr), 2, ctypes.addressof(out)) == C.VS_ERR_ARG
+    arr[1].z_near = 0.01
+    arr[1].R[4] = float("nan")
+    assert C.load().vs_views_prepare(ctypes.addressof(arr), 2, ctypes.addressof(out)) == C.VS_ERR_ARG
+    assert b"rotation" in C.load().vs_last_error()
+
+
+def _fake_call_args(C, k=2, n_views=1):
+    """Host-side structs with non-null fake device pointers: only validation runs."""
+    arr, _ = _cams([(64, 48)] * n_views)
+    host = (C.VsView * (n_views + 1))()
+    assert C.load().vs_views_prepare(ctypes.addressof(arr), n_views, ctypes.addressof(host)) == 0
+    views = C.VsViews(ctypes.addressof(host), 0x1000, n_views)
+    meshes = (C.VsMesh * k)(*[C.VsMesh(0x1000, 0x2000, 0x3000, 10, 5) for _ in range(k)])
+    tex = (C.VsTexture * k)(*[C.VsTexture(0x4000, 8, 8) for _ in range(k)])
+    return host, views, meshes, tex
+
+
+def test_raster_validation_without_gpu(C):
+    L = C.load()
+    host, views, meshes, tex = _fake_call_args(C)
+    need = L.vs_raster_workspace_bytes(ctypes.addressof(meshes), 2, ctypes.byref(views), None)
+    assert need >= 256 + 2 * 0
+    # k out of range
+    assert L.vs_raster_layers(ctypes.addressof(meshes), 0, ctypes.byref(views), 0x5000, 0x100000, need, None,
+                              None) == C.VS_ERR_SIZE
+    assert L.vs_raster_layers(ctypes.addressof(meshes), 17, ctypes.byref(views), 0x5000, 0x100000, need, None,
+                              None) == C.VS_ERR_SIZE
+    # null vis
+    assert L.vs_raster_layers(ctypes.addressof(meshes), 2, ctypes.byref(views), None, 0x100000, need, None,
+                              None) == C.VS_ERR_ARG
+    # workspace too small / misaligned / null
+    assert L.vs_raster_layers(ctypes.addressof(meshes), 2, ctypes.byref(views), 0x5000, 0x100000, need - 1, None,
+                              None) == C.VS_ERR_WORKSPACE
+    assert L.vs_raster_layers(ctypes.addressof(meshes), 2, ctypes.byref(views), 0x5000, 0x100010, need, None,
+                              None) == C.VS_ERR_WORKSPACE
+    assert L.vs_raster_layers(ctypes.addressof(meshes), 2, ctypes.byref(views), 0x5000, None, need, None,
+                              None) == C.VS_ERR_WORKSPACE
+    # null mesh pointer
+    meshes[1].tri = None
+    assert L.vs_raster_layers(ctypes.addressof(meshes), 2, ctypes.byref(views), 0x5000, 0x100000, need, None,
+                              None) == C.VS_ERR_ARG
+    assert b"layer 1" in L.vs_last_error()
+    # a tampered view table
+    meshes[1].tri = 0x3000
+    host[1].pix_offset += 1
+    assert L.vs_raster_layers(ctypes.addressof(meshes), 2, ctypes.byref(views), 0x5000, 0x100000, need, None,
+                              None) == C.VS_ERR_ARG
+
+
+def test_render_validation_without_gpu(C):
+    L = C.load()
+    host, views, meshes, tex = _fake_call_args(C)
+    need = L.vs_raster_workspace_bytes(ctypes.addressof(meshes), 2, ctypes.byref(views), None)
+    bad = C.VsShadeOpts(0.0, 7, None, 1.0, 0)
+    assert L.vs_render(ctypes.addressof(meshes), ctypes.addressof(tex), 2, ctypes.byref(views), 0x5000, 0x100000,
+                       need, 0x6000, ctypes.byref(bad), None) == C.VS_ERR_UNSUPPORTED
+    neg = C.VsShadeOpts(-1.0, 0, None, 1.0, 0)
+    assert L.vs_render(ctypes.addressof(meshes), ctypes.addressof(tex), 2, ctypes.byref(views), 0x5000, 0x100000,
+                       need, 0x6000, ctypes.byref(neg), None) == C.VS_ERR_ARG
+    tex[0].width = 20000
+    assert L.vs_render(ctypes.addressof(meshes), ctypes.addressof(tex), 2, ctypes.byref(views), 0x5000, 0x100000,
+                       need, 0x6000, None, None) == C.VS_ERR_SIZE
+    tex[0].width = 8
+    gp = (ctypes.c_void_p * 2)(0x7000, None)
+    assert L.vs_render_backward(ctypes.addressof(meshes), ctypes.addressof(tex), 2, ctypes.byref(views), 0x5000,
+                                0x100000, need, 0x6000, ctypes.addressof(gp), None, None, None, None) == C.VS_ERR_ARG
+    gp = (ctypes.c_void_p * 2)(0x7000, 0x8000)
+    # neither grad_rgba nor a target
+    assert L.vs_render_backward(ctypes.addressof(meshes), ctypes.addressof(tex), 2, ctypes.byref(views), 0x5000,
+                                0x100000, need, None, ctypes.addressof(gp), None, None, None, None) == C.VS_ERR_ARG
+
+
+def test_status_strings(C):
+    L = C.load()
+    assert L.vs_status_string(0) == b"VS_OK"
+    assert L.vs_status_string(3) == b"VS_ERR_WORKSPACE"
+    assert L.vs_version().startswith(b"volsurf")
