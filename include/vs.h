@@ -122,12 +122,19 @@ typedef struct vs_views {
 
 /* Raster options.  bin: screen-tile edge in pixels, one of 8, 16, 32, 64, or
  * 0 for the library default; the result is bit-identical for every value.
+ * The workspace must have been sized for the same bin value.
  * flags: VS_RASTER_COUNT_FRAGMENTS counts covered (triangle, pixel) pairs in
- * the status block (costs extra atomics). */
+ * the status block (costs extra atomics); VS_RASTER_DIRECT uses the unbinned
+ * one-thread-per-triangle path with global atomics (a slower, independent
+ * implementation of the same result, kept for cross-checking). */
 #define VS_RASTER_COUNT_FRAGMENTS 1
+#define VS_RASTER_DIRECT 2
 typedef struct vs_raster_opts {
   int32_t bin;
   int32_t flags;
+  int64_t list_capacity;      /* triangle-list entries reserved in the workspace; 0 = automatic.
+                                 Bins that do not fit are still rasterised exactly, more slowly,
+                                 and counted in VS_STAT_BIN_OVERFLOW. */
 } vs_raster_opts;
 
 /* Shading options.
@@ -154,7 +161,7 @@ enum {
   VS_STAT_BAD_INDEX = 2,        /* vertex ids outside [0, n_vert) */
   VS_STAT_FRAGMENTS = 3,        /* covered (triangle, pixel) pairs tested by the raster */
   VS_STAT_BAD_KEY = 4,          /* visibility keys naming a triangle id >= n_tri */
-  VS_STAT_BIN_OVERFLOW = 5,     /* reserved */
+  VS_STAT_BIN_OVERFLOW = 5,     /* bins whose triangle list exceeded the workspace (still exact, slower) */
   VS_STAT_COUNT = 8
 };
 
@@ -213,6 +220,48 @@ vs_status vs_render_backward(const vs_mesh* layers, const vs_texture* tex, int32
 /* Copy the status block (VS_STAT_COUNT int64 counters) to host memory.
  * Synchronises the stream. */
 vs_status vs_read_status(const void* ws, size_t ws_bytes, int64_t* out, void* stream);
+
+/* Pick the raster bin size for these layers and views by timing every bin
+ * size whose workspace fits in ws_bytes (size the workspace with bin = 8 to
+ * allow all of them) with HIP events on the stream; all candidates must give
+ * the same visibility checksum, else VS_ERR_HIP.  On return inout->bin holds
+ * the fastest bin (inout->flags and list_capacity are kept).  cache_path
+ * (may be NULL): a text file of "key bin" lines; a hit skips the timing, a
+ * miss appends.  Synchronises the stream; never call it while capturing.
+ * vis and ws are overwritten (vis holds a valid result afterwards). */
+vs_status vs_autotune(const vs_mesh* layers, int32_t k, const vs_views* views, uint64_t* vis, void* ws,
+                      size_t ws_bytes, vs_raster_opts* inout, const char* cache_path, void* stream);
+
+/* ---- texture fitting (textures are fit on fixed meshes, Sec. 4.3) ---- */
+
+/* Adam hyper-parameters; after each step every texel scalar is projected to [lo, hi]. */
+typedef struct vs_adam_opts {
+  float lr, beta1, beta2, eps, lo, hi;
+} vs_adam_opts;
+
+/* One fused Adam step over k texture planes: params, grads, m, v are host
+ * arrays [k] of device pointers to f32 buffers of counts[l] scalars each
+ * (counts: host array, multiples of 4, 16-byte aligned buffers).  The step
+ * number is read from *step (device int32, t = *step + 1), so a captured graph
+ * advances it on every replay.  After the update every gradient scalar is
+ * reset to 0.  Then, in stream order: if sse (device f64 [1]) is non-NULL,
+ * history[*step] = *sse when *step < hist_len (history: device f64
+ * [hist_len] or NULL) and *sse = 0; finally ++*step. */
+vs_status vs_adam_step(float* const* params, float* const* grads, float* const* m, float* const* v,
+                       const int64_t* counts, int32_t k, const vs_adam_opts* opts, int32_t* step, double* sse,
+                       double* history, int32_t hist_len, void* stream);
+
+/* ---- HIP graphs: capture a sequence of the calls above on one stream ---- */
+typedef struct vs_graph_s* vs_graph;
+
+/* Start capturing work enqueued on stream (must not be the null stream). */
+vs_status vs_graph_begin(void* stream);
+/* End the capture and instantiate it; *out receives the executable graph. */
+vs_status vs_graph_end(void* stream, vs_graph* out);
+/* Replay a captured graph on stream. */
+vs_status vs_graph_launch(vs_graph g, void* stream);
+/* Release a graph (NULL is ignored). */
+vs_status vs_graph_destroy(vs_graph g);
 
 #ifdef __cplusplus
 }

@@ -5,8 +5,8 @@ rendering of k nested UV-textured mesh shells and its texture adjoint, as
 hand-written HIP kernels behind a C ABI (include/vs.h).
 """
 from ._lib import LIB_PATH, VsError, load  # noqa: F401
-from .render import (Layers, Renderer, Views, alloc_workspace, raster, read_status, render,  # noqa: F401
-                     render_backward, workspace_bytes)
+from .render import (Graph, Layers, Renderer, Views, adam_step, alloc_workspace, autotune, raster,  # noqa: F401
+                     read_status, render, render_backward, workspace_bytes)
 
 __all__ = ["Layers", "Views", "Renderer", "raster", "render", "render_backward", "read_status",
-           "workspace_bytes", "alloc_workspace", "load", "VsError", "LIB_PATH"]
+           "workspace_bytes", "alloc_workspace", "autotune", "adam_step", "Graph", "load", "VsError", "LIB_PATH"]

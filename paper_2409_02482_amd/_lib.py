@@ -18,6 +18,7 @@ VS_OK, VS_ERR_ARG, VS_ERR_SIZE, VS_ERR_WORKSPACE, VS_ERR_HIP, VS_ERR_UNSUPPORTED
 VS_MAX_LAYERS = 16
 VS_EMPTY = 0xFFFFFFFFFFFFFFFF
 VS_RASTER_COUNT_FRAGMENTS = 1
+VS_RASTER_DIRECT = 2
 STAT_NAMES = ["culled_invalid", "culled_degenerate", "bad_index", "fragments", "bad_key", "bin_overflow",
               "reserved6", "reserved7"]
 VS_STAT_COUNT = 8
@@ -45,7 +46,11 @@ class VsViews(ctypes.Structure):
 
 
 class VsRasterOpts(ctypes.Structure):
-    _fields_ = [("bin", c_i32), ("flags", c_i32)]
+    _fields_ = [("bin", c_i32), ("flags", c_i32), ("list_capacity", c_i64)]
+
+
+class VsAdamOpts(ctypes.Structure):
+    _fields_ = [("lr", c_f32), ("beta1", c_f32), ("beta2", c_f32), ("eps", c_f32), ("lo", c_f32), ("hi", c_f32)]
 
 
 class VsShadeOpts(ctypes.Structure):
@@ -63,6 +68,12 @@ SIGNATURES = {
     "vs_render": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp, c_vp, c_vp]),
     "vs_render_backward": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "vs_read_status": (c_i32, [c_vp, c_sz, c_vp, c_vp]),
+    "vs_autotune": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp, ctypes.c_char_p, c_vp]),
+    "vs_adam_step": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp]),
+    "vs_graph_begin": (c_i32, [c_vp]),
+    "vs_graph_end": (c_i32, [c_vp, c_vp]),
+    "vs_graph_launch": (c_i32, [c_vp, c_vp]),
+    "vs_graph_destroy": (c_i32, [c_vp]),
 }
 
 _lib = None

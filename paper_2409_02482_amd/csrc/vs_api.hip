@@ -2,16 +2,21 @@
 // workspace layout and kernel launches on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
+#include <vector>
 
 #include "vs.h"
 #include "vs_common.h"
 #include "vs_raster.h"
 #include "vs_shade.h"
+#include "vs_fit.h"
 
 namespace {
 
@@ -111,17 +116,41 @@ vs_status build_textures(const vs_texture* tex, int32_t k, vs::TexTable& X) {
     X.tex[l] = reinterpret_cast<const float4*>(tex[l].rgba);
     X.w[l] = tex[l].width;
     X.h[l] = tex[l].height;
+    X.inv_w[l] = 1.0 / tex[l].width;
+    X.inv_h[l] = 1.0 / tex[l].height;
   }
   return VS_OK;
 }
 
-vs::WsLayout ws_layout(const vs::LayerTable& L, int n_views) {
+int bin_slot(int bin) { return bin == 8 ? 0 : bin == 16 ? 1 : bin == 32 ? 2 : bin == 64 ? 3 : -1; }
+
+constexpr int kDefaultBin = 16;
+
+vs::WsLayout ws_layout(const vs::LayerTable& L, const vs_views* views, int bin, int64_t capacity = 0) {
   vs::WsLayout w;
+  const int n_views = views->n_views;
+  w.bin = bin ? bin : kDefaultBin;
+  w.slot = bin_slot(w.bin);
+  const vs_view& tot = views->host[n_views];
+  w.n_tiles16 = tot.tile_offset[1];
+  w.n_tiles_bin = w.slot >= 0 ? tot.tile_offset[w.slot] : 0;
+  w.n_bins = w.n_tiles_bin * L.k;
+  w.n_partial = (w.n_bins + 1023) / 1024;
+  const uint64_t tris = (uint64_t)n_views * (uint64_t)L.tri_off[L.k];
+  const uint64_t factor = w.bin == 8 ? 4 : w.bin == 16 ? 3 : 2;
+  w.capacity = capacity > 0 ? (uint64_t)capacity : std::max<uint64_t>(tris * factor, 1u << 20);
   size_t off = 0;
-  w.status = off;
-  off += 256;
-  w.proj = off;
-  off += vs::align_up((size_t)n_views * (size_t)L.vert_off[L.k] * sizeof(vs::ProjVert), 256);
+  auto take = [&](size_t bytes) { const size_t o = off; off += vs::align_up(bytes, 256); return o; };
+  w.status = take(256);
+  w.tile_view = take((size_t)w.n_tiles16 * 4);
+  w.proj = take((size_t)n_views * (size_t)L.vert_off[L.k] * sizeof(vs::ProjVert));
+  // everything below depends on the bin size; render and backward read only the part above
+  w.bin_view = take((size_t)w.n_tiles_bin * 4);
+  w.count = take((size_t)w.n_bins * 4);
+  w.offset = take((size_t)w.n_bins * 4);
+  w.cursor = take((size_t)w.n_bins * 4);
+  w.partial = take((size_t)w.n_partial * 4);
+  w.list = take((size_t)w.capacity * 4);
   w.total = off;
   return w;
 }
@@ -183,10 +212,12 @@ vs_status vs_views_prepare(const vs_camera* cams, int32_t n_views, vs_view* out)
 
 size_t vs_raster_workspace_bytes(const vs_mesh* layers, int32_t k, const vs_views* views,
                                  const vs_raster_opts* opts) {
-  (void)opts;
   vs::LayerTable L;
   if (build_layers(layers, k, L) || check_views(views)) return 0;
-  return ws_layout(L, views->n_views).total;
+  const int bin = opts ? opts->bin : 0;
+  if (bin && bin_slot(bin) < 0) return 0;
+  if (opts && opts->list_capacity < 0) return 0;
+  return ws_layout(L, views, bin, opts ? opts->list_capacity : 0).total;
 }
 
 vs_status vs_raster_layers(const vs_mesh* layers, int32_t k, const vs_views* views, uint64_t* vis, void* ws,
@@ -196,22 +227,72 @@ vs_status vs_raster_layers(const vs_mesh* layers, int32_t k, const vs_views* vie
   if (st) return st;
   if ((st = check_views(views))) return st;
   if (!vis) return fail(VS_ERR_ARG, "vis: null");
-  const vs::WsLayout lay = ws_layout(L, views->n_views);
+  const int bin = opts ? opts->bin : 0;
+  if (bin && bin_slot(bin) < 0) return fail(VS_ERR_UNSUPPORTED, "bin = %d (use 0, 8, 16, 32 or 64)", bin);
+  if ((uint64_t)views->n_views * (uint64_t)L.tri_off[k] >= (1ull << 30))
+    return fail(VS_ERR_SIZE, "n_views * total triangles must be below 2^30");
+  const int64_t cap = opts ? opts->list_capacity : 0;
+  if (cap < 0 || cap >= (1ll << 32)) return fail(VS_ERR_SIZE, "list_capacity must be in [0, 2^32)");
+  const vs::WsLayout lay = ws_layout(L, views, bin, cap);
   if ((st = check_ws(ws, ws_bytes, lay.total))) return st;
-  const int count_frags = opts ? (opts->flags & VS_RASTER_COUNT_FRAGMENTS) : 0;
+  const int flags = opts ? opts->flags : 0;
+  const int count_frags = flags & VS_RASTER_COUNT_FRAGMENTS;
   hipStream_t s = (hipStream_t)stream;
   char* base = (char*)ws;
   auto* status = (unsigned long long*)(base + lay.status);
   auto* proj = (vs::ProjVert*)(base + lay.proj);
+  auto* tile_view = (int32_t*)(base + lay.tile_view);
+  auto* bin_view = (int32_t*)(base + lay.bin_view);
+  auto* count = (uint32_t*)(base + lay.count);
+  auto* offset = (uint32_t*)(base + lay.offset);
+  auto* cursor = (uint32_t*)(base + lay.cursor);
+  auto* partial = (uint32_t*)(base + lay.partial);
+  auto* list = (int32_t*)(base + lay.list);
   const int64_t vpv = L.vert_off[k];
-  const int64_t total_slots = (int64_t)k * views->host[views->n_views].pix_offset;
   const int nv = views->n_views;
+  const int64_t ntri = L.tri_off[k];
   hipLaunchKernelGGL(vs::k_fill_u64, dim3(1), dim3(256), 0, s, (uint64_t*)status, (int64_t)VS_STAT_COUNT, 0ull);
-  hipLaunchKernelGGL(vs::k_fill_u64, dim3((unsigned)std::min<int64_t>(grid_1d(total_slots, 256), 65536)), dim3(256),
-                     0, s, vis, total_slots, (uint64_t)VS_EMPTY);
+  hipLaunchKernelGGL(vs::k_tile_view, dim3(grid_1d(lay.n_tiles16, 256)), dim3(256), 0, s, views->dev, nv, tile_view,
+                     lay.n_tiles16);
   hipLaunchKernelGGL(vs::k_project, dim3(grid_1d(vpv, 256), nv), dim3(256), 0, s, views->dev, L, proj, vpv);
-  hipLaunchKernelGGL(vs::k_raster_direct, dim3(grid_1d(L.tri_off[k], 256), nv), dim3(256), 0, s, views->dev, L,
-                     (const vs::ProjVert*)proj, vpv, (unsigned long long*)vis, status, count_frags);
+  if (flags & VS_RASTER_DIRECT) {
+    const int64_t total_slots = (int64_t)k * views->host[nv].pix_offset;
+    hipLaunchKernelGGL(vs::k_fill_u64, dim3((unsigned)std::min<int64_t>(grid_1d(total_slots, 256), 65536)),
+                       dim3(256), 0, s, vis, total_slots, (uint64_t)VS_EMPTY);
+    hipLaunchKernelGGL(vs::k_raster_direct, dim3(grid_1d(ntri, 256), nv), dim3(256), 0, s, views->dev, L,
+                       (const vs::ProjVert*)proj, vpv, (unsigned long long*)vis, status, count_frags);
+    if ((st = check_launch("vs_raster_layers"))) return st;
+    return ok();
+  }
+  const int B = lay.bin, slot = lay.slot;
+  const unsigned fill_grid = (unsigned)std::min<int64_t>(grid_1d(lay.n_bins, 256), 65536);
+  hipLaunchKernelGGL(vs::k_tile_view_slot, dim3(grid_1d(lay.n_tiles_bin, 256)), dim3(256), 0, s, views->dev, nv,
+                     bin_view, lay.n_tiles_bin, slot);
+  hipLaunchKernelGGL(vs::k_fill_u32, dim3(fill_grid), dim3(256), 0, s, count, lay.n_bins, 0u);
+  hipLaunchKernelGGL(vs::k_fill_u32, dim3(fill_grid), dim3(256), 0, s, cursor, lay.n_bins, 0u);
+  hipLaunchKernelGGL(vs::k_bin_count, dim3(grid_1d(ntri, 256), nv), dim3(256), 0, s, views->dev, L,
+                     (const vs::ProjVert*)proj, vpv, B, slot, count, status);
+  hipLaunchKernelGGL(vs::k_scan_local, dim3((unsigned)lay.n_partial), dim3(256), 0, s, (const uint32_t*)count,
+                     offset, partial, lay.n_bins);
+  hipLaunchKernelGGL(vs::k_scan_partials, dim3(1), dim3(1024), 0, s, partial, lay.n_partial);
+  hipLaunchKernelGGL(vs::k_scan_add, dim3(grid_1d(lay.n_bins, 256)), dim3(256), 0, s, offset,
+                     (const uint32_t*)partial, lay.n_bins);
+  hipLaunchKernelGGL(vs::k_bin_scatter, dim3(grid_1d(ntri, 256), nv), dim3(256), 0, s, views->dev, L,
+                     (const vs::ProjVert*)proj, vpv, B, slot, (const uint32_t*)count, (const uint32_t*)offset, cursor,
+                     list, lay.capacity, status);
+  const unsigned nblk = (unsigned)((lay.n_bins + 7) / 8 * 8);
+  auto raster = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(nblk), dim3(vs::kRasterThreads), 0, s, views->dev, (const int32_t*)bin_view,
+                       lay.n_tiles_bin, L, (const vs::ProjVert*)proj, vpv, slot, (const uint32_t*)count,
+                       (const uint32_t*)offset, (const int32_t*)list, lay.capacity, (unsigned long long*)vis, status,
+                       count_frags);
+  };
+  switch (B) {
+    case 8: raster(vs::k_raster_bins<8>); break;
+    case 16: raster(vs::k_raster_bins<16>); break;
+    case 32: raster(vs::k_raster_bins<32>); break;
+    default: raster(vs::k_raster_bins<64>); break;
+  }
   if ((st = check_launch("vs_raster_layers"))) return st;
   return ok();
 }
@@ -226,8 +307,9 @@ vs_status vs_render(const vs_mesh* layers, const vs_texture* tex, int32_t k, con
   if ((st = build_textures(tex, k, X))) return st;
   if ((st = check_views(views))) return st;
   if (!vis || !out_rgba) return fail(VS_ERR_ARG, "vis/out_rgba: null");
-  const vs::WsLayout lay = ws_layout(L, views->n_views);
-  if ((st = check_ws(ws, ws_bytes, lay.total))) return st;
+  const vs::WsLayout lay = ws_layout(L, views, 0);
+  if ((st = check_ws(ws, ws_bytes, lay.proj + (size_t)views->n_views * L.vert_off[k] * sizeof(vs::ProjVert))))
+    return st;
   const float eps = opts ? opts->eps_T : 0.0f;
   const int wrap = opts ? opts->wrap : 0;
   if (wrap != 0 && wrap != 1) return fail(VS_ERR_UNSUPPORTED, "wrap = %d", wrap);
@@ -237,8 +319,10 @@ vs_status vs_render(const vs_mesh* layers, const vs_texture* tex, int32_t k, con
   const auto* proj = (const vs::ProjVert*)(base + lay.proj);
   hipStream_t s = (hipStream_t)stream;
   const int64_t tiles = total_tiles(views, vs::kShadeTileSlot);
-  hipLaunchKernelGGL(vs::k_shade_fwd, dim3((unsigned)tiles), dim3(256), 0, s, views->dev, views->n_views, L, X, proj,
-                     L.vert_off[k], vis, (float4*)out_rgba, eps, wrap, status);
+  const auto* tile_view = (const int32_t*)(base + lay.tile_view);
+  hipLaunchKernelGGL(vs::k_shade_fwd, dim3((unsigned)vs::shade_grid_blocks(tiles)), dim3(256), 0, s, views->dev,
+                     views->n_views, tile_view, tiles, L, X, proj, L.vert_off[k], vis, (float4*)out_rgba, eps, wrap,
+                     status);
   if ((st = check_launch("vs_render"))) return st;
   return ok();
 }
@@ -264,15 +348,18 @@ vs_status vs_render_backward(const vs_mesh* layers, const vs_texture* tex, int32
   const float scale = opts ? opts->loss_scale : 1.0f;
   const int wrap = opts ? opts->wrap : 0;
   if (wrap != 0 && wrap != 1) return fail(VS_ERR_UNSUPPORTED, "wrap = %d", wrap);
-  const vs::WsLayout lay = ws_layout(L, views->n_views);
-  if ((st = check_ws(ws, ws_bytes, lay.total))) return st;
+  const vs::WsLayout lay = ws_layout(L, views, 0);
+  if ((st = check_ws(ws, ws_bytes, lay.proj + (size_t)views->n_views * L.vert_off[k] * sizeof(vs::ProjVert))))
+    return st;
   const char* base = (const char*)ws;
   auto* status = (unsigned long long*)(base + lay.status);
   const auto* proj = (const vs::ProjVert*)(base + lay.proj);
   hipStream_t s = (hipStream_t)stream;
   const int64_t tiles = total_tiles(views, vs::kShadeTileSlot);
+  const auto* tile_view = (const int32_t*)(base + lay.tile_view);
   auto launch = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(256), 0, s, views->dev, views->n_views, L, X, proj,
+    hipLaunchKernelGGL(kern, dim3((unsigned)vs::shade_grid_blocks(tiles)), dim3(256), 0, s, views->dev,
+                       views->n_views, tile_view, tiles, L, X, proj,
                        L.vert_off[k], vis, (const float4*)grad_rgba, (const float4*)target, scale,
                        (float4*)out_rgba, target ? sse : nullptr, wrap, status);
   };
@@ -294,3 +381,193 @@ vs_status vs_read_status(const void* ws, size_t ws_bytes, int64_t* out, void* st
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ autotune
+
+namespace {
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+  const unsigned char* b = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+uint64_t problem_key(const vs::LayerTable& L, const vs_views* views) {
+  uint64_t h = 1469598103934665603ull;
+  h = fnv1a(h, &L.k, sizeof(L.k));
+  for (int l = 0; l < L.k; ++l) {
+    h = fnv1a(h, &L.n_vert[l], 4);
+    h = fnv1a(h, &L.n_tri[l], 4);
+  }
+  h = fnv1a(h, &views->n_views, 4);
+  for (int v = 0; v < views->n_views; ++v) {
+    h = fnv1a(h, &views->host[v].cam.width, 4);
+    h = fnv1a(h, &views->host[v].cam.height, 4);
+  }
+  return h;
+}
+
+int cache_lookup(const char* path, uint64_t key) {
+  if (!path) return 0;
+  std::ifstream f(path);
+  std::string line;
+  int found = 0;
+  while (std::getline(f, line)) {
+    std::istringstream ss(line);
+    std::string hex;
+    int bin = 0;
+    if (ss >> hex >> bin && std::strtoull(hex.c_str(), nullptr, 16) == key && bin_slot(bin) >= 0) found = bin;
+  }
+  return found;
+}
+
+}  // namespace
+
+extern "C" vs_status vs_autotune(const vs_mesh* layers, int32_t k, const vs_views* views, uint64_t* vis, void* ws,
+                                 size_t ws_bytes, vs_raster_opts* inout, const char* cache_path, void* stream) {
+  vs::LayerTable L;
+  vs_status st = build_layers(layers, k, L);
+  if (st) return st;
+  if ((st = check_views(views))) return st;
+  if (!inout || !vis || !ws) return fail(VS_ERR_ARG, "vs_autotune: null pointer");
+  const uint64_t key = problem_key(L, views);
+  const int cached = cache_lookup(cache_path, key);
+  if (cached) {
+    inout->bin = cached;
+    return ok();
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(VS_ERR_HIP, "vs_autotune: hipEventCreate failed");
+  const int cands[4] = {8, 16, 32, 64};
+  float best_ms = 1e30f;
+  int best = 0;
+  unsigned long long ref_sum = 0;
+  bool have_ref = false;
+  const int64_t n_slots = (int64_t)k * views->host[views->n_views].pix_offset;
+  auto* sum_dev = (unsigned long long*)((char*)ws + 7 * sizeof(unsigned long long));  // status slot 7
+  vs_status result = VS_OK;
+  for (int ci = 0; ci < 4 && result == VS_OK; ++ci) {
+    vs_raster_opts o = *inout;
+    o.bin = cands[ci];
+    o.flags &= ~VS_RASTER_DIRECT;
+    if (ws_layout(L, views, o.bin, o.list_capacity).total > ws_bytes) continue;
+    float ms = 1e30f;
+    for (int rep = 0; rep < 4 && result == VS_OK; ++rep) {
+      if (hipEventRecord(e0, s) != hipSuccess) { result = fail(VS_ERR_HIP, "vs_autotune: event record failed"); break; }
+      result = vs_raster_layers(layers, k, views, vis, ws, ws_bytes, &o, stream);
+      if (result != VS_OK) break;
+      float t = 0.f;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+        result = fail(VS_ERR_HIP, "vs_autotune: event timing failed");
+      if (rep > 0) ms = std::min(ms, t);
+    }
+    if (result != VS_OK) break;
+    hipLaunchKernelGGL(vs::k_fill_u64, dim3(1), dim3(64), 0, s, (uint64_t*)sum_dev, (int64_t)1, 0ull);
+    hipLaunchKernelGGL(vs::k_vis_checksum, dim3(1024), dim3(256), 0, s, (const uint64_t*)vis, n_slots, sum_dev);
+    unsigned long long sum = 0;
+    if (hipMemcpyAsync(&sum, sum_dev, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      result = fail(VS_ERR_HIP, "vs_autotune: checksum copy failed");
+    if (result != VS_OK) break;
+    if (!have_ref) { ref_sum = sum; have_ref = true; }
+    else if (sum != ref_sum) result = fail(VS_ERR_HIP, "vs_autotune: bin %d gives a different visibility buffer", o.bin);
+    if (ms < best_ms) { best_ms = ms; best = o.bin; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (result != VS_OK) return result;
+  if (!best) return fail(VS_ERR_WORKSPACE, "vs_autotune: no bin size fits the workspace");
+  // leave vis holding the chosen configuration's result (identical for every bin)
+  inout->bin = best;
+  if (cache_path) {
+    std::ofstream f(cache_path, std::ios::app);
+    char line[64];
+    snprintf(line, sizeof(line), "%016llx %d\n", (unsigned long long)key, best);
+    f << line;
+  }
+  return ok();
+}
+
+// ------------------------------------------------------------------ fitting
+
+extern "C" vs_status vs_adam_step(float* const* params, float* const* grads, float* const* m, float* const* v,
+                                  const int64_t* counts, int32_t k, const vs_adam_opts* opts, int32_t* step,
+                                  double* sse, double* history, int32_t hist_len, void* stream) {
+  if (!params || !grads || !m || !v || !counts || !opts || !step) return fail(VS_ERR_ARG, "vs_adam_step: null pointer");
+  if (k < 1 || k > VS_MAX_LAYERS) return fail(VS_ERR_SIZE, "vs_adam_step: k = %d", k);
+  vs::AdamTable A;
+  std::memset(&A, 0, sizeof(A));
+  A.k = k;
+  for (int l = 0; l < k; ++l) {
+    if (!params[l] || !grads[l] || !m[l] || !v[l]) return fail(VS_ERR_ARG, "vs_adam_step: layer %d null", l);
+    if (counts[l] <= 0 || counts[l] % 4) return fail(VS_ERR_SIZE, "vs_adam_step: count %d not a positive multiple of 4", l);
+    for (const void* p : {(const void*)params[l], (const void*)grads[l], (const void*)m[l], (const void*)v[l]})
+      if ((uintptr_t)p % 16) return fail(VS_ERR_ARG, "vs_adam_step: layer %d buffer not 16-byte aligned", l);
+    A.p[l] = params[l]; A.g[l] = grads[l]; A.m[l] = m[l]; A.v[l] = v[l];
+    A.off[l + 1] = A.off[l] + counts[l];
+  }
+  for (int l = k + 1; l <= VS_MAX_LAYERS; ++l) A.off[l] = A.off[k];
+  if (!(opts->lr >= 0.f) || !(opts->beta1 >= 0.f && opts->beta1 < 1.f) || !(opts->beta2 >= 0.f && opts->beta2 < 1.f) ||
+      !(opts->eps > 0.f) || !(opts->lo <= opts->hi))
+    return fail(VS_ERR_ARG, "vs_adam_step: bad hyper-parameters");
+  if (history && hist_len < 0) return fail(VS_ERR_ARG, "vs_adam_step: hist_len < 0");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n4 = A.off[k] / 4;
+  const unsigned grid = (unsigned)std::min<int64_t>(grid_1d(n4, 256), 8192);
+  hipLaunchKernelGGL(vs::k_adam, dim3(grid), dim3(256), 0, s, A, opts->lr, opts->beta1, opts->beta2, opts->eps, opts->lo,
+                     opts->hi, (const int32_t*)step);
+  hipLaunchKernelGGL(vs::k_fit_bookkeep, dim3(1), dim3(64), 0, s, sse, history, hist_len, step);
+  vs_status st = check_launch("vs_adam_step");
+  if (st) return st;
+  return ok();
+}
+
+// ------------------------------------------------------------------ graphs
+
+struct vs_graph_s {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+extern "C" vs_status vs_graph_begin(void* stream) {
+  if (!stream) return fail(VS_ERR_ARG, "vs_graph_begin: the null stream cannot be captured");
+  const hipError_t e = hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return fail(VS_ERR_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+  return ok();
+}
+
+extern "C" vs_status vs_graph_end(void* stream, vs_graph* out) {
+  if (!stream || !out) return fail(VS_ERR_ARG, "vs_graph_end: null pointer");
+  *out = nullptr;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture((hipStream_t)stream, &g);
+  if (e != hipSuccess) return fail(VS_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(VS_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  *out = new vs_graph_s{g, x};
+  return ok();
+}
+
+extern "C" vs_status vs_graph_launch(vs_graph g, void* stream) {
+  if (!g) return fail(VS_ERR_ARG, "vs_graph_launch: null graph");
+  const hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(VS_ERR_HIP, "hipGraphLaunch: %s", hipGetErrorString(e));
+  return ok();
+}
+
+extern "C" vs_status vs_graph_destroy(vs_graph g) {
+  if (!g) return ok();
+  (void)hipGraphExecDestroy(g->exec);
+  (void)hipGraphDestroy(g->graph);
+  delete g;
+  return ok();
+}

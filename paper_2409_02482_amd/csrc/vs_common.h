@@ -36,6 +36,8 @@ struct TexTable {
   float* grad[kMaxLayers];
   int32_t w[kMaxLayers];
   int32_t h[kMaxLayers];
+  double inv_w[kMaxLayers];
+  double inv_h[kMaxLayers];
 };
 
 // Projected vertex: snapped screen position in 1/256 px and w = 1/z.
@@ -48,7 +50,17 @@ struct alignas(16) ProjVert {
 // Workspace layout (offsets in bytes from the 256-aligned workspace base).
 struct WsLayout {
   size_t status;     // VS_STAT_COUNT u64 counters
+  size_t tile_view;  // int32 [16-pixel tiles of all views]: owning view (shading)
+  size_t bin_view;   // int32 [B-pixel tiles of all views]: owning view (raster bins)
   size_t proj;       // ProjVert [n_views][sum n_vert]
+  size_t count;      // u32 [n_bins] triangles per bin
+  size_t offset;     // u32 [n_bins] exclusive prefix of count
+  size_t cursor;     // u32 [n_bins] scatter cursors
+  size_t partial;    // u32 [ceil(n_bins / 1024)] scan block totals
+  size_t list;       // int32 [capacity] triangle ids of all bins
+  int64_t n_tiles16, n_tiles_bin, n_bins, n_partial;
+  uint64_t capacity;
+  int bin, slot;
   size_t total;
 };
 

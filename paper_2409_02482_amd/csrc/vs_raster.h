@@ -1,13 +1,34 @@
 // Visibility kernels (steps 1-3): vertex projection and per-layer
 // rasterisation into 64-bit (depth, triangle id) keys.
+//
+// Binned pipeline (one call of vs_raster_layers):
+//   k_project      snapped screen positions and w = 1/z for every (view, layer, vertex)
+//   k_bin_count    per triangle: setup, cull, bounding box -> screen tiles of
+//                  B x B pixels; count triangles per bin = (view, tile, layer)
+//   k_scan_*       exclusive prefix sum of the counts -> list offsets
+//   k_bin_scatter  write triangle ids into the bin lists
+//   k_raster_bins  one block per bin: an LDS tile of keys starts EMPTY, the
+//                  bin's triangles take 64-bit LDS minima, and the finished
+//                  tile is stored once, coalesced (so no clear pass is needed)
+// Atomics on bin counters are aggregated per wavefront: lanes that hit the
+// same bin elect one lane that adds the whole group.
 #pragma once
 
 #include "vs_common.h"
 
 namespace vs {
 
+constexpr int kRasterThreads = 256;
+constexpr int kSmallSpan = 16384;   // small-triangle path: bbox extents <= 64 px, so edge values fit int32
+constexpr int kSmallArea = 64;      // ... and at most this many candidate pixels in the tile
+
 // Fill n u64 words with a value (grid-stride).
 __global__ void __launch_bounds__(256) k_fill_u64(uint64_t* __restrict__ p, int64_t n, uint64_t val) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = val;
+}
+
+__global__ void __launch_bounds__(256) k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t val) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = val;
 }
@@ -25,10 +46,318 @@ __global__ void __launch_bounds__(256) k_project(const vs_view* __restrict__ vie
   proj[(int64_t)v * vpv + g] = project_vertex(L.xyz[l] + 3 * i, views[v].cam);
 }
 
-// Steps 2-3, direct form: one thread per (view, layer, triangle); the thread
-// walks its triangle's fixed-point bounding box and takes a 64-bit atomic
-// minimum into the layer's visibility plane (which must hold EMPTY before).
-// grid.x covers the triangles of all layers (tri_off prefix), grid.y = view.
+// Pixel-centre range covered by the triangle's fixed-point bounding box, clipped to the view.
+struct PixRange { int i0, i1, j0, j1; };
+
+__device__ inline PixRange pixel_range(const TriSetup& T, int W, int H) {
+  const double mnx = fmin(T.X[0], fmin(T.X[1], T.X[2])), mxx = fmax(T.X[0], fmax(T.X[1], T.X[2]));
+  const double mny = fmin(T.Y[0], fmin(T.Y[1], T.Y[2])), mxy = fmax(T.Y[0], fmax(T.Y[1], T.Y[2]));
+  PixRange r;
+  r.i0 = max((int)ceil((mnx - 128.0) * (1.0 / 256.0)), 0);
+  r.i1 = min((int)floor((mxx - 128.0) * (1.0 / 256.0)), W - 1);
+  r.j0 = max((int)ceil((mny - 128.0) * (1.0 / 256.0)), 0);
+  r.j1 = min((int)floor((mxy - 128.0) * (1.0 / 256.0)), H - 1);
+  return r;
+}
+
+__device__ inline int cull_slot(int r) {
+  return r == kTriInvalid ? VS_STAT_CULLED_INVALID : r == kTriDegenerate ? VS_STAT_CULLED_DEGENERATE
+                                                                        : VS_STAT_BAD_INDEX;
+}
+
+// Bin index of (global tile g, layer l): bins of one tile are consecutive.
+__device__ inline int64_t bin_index(int64_t g, int l, int k) { return g * k + l; }
+
+// Shared front end of the count and scatter passes: the triangle handled by
+// this thread and its tile span.  Returns false if it covers no pixel.
+struct BinWork {
+  int v, l;
+  int32_t t;
+  int tx0, tx1, ty0, ty1;   // tile span (inclusive)
+  int64_t g0;               // global tile index of the view's tile (0, 0)
+  int ntx;                  // tiles per row in this view
+};
+
+__device__ inline bool bin_front(const vs_view* __restrict__ views, const LayerTable& L,
+                                 const ProjVert* __restrict__ proj, int64_t vpv, int B, int slot, BinWork& w,
+                                 unsigned long long* status, bool count_culls) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  const int k = L.k;
+  if (g >= L.tri_off[k]) return false;
+  int l = 0;
+  while (l + 1 < k && L.tri_off[l + 1] <= g) ++l;
+  const int32_t t = (int32_t)(g - L.tri_off[l]);
+  const vs_view& V = views[v];
+  const int W = V.cam.width, H = V.cam.height;
+  const ProjVert* P = proj + (int64_t)v * vpv + L.vert_off[l];
+  TriSetup T;
+  const int r = setup_triangle(L.tri[l] + 3 * (int64_t)t, L.n_vert[l], P, T);
+  if (r != kTriOk) {
+    if (count_culls) atomicAdd(status + cull_slot(r), 1ull);
+    return false;
+  }
+  const PixRange pr = pixel_range(T, W, H);
+  if (pr.i0 > pr.i1 || pr.j0 > pr.j1) return false;
+  w.v = v; w.l = l; w.t = t;
+  w.tx0 = pr.i0 / B; w.tx1 = pr.i1 / B; w.ty0 = pr.j0 / B; w.ty1 = pr.j1 / B;
+  w.g0 = V.tile_offset[slot];
+  w.ntx = (W + B - 1) / B;
+  return true;
+}
+
+// Count triangles per bin.
+__global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ views, LayerTable L,
+                                                   const ProjVert* __restrict__ proj, int64_t vpv, int B, int slot,
+                                                   uint32_t* __restrict__ count, unsigned long long* __restrict__ status) {
+  BinWork w;
+  const bool ok = bin_front(views, L, proj, vpv, B, slot, w, status, true);
+  const int k = L.k;
+  // first bin of every lane: aggregated across the wavefront
+  int64_t b0 = ok ? bin_index(w.g0 + (int64_t)w.ty0 * w.ntx + w.tx0, w.l, k) : -1;
+  uint64_t active = __ballot(b0 >= 0);
+  while (active) {
+    const int leader = __ffsll((unsigned long long)active) - 1;
+    const int64_t lb = __shfl(b0, leader);
+    const uint64_t same = __ballot(b0 == lb);
+    if ((int)__lane_id() == leader) atomicAdd(count + lb, (uint32_t)__popcll(same));
+    active &= ~same;
+  }
+  if (!ok) return;
+  for (int ty = w.ty0; ty <= w.ty1; ++ty)
+    for (int tx = w.tx0; tx <= w.tx1; ++tx) {
+      if (ty == w.ty0 && tx == w.tx0) continue;
+      atomicAdd(count + bin_index(w.g0 + (int64_t)ty * w.ntx + tx, w.l, k), 1u);
+    }
+}
+
+// Exclusive scan, pass 1: each block scans 1024 counts, writes local prefixes and its total.
+__global__ void __launch_bounds__(256) k_scan_local(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                    uint32_t* __restrict__ partial, int64_t n) {
+  __shared__ uint32_t s[256];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * 1024 + tid * 4;
+  uint32_t v[4];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    v[q] = base + q < n ? in[base + q] : 0u;
+    sum += v[q];
+  }
+  s[tid] = sum;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t add = tid >= off ? s[tid - off] : 0u;
+    __syncthreads();
+    s[tid] += add;
+    __syncthreads();
+  }
+  uint32_t run = s[tid] - sum;  // exclusive prefix of this thread
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (base + q < n) out[base + q] = run;
+    run += v[q];
+  }
+  if (tid == 255) partial[blockIdx.x] = s[255];
+}
+
+// Pass 2: one block scans the block totals in place (exclusive), carrying across chunks.
+__global__ void __launch_bounds__(1024) k_scan_partials(uint32_t* __restrict__ partial, int64_t n) {
+  __shared__ uint32_t s[1024];
+  __shared__ uint32_t carry;
+  const int tid = threadIdx.x;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < n; base += 1024) {
+    const uint32_t v = base + tid < n ? partial[base + tid] : 0u;
+    s[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const uint32_t add = tid >= off ? s[tid - off] : 0u;
+      __syncthreads();
+      s[tid] += add;
+      __syncthreads();
+    }
+    if (base + tid < n) partial[base + tid] = carry + s[tid] - v;
+    __syncthreads();
+    if (tid == 1023) carry += s[1023];
+    __syncthreads();
+  }
+}
+
+// Pass 3: add the block prefixes.
+__global__ void __launch_bounds__(256) k_scan_add(uint32_t* __restrict__ out, const uint32_t* __restrict__ partial,
+                                                  int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += partial[i / 1024];
+}
+
+// Write triangle ids into the bin lists.  A bin whose list would end past the
+// capacity is left unwritten; the raster of that bin then scans every
+// triangle of its layer instead (slow but exact) and the overflow is counted.
+__global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__ views, LayerTable L,
+                                                     const ProjVert* __restrict__ proj, int64_t vpv, int B, int slot,
+                                                     const uint32_t* __restrict__ count,
+                                                     const uint32_t* __restrict__ offset,
+                                                     uint32_t* __restrict__ cursor, int32_t* __restrict__ list,
+                                                     uint64_t capacity, unsigned long long* __restrict__ status) {
+  BinWork w;
+  const bool ok = bin_front(views, L, proj, vpv, B, slot, w, status, false);
+  const int k = L.k;
+  int64_t b0 = ok ? bin_index(w.g0 + (int64_t)w.ty0 * w.ntx + w.tx0, w.l, k) : -1;
+  uint64_t active = __ballot(b0 >= 0);
+  const uint64_t lt = __lanemask_lt();
+  while (active) {
+    const int leader = __ffsll((unsigned long long)active) - 1;
+    const int64_t lb = __shfl(b0, leader);
+    const uint64_t same = __ballot(b0 == lb);
+    uint32_t base = 0;
+    if ((int)__lane_id() == leader) base = atomicAdd(cursor + lb, (uint32_t)__popcll(same));
+    base = __shfl(base, leader);
+    if (b0 == lb) {
+      const uint64_t end = (uint64_t)offset[lb] + count[lb];
+      if (end <= capacity) list[offset[lb] + base + __popcll(same & lt)] = w.t;
+    }
+    active &= ~same;
+  }
+  if (!ok) return;
+  for (int ty = w.ty0; ty <= w.ty1; ++ty)
+    for (int tx = w.tx0; tx <= w.tx1; ++tx) {
+      if (ty == w.ty0 && tx == w.tx0) continue;
+      const int64_t b = bin_index(w.g0 + (int64_t)ty * w.ntx + tx, w.l, k);
+      const uint32_t pos = atomicAdd(cursor + b, 1u);
+      const uint64_t end = (uint64_t)offset[b] + count[b];
+      if (end <= capacity) list[offset[b] + pos] = w.t;
+    }
+}
+
+// tile_view[g] = view owning tile g of the given tile-size slot.
+__global__ void __launch_bounds__(256) k_tile_view_slot(const vs_view* __restrict__ views, int n_views,
+                                                        int32_t* __restrict__ tile_view, int64_t n_tiles, int slot) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_tiles) return;
+  tile_view[g] = find_view_tile(views, n_views, g, slot);
+}
+
+// One block per bin.  Small triangles (bounding box <= 64 px on each side and
+// few candidate pixels) are walked by one lane with exact int32 edge values;
+// larger ones are queued in LDS and tested by the whole block, each thread
+// owning B*B/256 pixels, with exact FP64 edge values.
+template <int B>
+__global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
+    const vs_view* __restrict__ views, const int32_t* __restrict__ bin_view, int64_t n_tiles, LayerTable L,
+    const ProjVert* __restrict__ proj, int64_t vpv, int slot, const uint32_t* __restrict__ count,
+    const uint32_t* __restrict__ offset, const int32_t* __restrict__ list, uint64_t capacity,
+    unsigned long long* __restrict__ vis, unsigned long long* __restrict__ status, int count_frags) {
+  __shared__ unsigned long long tile[B * B];
+  __shared__ int32_t queue[kRasterThreads];
+  __shared__ int nq;
+  const int k = L.k;
+  const int64_t n_bins = n_tiles * k;
+  // XCD-contiguous remap of the block index
+  const int64_t chunk = (n_bins + 7) / 8;
+  const int64_t bid = ((int64_t)blockIdx.x % 8) * chunk + (int64_t)blockIdx.x / 8;
+  if (bid >= n_bins) return;
+  const int64_t g = bid / k;
+  const int l = (int)(bid - g * k);
+  const int v = bin_view[g];
+  const vs_view& V = views[v];
+  const int W = V.cam.width, H = V.cam.height;
+  const int ntx = (W + B - 1) / B;
+  const int64_t tl = g - V.tile_offset[slot];
+  const int ty = (int)(tl / ntx), tx = (int)(tl - (int64_t)ty * ntx);
+  const int x0 = tx * B, y0 = ty * B;
+  const int x1 = min(x0 + B, W) - 1, y1 = min(y0 + B, H) - 1;
+  const int tid = threadIdx.x;
+  for (int p = tid; p < B * B; p += kRasterThreads) tile[p] = kEmpty;
+  if (tid == 0) nq = 0;
+  const ProjVert* P = proj + (int64_t)v * vpv + L.vert_off[l];
+  const int32_t* tri = L.tri[l];
+  const int32_t nvert = L.n_vert[l];
+  const uint32_t cnt = count[bid];
+  const bool overflow = (uint64_t)offset[bid] + cnt > capacity;
+  const uint32_t n = overflow ? (uint32_t)L.n_tri[l] : cnt;
+  const int32_t* lst = list + offset[bid];
+  unsigned long long frags = 0;
+  __syncthreads();
+  for (uint32_t c0 = 0; c0 < n; c0 += kRasterThreads) {
+    const uint32_t c = c0 + tid;
+    if (c < n) {
+      const int32_t t = overflow ? (int32_t)c : lst[c];
+      TriSetup T;
+      if (setup_triangle(tri + 3 * (int64_t)t, nvert, P, T) == kTriOk) {
+        PixRange pr = pixel_range(T, W, H);
+        const int ci0 = max(pr.i0, x0), ci1 = min(pr.i1, x1), cj0 = max(pr.j0, y0), cj1 = min(pr.j1, y1);
+        if (ci0 <= ci1 && cj0 <= cj1) {
+          const double spanx = fmax(T.X[0], fmax(T.X[1], T.X[2])) - fmin(T.X[0], fmin(T.X[1], T.X[2]));
+          const double spany = fmax(T.Y[0], fmax(T.Y[1], T.Y[2])) - fmin(T.Y[0], fmin(T.Y[1], T.Y[2]));
+          const int area = (ci1 - ci0 + 1) * (cj1 - cj0 + 1);
+          if (spanx <= kSmallSpan && spany <= kSmallSpan && area <= kSmallArea) {
+            // exact int32 edge walk: every edge value inside the bbox is below 2^30 in magnitude
+            double E[3];
+            edge_values(T, 256.0 * ci0 + 128.0, 256.0 * cj0 + 128.0, E);
+            int32_t er0 = (int32_t)E[0] - (int32_t)T.th[0];
+            int32_t er1 = (int32_t)E[1] - (int32_t)T.th[1];
+            int32_t er2 = (int32_t)E[2] - (int32_t)T.th[2];
+            const int32_t ax0 = (int32_t)(-(T.Y[2] - T.Y[1]) * 256.0), ay0 = (int32_t)((T.X[2] - T.X[1]) * 256.0);
+            const int32_t ax1 = (int32_t)(-(T.Y[0] - T.Y[2]) * 256.0), ay1 = (int32_t)((T.X[0] - T.X[2]) * 256.0);
+            const int32_t ax2 = (int32_t)(-(T.Y[1] - T.Y[0]) * 256.0), ay2 = (int32_t)((T.X[1] - T.X[0]) * 256.0);
+            for (int j = cj0; j <= cj1; ++j) {
+              int32_t e0 = er0, e1 = er1, e2 = er2;
+              for (int i = ci0; i <= ci1; ++i) {
+                if ((e0 | e1 | e2) >= 0) {
+                  const double E0 = (double)e0 + T.th[0], E1 = (double)e1 + T.th[1], E2 = (double)e2 + T.th[2];
+                  atomicMin(&tile[(j - y0) * B + (i - x0)],
+                            (unsigned long long)depth_key(T, E0, E1, E2, (uint32_t)t));
+                  ++frags;
+                }
+                e0 += ax0; e1 += ax1; e2 += ax2;
+              }
+              er0 += ay0; er1 += ay1; er2 += ay2;
+            }
+          } else {
+            queue[atomicAdd(&nq, 1)] = t;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    const int nbig = nq;
+    for (int q = 0; q < nbig; ++q) {
+      const int32_t t = queue[q];
+      TriSetup T;
+      setup_triangle(tri + 3 * (int64_t)t, nvert, P, T);
+      for (int p = tid; p < B * B; p += kRasterThreads) {
+        const int i = x0 + (p % B), j = y0 + (p / B);
+        if (i > x1 || j > y1) continue;
+        double E[3];
+        edge_values(T, 256.0 * i + 128.0, 256.0 * j + 128.0, E);
+        if (E[0] >= T.th[0] && E[1] >= T.th[1] && E[2] >= T.th[2]) {
+          atomicMin(&tile[p], (unsigned long long)depth_key(T, E[0], E[1], E[2], (uint32_t)t));
+          ++frags;
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == 0) nq = 0;
+    __syncthreads();
+  }
+  // coalesced store of the finished tile
+  unsigned long long* plane = vis + (int64_t)k * V.pix_offset + (int64_t)l * W * H;
+  for (int p = tid; p < B * B; p += kRasterThreads) {
+    const int i = x0 + (p % B), j = y0 + (p / B);
+    if (i <= x1 && j <= y1) plane[(int64_t)j * W + i] = tile[p];
+  }
+  if (count_frags) {
+    for (int off = 32; off > 0; off >>= 1) frags += __shfl_xor(frags, off);
+    if ((tid & 63) == 0 && frags) atomicAdd(status + VS_STAT_FRAGMENTS, frags);
+  }
+  if (tid == 0 && overflow) atomicAdd(status + VS_STAT_BIN_OVERFLOW, 1ull);
+}
+
+// Steps 2-3, direct form (reference path for tests): one thread per (view,
+// layer, triangle) walks its bounding box and takes 64-bit atomic minima in
+// the visibility plane, which must hold EMPTY before.
 __global__ void __launch_bounds__(256) k_raster_direct(const vs_view* __restrict__ views, LayerTable L,
                                                        const ProjVert* __restrict__ proj, int64_t vpv,
                                                        unsigned long long* __restrict__ vis,
@@ -46,30 +375,21 @@ __global__ void __launch_bounds__(256) k_raster_direct(const vs_view* __restrict
   TriSetup T;
   const int r = setup_triangle(L.tri[l] + 3 * (int64_t)t, L.n_vert[l], P, T);
   if (r != kTriOk) {
-    const int slot = r == kTriInvalid ? VS_STAT_CULLED_INVALID
-                   : r == kTriDegenerate ? VS_STAT_CULLED_DEGENERATE : VS_STAT_BAD_INDEX;
-    atomicAdd(status + slot, 1ull);
+    atomicAdd(status + cull_slot(r), 1ull);
     return;
   }
-  const double mnx = fmin(T.X[0], fmin(T.X[1], T.X[2])), mxx = fmax(T.X[0], fmax(T.X[1], T.X[2]));
-  const double mny = fmin(T.Y[0], fmin(T.Y[1], T.Y[2])), mxy = fmax(T.Y[0], fmax(T.Y[1], T.Y[2]));
-  // pixel centres 256 i + 128 inside [mnx, mxx]
-  const int i0 = max((int)ceil((mnx - 128.0) * (1.0 / 256.0)), 0);
-  const int i1 = min((int)floor((mxx - 128.0) * (1.0 / 256.0)), W - 1);
-  const int j0 = max((int)ceil((mny - 128.0) * (1.0 / 256.0)), 0);
-  const int j1 = min((int)floor((mxy - 128.0) * (1.0 / 256.0)), H - 1);
-  if (i0 > i1 || j0 > j1) return;
+  const PixRange pr = pixel_range(T, W, H);
+  if (pr.i0 > pr.i1 || pr.j0 > pr.j1) return;
   unsigned long long* plane = vis + (int64_t)k * V.pix_offset + (int64_t)l * W * H;
-  // d E / d(pixel step in x) and in y
   const double dx0 = -(T.Y[2] - T.Y[1]) * 256.0, dy0 = (T.X[2] - T.X[1]) * 256.0;
   const double dx1 = -(T.Y[0] - T.Y[2]) * 256.0, dy1 = (T.X[0] - T.X[2]) * 256.0;
   const double dx2 = -(T.Y[1] - T.Y[0]) * 256.0, dy2 = (T.X[1] - T.X[0]) * 256.0;
   double Er[3];
-  edge_values(T, 256.0 * i0 + 128.0, 256.0 * j0 + 128.0, Er);
+  edge_values(T, 256.0 * pr.i0 + 128.0, 256.0 * pr.j0 + 128.0, Er);
   unsigned long long frags = 0;
-  for (int j = j0; j <= j1; ++j) {
+  for (int j = pr.j0; j <= pr.j1; ++j) {
     double E0 = Er[0], E1 = Er[1], E2 = Er[2];
-    for (int i = i0; i <= i1; ++i) {
+    for (int i = pr.i0; i <= pr.i1; ++i) {
       if (E0 >= T.th[0] && E1 >= T.th[1] && E2 >= T.th[2]) {
         atomicMin(plane + (int64_t)j * W + i, (unsigned long long)depth_key(T, E0, E1, E2, (uint32_t)t));
         ++frags;

@@ -4,6 +4,12 @@
 // Barycentrics, UVs and texel coordinates are computed in FP64 (an FP32 texel
 // coordinate near 1024 has an ulp of 6e-5 texel); the fractional offsets,
 // the bilinear blend and the compositing run in FP32.
+//
+// Work decomposition: one 256-thread block per 16 x 16 pixel tile of one
+// view, one thread per pixel, layers walked front to back.  Tiles of all
+// views are numbered consecutively; the block -> tile mapping gives each XCD
+// (blocks are dealt round-robin to the 8 XCDs) a contiguous run of tiles so
+// that neighbouring tiles, which read neighbouring texels, share an L2.
 #pragma once
 
 #include "vs_common.h"
@@ -12,44 +18,45 @@ namespace vs {
 
 constexpr int kShadeTile = 16;      // 16 x 16 pixel tiles, one 256-thread block each
 constexpr int kShadeTileSlot = 1;   // vs_view::tile_offset slot of 16-pixel tiles
+constexpr int kNumXcd = 8;
+constexpr int kWinTexels = 1024;    // LDS gradient window of the adjoint (16 KB)
 
 struct Foot {
   int32_t i0, i1, j0, j1;  // wrapped texel indices of the 2x2 footprint
   float fx, fy;            // offsets from texel centre (i0, j0)
 };
 
-__device__ inline int32_t wrap_texel(int64_t i, int32_t n, int wrap) {
-  if (wrap == kWrapClamp) return (int32_t)(i < 0 ? 0 : (i >= n ? n - 1 : i));
-  int64_t m = i % n;
-  return (int32_t)(m < 0 ? m + n : m);
-}
-
-// Bilinear footprint: texel centres at (i + 1/2)/W, so the sample sits at
-// x = u W - 1/2 in texel-centre coordinates.
-__device__ inline Foot footprint(double u, double v, int32_t W, int32_t H, int wrap) {
-  double x = u * (double)W - 0.5, y = v * (double)H - 0.5;
-  x = fmin(fmax(x, -1.0e9), 1.0e9);
-  y = fmin(fmax(y, -1.0e9), 1.0e9);
-  const double xf = floor(x), yf = floor(y);
-  Foot f;
-  f.fx = (float)(x - xf);
-  f.fy = (float)(y - yf);
-  const int64_t ix = (int64_t)xf, iy = (int64_t)yf;
-  f.i0 = wrap_texel(ix, W, wrap);
-  f.i1 = wrap_texel(ix + 1, W, wrap);
-  f.j0 = wrap_texel(iy, H, wrap);
-  f.j1 = wrap_texel(iy + 1, H, wrap);
-  return f;
+// Split a texel-centre coordinate into the two neighbouring texel indices and
+// the offset from the first, wrapping (repeat) or clamping to [0, n-1].
+__device__ inline void split_coord(double x, int32_t n, double inv_n, int wrap, int32_t& i0, int32_t& i1,
+                                   float& fr) {
+  x = fmin(fmax(x, -1.0e9), 1.0e9);  // also maps NaN to a finite value
+  if (wrap == kWrapClamp) {
+    x = fmin(fmax(x, 0.0), (double)(n - 1));
+    const double f = floor(x);
+    i0 = (int32_t)f;
+    fr = (float)(x - f);
+    i1 = i0 + 1 < n ? i0 + 1 : n - 1;
+    return;
+  }
+  const double f = floor(x);
+  fr = (float)(x - f);
+  double m = f - (double)n * floor(f * inv_n);  // f mod n, exact for |f| < 2^52
+  int32_t i = (int32_t)m;
+  if (i < 0) i += n;
+  if (i >= n) i -= n;
+  i0 = i;
+  i1 = i + 1 == n ? 0 : i + 1;
 }
 
 __device__ inline float4 bilinear(const float4* __restrict__ tex, int32_t W, const Foot& f) {
 #pragma clang fp contract(fast)
-  const float4 t00 = tex[(int64_t)f.j0 * W + f.i0];
-  const float4 t01 = tex[(int64_t)f.j0 * W + f.i1];
-  const float4 t10 = tex[(int64_t)f.j1 * W + f.i0];
-  const float4 t11 = tex[(int64_t)f.j1 * W + f.i1];
-  const float w00 = (1.0f - f.fx) * (1.0f - f.fy), w01 = f.fx * (1.0f - f.fy);
-  const float w10 = (1.0f - f.fx) * f.fy, w11 = f.fx * f.fy;
+  const float4 t00 = tex[f.j0 * W + f.i0];
+  const float4 t01 = tex[f.j0 * W + f.i1];
+  const float4 t10 = tex[f.j1 * W + f.i0];
+  const float4 t11 = tex[f.j1 * W + f.i1];
+  const float gx = 1.0f - f.fx, gy = 1.0f - f.fy;
+  const float w00 = gx * gy, w01 = f.fx * gy, w10 = gx * f.fy, w11 = f.fx * f.fy;
   float4 r;
   r.x = w00 * t00.x + w01 * t01.x + w10 * t10.x + w11 * t11.x;
   r.y = w00 * t00.y + w01 * t01.y + w10 * t10.y + w11 * t11.y;
@@ -58,70 +65,120 @@ __device__ inline float4 bilinear(const float4* __restrict__ tex, int32_t W, con
   return r;
 }
 
-// Rebuild the triangle named by a key and compute the UV footprint at pixel
-// (x, y).  Returns false (and counts a bad key) if the key names no valid triangle.
-__device__ inline bool slot_footprint(const LayerTable& L, int l, const ProjVert* P, uint64_t key, int x, int y,
-                                      int32_t W, int32_t H, int wrap, Foot& f,
-                                      unsigned long long* status) {
+struct Tri3 { int32_t a, b, c; };
+
+// Rebuild the triangle a key names and compute its UV footprint at the pixel
+// centre (px, py) (1/256 px units).  Barycentrics are perspective-correct:
+// lambda_q = E_q w_q / sum_r E_r w_r, which does not depend on the winding,
+// so no orientation normalisation is needed here.  Returns false (and counts
+// a bad key) if the key names no valid triangle.
+__device__ inline bool slot_footprint(const int32_t* __restrict__ tri, int32_t n_tri, int32_t n_vert,
+                                      const ProjVert* __restrict__ P, const float2* __restrict__ uv, uint64_t key,
+                                      double px, double py, int32_t W, int32_t H, double invW, double invH, int wrap,
+                                      Foot& f, unsigned long long* status) {
+#pragma clang fp contract(fast)
   const uint32_t t = (uint32_t)(key & 0xffffffffu);
-  TriSetup T;
-  if (t >= (uint32_t)L.n_tri[l] || setup_triangle(L.tri[l] + 3 * (int64_t)t, L.n_vert[l], P, T) != kTriOk) {
+  if (t >= (uint32_t)n_tri) {
     atomicAdd(status + VS_STAT_BAD_KEY, 1ull);
     return false;
   }
-  double E[3];
-  edge_values(T, 256.0 * x + 128.0, 256.0 * y + 128.0, E);
-  const double s = (E[0] * T.w[0] + E[1] * T.w[1]) + E[2] * T.w[2];
-  const double inv = 1.0 / s;
-  const double la = E[0] * T.w[0] * inv, lb = E[1] * T.w[1] * inv, lc = E[2] * T.w[2] * inv;
-  const float2* uv = reinterpret_cast<const float2*>(L.uv[l]);
-  const float2 ua = uv[T.vid[0]], ub = uv[T.vid[1]], uc = uv[T.vid[2]];
-  const double u = (la * (double)ua.x + lb * (double)ub.x) + lc * (double)uc.x;
-  const double v = (la * (double)ua.y + lb * (double)ub.y) + lc * (double)uc.y;
-  f = footprint(u, v, W, H, wrap);
+  const Tri3 id = reinterpret_cast<const Tri3*>(tri)[t];
+  if ((uint32_t)id.a >= (uint32_t)n_vert || (uint32_t)id.b >= (uint32_t)n_vert ||
+      (uint32_t)id.c >= (uint32_t)n_vert) {
+    atomicAdd(status + VS_STAT_BAD_KEY, 1ull);
+    return false;
+  }
+  const ProjVert a = P[id.a], b = P[id.b], c = P[id.c];
+  const float2 ua = uv[id.a], ub = uv[id.b], uc = uv[id.c];
+  const double ax = a.X, ay = a.Y, bx = b.X, by = b.Y, cx = c.X, cy = c.Y;
+  const double E0 = (cx - bx) * (py - by) - (cy - by) * (px - bx);
+  const double E1 = (ax - cx) * (py - cy) - (ay - cy) * (px - cx);
+  const double E2 = (bx - ax) * (py - ay) - (by - ay) * (px - ax);
+  const double q0 = E0 * a.w, q1 = E1 * b.w, q2 = E2 * c.w;
+  const double s = q0 + q1 + q2;
+  // 1/s: hardware reciprocal refined by two Newton steps (relative error ~1e-16)
+  double r = __builtin_amdgcn_rcp(s);
+  r = r * (2.0 - s * r);
+  r = r * (2.0 - s * r);
+  const double la = q0 * r, lb = q1 * r, lc = q2 * r;
+  const double u = la * (double)ua.x + lb * (double)ub.x + lc * (double)uc.x;
+  const double v = la * (double)ua.y + lb * (double)ub.y + lc * (double)uc.y;
+  split_coord(u * (double)W - 0.5, W, invW, wrap, f.i0, f.i1, f.fx);
+  split_coord(v * (double)H - 0.5, H, invH, wrap, f.j0, f.j1, f.fy);
   return true;
 }
 
 struct TileCoord {
   int v, x, y;
   bool valid;
+  bool live;   // false for padding blocks of the XCD remap
 };
 
-__device__ inline TileCoord shade_tile_coord(const vs_view* __restrict__ views, int n_views) {
+// Block -> (view, tile) with an XCD-contiguous remap; tile_view[g] is the view of tile g.
+// A tile whose table entry is out of range (a workspace not filled by
+// vs_raster_layers for these views) is skipped rather than trusted.
+__device__ inline TileCoord shade_tile_coord(const vs_view* __restrict__ views, int n_views,
+                                             const int32_t* __restrict__ tile_view, int64_t n_tiles) {
   TileCoord c;
-  const int64_t g = blockIdx.x;
-  c.v = find_view_tile(views, n_views, g, kShadeTileSlot);
+  const int64_t chunk = (n_tiles + kNumXcd - 1) / kNumXcd;
+  const int64_t b = blockIdx.x;
+  const int64_t g = (b % kNumXcd) * chunk + b / kNumXcd;
+  c.v = 0; c.x = c.y = 0; c.valid = false;
+  c.live = g < n_tiles;
+  if (!c.live) return c;
+  c.v = tile_view[g];
+  if ((unsigned)c.v >= (unsigned)n_views) { c.v = 0; c.live = false; return c; }
   const vs_view& V = views[c.v];
   const int64_t local = g - V.tile_offset[kShadeTileSlot];
   const int tiles_x = (V.cam.width + kShadeTile - 1) / kShadeTile;
-  const int tx = (int)(local % tiles_x), ty = (int)(local / tiles_x);
-  c.x = tx * kShadeTile + (threadIdx.x % kShadeTile);
-  c.y = ty * kShadeTile + (threadIdx.x / kShadeTile);
+  const int64_t ty = local / tiles_x, tx = local - ty * tiles_x;
+  if (local < 0 || ty * kShadeTile >= V.cam.height) { c.live = false; return c; }
+  c.x = (int)tx * kShadeTile + (threadIdx.x % kShadeTile);
+  c.y = (int)ty * kShadeTile + (threadIdx.x / kShadeTile);
   c.valid = c.x < V.cam.width && c.y < V.cam.height;
   return c;
 }
 
-// Forward: one thread per pixel, 16x16 tiles, layers front to back.
-__global__ void __launch_bounds__(256) k_shade_fwd(const vs_view* __restrict__ views, int n_views, LayerTable L,
-                                                   TexTable X, const ProjVert* __restrict__ proj, int64_t vpv,
+__host__ __device__ inline int64_t shade_grid_blocks(int64_t n_tiles) {
+  return (n_tiles + kNumXcd - 1) / kNumXcd * kNumXcd;
+}
+
+// tile_view[g] = view owning 16-pixel tile g.
+__global__ void __launch_bounds__(256) k_tile_view(const vs_view* __restrict__ views, int n_views,
+                                                   int32_t* __restrict__ tile_view, int64_t n_tiles) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_tiles) return;
+  tile_view[g] = find_view_tile(views, n_views, g, kShadeTileSlot);
+}
+
+// Forward: one thread per pixel, layers front to back.
+__global__ void __launch_bounds__(256) k_shade_fwd(const vs_view* __restrict__ views, int n_views,
+                                                   const int32_t* __restrict__ tile_view,
+                                                   int64_t n_tiles, LayerTable L, TexTable X,
+                                                   const ProjVert* __restrict__ proj, int64_t vpv,
                                                    const uint64_t* __restrict__ vis, float4* __restrict__ out,
                                                    float eps_T, int wrap, unsigned long long* __restrict__ status) {
 #pragma clang fp contract(fast)
-  const TileCoord c = shade_tile_coord(views, n_views);
+  const TileCoord c = shade_tile_coord(views, n_views, tile_view, n_tiles);
+  if (!c.live) return;
   const vs_view& V = views[c.v];
   const int W = V.cam.width, H = V.cam.height;
   const int64_t P = (int64_t)W * H;
   const int k = L.k;
   const int64_t pix = (int64_t)c.y * W + c.x;
   const uint64_t* vrow = vis + (int64_t)k * V.pix_offset + pix;
+  const ProjVert* pview = proj + (int64_t)c.v * vpv;
+  const double px = 256.0 * c.x + 128.0, py = 256.0 * c.y + 128.0;
   float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = c.valid ? 1.0f : 0.0f;
   for (int l = 0; l < k; ++l) {
-    const uint64_t key = c.valid ? vrow[(int64_t)l * P] : kEmpty;
+    const uint64_t key = c.valid ? vrow[l * P] : kEmpty;
     if (key != kEmpty) {
       Foot f;
-      if (slot_footprint(L, l, proj + (int64_t)c.v * vpv + L.vert_off[l], key, c.x, c.y, X.w[l], X.h[l], wrap, f,
-                         status)) {
-        const float4 s = bilinear(X.tex[l], X.w[l], f);
+      const int32_t Wt = X.w[l], Ht = X.h[l];
+      if (slot_footprint(L.tri[l], L.n_tri[l], L.n_vert[l], pview + L.vert_off[l],
+                         reinterpret_cast<const float2*>(L.uv[l]), key, px, py, Wt, Ht, X.inv_w[l], X.inv_h[l],
+                         wrap, f, status)) {
+        const float4 s = bilinear(X.tex[l], Wt, f);
         const float ta = T * s.w;
         Cr += ta * s.x; Cg += ta * s.y; Cb += ta * s.z;
         T *= (1.0f - s.w);
@@ -132,42 +189,76 @@ __global__ void __launch_bounds__(256) k_shade_fwd(const vs_view* __restrict__ v
   if (c.valid) out[V.pix_offset + pix] = make_float4(Cr, Cg, Cb, 1.0f - T);
 }
 
+// Relative texel offset of index i from reference r in [-n/2, n/2) (repeat) or plain difference (clamp).
+__device__ inline int32_t rel_index(int32_t i, int32_t r, int32_t n, int wrap) {
+  int32_t d = i - r;
+  if (wrap == kWrapClamp) return d;
+  if (d >= (n >> 1)) d -= n;
+  else if (d < -(n >> 1)) d += n;
+  return d;
+}
+
+__device__ inline int32_t abs_index(int32_t r, int32_t d, int32_t n, int wrap) {
+  int32_t i = r + d;
+  if (wrap == kWrapClamp) return i;
+  if (i >= n) i -= n;
+  else if (i < 0) i += n;
+  return i;
+}
+
 // Backward: recompute the layers front to back (keeping c, a, T and the
 // footprint of each hit layer), form dL/d(RGB, A), then walk back to front:
 //   dL/dc_l = g_rgb a_l T_l,  dL/da_l = T_l <g_rgb, c_l - S_l> + g_A T_l prod_{m>l}(1 - a_m),
 // S_l the colour blended behind layer l.  Division-free (a = 1 is fine).
 // Each of the 4 corner texels receives its bilinear weight times these.
+//
+// Scatter: per layer, the block's footprints are gathered into an LDS texel
+// window (relative to a reference texel, wrap-aware) with LDS atomics, then
+// the window is flushed with coalesced global atomics, skipping untouched
+// texels.  A layer whose footprint does not fit the window falls back to
+// direct global atomics for that block.
 template <int KMAX>
-__global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ views, int n_views, LayerTable L,
-                                                   TexTable X, const ProjVert* __restrict__ proj, int64_t vpv,
-                                                   const uint64_t* __restrict__ vis,
+__global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ views, int n_views,
+                                                   const int32_t* __restrict__ tile_view, int64_t n_tiles,
+                                                   LayerTable L, TexTable X, const ProjVert* __restrict__ proj,
+                                                   int64_t vpv, const uint64_t* __restrict__ vis,
                                                    const float4* __restrict__ grad_out,
                                                    const float4* __restrict__ target, float loss_scale,
                                                    float4* __restrict__ out, double* __restrict__ sse, int wrap,
                                                    unsigned long long* __restrict__ status) {
 #pragma clang fp contract(fast)
-  const TileCoord c = shade_tile_coord(views, n_views);
+  __shared__ float win[kWinTexels * 4];
+  __shared__ int red[8];
+  __shared__ double sred[4];
+  const TileCoord c = shade_tile_coord(views, n_views, tile_view, n_tiles);
+  if (!c.live) return;  // uniform per block
   const vs_view& V = views[c.v];
   const int W = V.cam.width, H = V.cam.height;
   const int64_t P = (int64_t)W * H;
   const int k = L.k;
   const int64_t pix = (int64_t)c.y * W + c.x;
   const uint64_t* vrow = vis + (int64_t)k * V.pix_offset + pix;
-  float cr[KMAX], cg[KMAX], cb[KMAX], ca[KMAX], Tl[KMAX];
-  Foot fp[KMAX];
-  bool hit[KMAX];
+  const ProjVert* pview = proj + (int64_t)c.v * vpv;
+  const double px = 256.0 * c.x + 128.0, py = 256.0 * c.y + 128.0;
+  float cr[KMAX], cg[KMAX], cb[KMAX], ca[KMAX], Tl[KMAX], fxs[KMAX], fys[KMAX];
+  int32_t ii[KMAX], jj[KMAX];   // packed (i1 << 16 | i0), (j1 << 16 | j0)
+  uint32_t hitmask = 0;
   float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.0f;
 #pragma unroll
   for (int l = 0; l < KMAX; ++l) {
-    hit[l] = false;
     if (l < k && c.valid) {
-      const uint64_t key = vrow[(int64_t)l * P];
+      const uint64_t key = vrow[l * P];
+      Foot f;
       if (key != kEmpty &&
-          slot_footprint(L, l, proj + (int64_t)c.v * vpv + L.vert_off[l], key, c.x, c.y, X.w[l], X.h[l], wrap,
-                         fp[l], status)) {
-        const float4 s = bilinear(X.tex[l], X.w[l], fp[l]);
-        hit[l] = true;
+          slot_footprint(L.tri[l], L.n_tri[l], L.n_vert[l], pview + L.vert_off[l],
+                         reinterpret_cast<const float2*>(L.uv[l]), key, px, py, X.w[l], X.h[l], X.inv_w[l],
+                         X.inv_h[l], wrap, f, status)) {
+        const float4 s = bilinear(X.tex[l], X.w[l], f);
+        hitmask |= 1u << l;
         cr[l] = s.x; cg[l] = s.y; cb[l] = s.z; ca[l] = s.w; Tl[l] = T;
+        fxs[l] = f.fx; fys[l] = f.fy;
+        ii[l] = (f.i1 << 16) | f.i0;
+        jj[l] = (f.j1 << 16) | f.j0;
         const float ta = T * s.w;
         Cr += ta * s.x; Cg += ta * s.y; Cb += ta * s.z;
         T *= (1.0f - s.w);
@@ -181,7 +272,8 @@ __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ v
     if (target) {
       const float4 tg = target[gp];
       const float dr = Cr - tg.x, dg = Cg - tg.y, db = Cb - tg.z;
-      gr = 2.0f * loss_scale * dr; gg = 2.0f * loss_scale * dg; gb = 2.0f * loss_scale * db;
+      const float s2 = 2.0f * loss_scale;
+      gr = s2 * dr; gg = s2 * dg; gb = s2 * db;
       my_sse = (double)dr * dr + (double)dg * dg + (double)db * db;
     } else {
       const float4 go = grad_out[gp];
@@ -190,42 +282,86 @@ __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ v
     if (out) out[gp] = make_float4(Cr, Cg, Cb, 1.0f - T);
   }
   float Sr = 0.f, Sg = 0.f, Sb = 0.f, Pm = 1.0f;
+  const int tid = threadIdx.x;
 #pragma unroll
   for (int l = KMAX - 1; l >= 0; --l) {
-    if (!hit[l]) continue;
-    const float a = ca[l], Tv = Tl[l];
-    const float dcr = gr * a * Tv, dcg = gg * a * Tv, dcb = gb * a * Tv;
-    const float da = Tv * (gr * (cr[l] - Sr) + gg * (cg[l] - Sg) + gb * (cb[l] - Sb)) + gA * Tv * Pm;
-    Sr = a * cr[l] + (1.0f - a) * Sr;
-    Sg = a * cg[l] + (1.0f - a) * Sg;
-    Sb = a * cb[l] + (1.0f - a) * Sb;
-    Pm *= (1.0f - a);
-    const Foot& f = fp[l];
-    const float w00 = (1.0f - f.fx) * (1.0f - f.fy), w01 = f.fx * (1.0f - f.fy);
-    const float w10 = (1.0f - f.fx) * f.fy, w11 = f.fx * f.fy;
-    float* G = X.grad[l];
-    const int32_t Wt = X.w[l];
-    const int64_t q[4] = {((int64_t)f.j0 * Wt + f.i0) * 4, ((int64_t)f.j0 * Wt + f.i1) * 4,
-                          ((int64_t)f.j1 * Wt + f.i0) * 4, ((int64_t)f.j1 * Wt + f.i1) * 4};
-    const float wq[4] = {w00, w01, w10, w11};
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      unsafeAtomicAdd(G + q[n] + 0, wq[n] * dcr);
-      unsafeAtomicAdd(G + q[n] + 1, wq[n] * dcg);
-      unsafeAtomicAdd(G + q[n] + 2, wq[n] * dcb);
-      unsafeAtomicAdd(G + q[n] + 3, wq[n] * da);
+    if (l >= k) continue;  // uniform
+    const bool hit = (hitmask >> l) & 1u;
+    float d[4] = {0.f, 0.f, 0.f, 0.f};   // dL/d(r, g, b, a) of this layer's sample
+    float wq[4] = {0.f, 0.f, 0.f, 0.f};
+    int32_t i0 = 0, i1 = 0, j0 = 0, j1 = 0;
+    if (hit) {
+      const float a = ca[l], Tv = Tl[l];
+      const float aT = a * Tv;
+      d[0] = gr * aT; d[1] = gg * aT; d[2] = gb * aT;
+      d[3] = Tv * (gr * (cr[l] - Sr) + gg * (cg[l] - Sg) + gb * (cb[l] - Sb)) + gA * Tv * Pm;
+      Sr = a * cr[l] + (1.0f - a) * Sr;
+      Sg = a * cg[l] + (1.0f - a) * Sg;
+      Sb = a * cb[l] + (1.0f - a) * Sb;
+      Pm *= (1.0f - a);
+      const float fx = fxs[l], fy = fys[l], gx = 1.0f - fx, gy = 1.0f - fy;
+      wq[0] = gx * gy; wq[1] = fx * gy; wq[2] = gx * fy; wq[3] = fx * fy;
+      i0 = ii[l] & 0xffff; i1 = ii[l] >> 16; j0 = jj[l] & 0xffff; j1 = jj[l] >> 16;
     }
+    float* G = X.grad[l];
+    const int32_t Wt = X.w[l], Ht = X.h[l];
+    // --- window extent: reference texel = min packed index over hit lanes
+    if (tid == 0) { red[0] = INT32_MAX; red[1] = INT32_MAX; red[2] = INT32_MIN; red[3] = INT32_MAX; red[4] = INT32_MIN; }
+    __syncthreads();
+    if (hit) atomicMin(&red[0], j0 * Wt + i0);
+    __syncthreads();
+    const int32_t refp = red[0];
+    if (refp == INT32_MAX) { __syncthreads(); continue; }   // no lane of the block hit this layer
+    const int32_t rj = refp / Wt, ri = refp - rj * Wt;
+    int32_t di0 = 0, di1 = 0, dj0 = 0, dj1 = 0;
+    if (hit) {
+      di0 = rel_index(i0, ri, Wt, wrap); di1 = rel_index(i1, ri, Wt, wrap);
+      dj0 = rel_index(j0, rj, Ht, wrap); dj1 = rel_index(j1, rj, Ht, wrap);
+      atomicMin(&red[1], min(di0, di1)); atomicMax(&red[2], max(di0, di1));
+      atomicMin(&red[3], min(dj0, dj1)); atomicMax(&red[4], max(dj0, dj1));
+    }
+    __syncthreads();
+    const int32_t dmin_i = red[1], dmin_j = red[3];
+    const int32_t ww = red[2] - dmin_i + 1, wh = red[4] - dmin_j + 1;
+    if (ww * wh <= kWinTexels) {
+      for (int e = tid; e < ww * wh * 4; e += 256) win[e] = 0.0f;
+      __syncthreads();
+      if (hit) {
+        const int32_t x0 = di0 - dmin_i, x1 = di1 - dmin_i, y0 = dj0 - dmin_j, y1 = dj1 - dmin_j;
+        const int32_t s[4] = {(y0 * ww + x0) * 4, (y0 * ww + x1) * 4, (y1 * ww + x0) * 4, (y1 * ww + x1) * 4};
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+#pragma unroll
+          for (int ch = 0; ch < 4; ++ch) atomicAdd(&win[s[n] + ch], wq[n] * d[ch]);
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < ww * wh * 4; e += 256) {
+        const float val = win[e];
+        if (val != 0.0f) {
+          const int32_t cell = e >> 2, ch = e & 3;
+          const int32_t y = cell / ww, x = cell - y * ww;
+          const int32_t ti = abs_index(ri, dmin_i + x, Wt, wrap), tj = abs_index(rj, dmin_j + y, Ht, wrap);
+          unsafeAtomicAdd(G + ((int64_t)tj * Wt + ti) * 4 + ch, val);
+        }
+      }
+    } else if (hit) {
+      const int32_t q[4] = {j0 * Wt + i0, j0 * Wt + i1, j1 * Wt + i0, j1 * Wt + i1};
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) unsafeAtomicAdd(G + (int64_t)q[n] * 4 + ch, wq[n] * d[ch]);
+      }
+    }
+    __syncthreads();  // red[] and win[] are reused by the next layer
   }
   if (sse) {
     // block reduction of the squared error, one atomic per block
-    __shared__ double red[256];
-    red[threadIdx.x] = my_sse;
+    double v = my_sse;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((tid & 63) == 0) sred[tid >> 6] = v;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) unsafeAtomicAdd(sse, red[0]);
+    if (tid == 0) unsafeAtomicAdd(sse, (sred[0] + sred[1]) + (sred[2] + sred[3]));
   }
 }
 

@@ -107,29 +107,35 @@ def textures_struct(textures: Sequence[torch.Tensor]):
     return arr
 
 
-def workspace_bytes(layers: Layers, views: Views, bin: int = 0) -> int:
-    opts = C.VsRasterOpts(bin, 0)
+def _raster_opts(bin=0, count_fragments=False, direct=False, list_capacity=0):
+    flags = (C.VS_RASTER_COUNT_FRAGMENTS if count_fragments else 0) | (C.VS_RASTER_DIRECT if direct else 0)
+    return C.VsRasterOpts(int(bin), flags, int(list_capacity))
+
+
+def workspace_bytes(layers: Layers, views: Views, bin: int = 0, list_capacity: int = 0) -> int:
+    opts = _raster_opts(bin, list_capacity=list_capacity)
     n = C.load().vs_raster_workspace_bytes(ctypes.addressof(layers.c), layers.k, ctypes.byref(views.c),
                                            ctypes.byref(opts))
     if n == 0:
-        C.check(C.VS_ERR_ARG, "vs_raster_workspace_bytes")
+        raise C.VsError(C.VS_ERR_ARG, "vs_raster_workspace_bytes", C.load().vs_last_error().decode() or
+                        "invalid layers, views or options")
     return int(n)
 
 
-def alloc_workspace(layers: Layers, views: Views, bin: int = 0, device="cuda") -> torch.Tensor:
-    return torch.empty(workspace_bytes(layers, views, bin), dtype=torch.uint8, device=device)
+def alloc_workspace(layers: Layers, views: Views, bin: int = 0, device="cuda", list_capacity: int = 0) -> torch.Tensor:
+    return torch.empty(workspace_bytes(layers, views, bin, list_capacity), dtype=torch.uint8, device=device)
 
 
 def raster(layers: Layers, views: Views, vis: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
-           bin: int = 0, count_fragments: bool = False, stream=None):
+           bin: int = 0, count_fragments: bool = False, direct: bool = False, list_capacity: int = 0, stream=None):
     """vs_raster_layers: returns (vis int64[sum_v k H_v W_v] holding u64 keys, workspace)."""
     dev = views.dev.device
     if vis is None:
         vis = torch.empty(layers.k * views.total_pixels, dtype=torch.int64, device=dev)
     if ws is None:
-        ws = alloc_workspace(layers, views, bin, dev)
+        ws = alloc_workspace(layers, views, bin, dev, list_capacity)
     _dev(vis, torch.int64, "vis")
-    opts = C.VsRasterOpts(bin, C.VS_RASTER_COUNT_FRAGMENTS if count_fragments else 0)
+    opts = _raster_opts(bin, count_fragments, direct, list_capacity)
     C.check(C.load().vs_raster_layers(ctypes.addressof(layers.c), layers.k, ctypes.byref(views.c), vis.data_ptr(),
                                       ws.data_ptr(), ws.numel(), ctypes.byref(opts), _stream(stream)),
             "vs_raster_layers")
@@ -188,6 +194,67 @@ def read_status(ws: torch.Tensor, stream=None) -> dict:
     C.check(C.load().vs_read_status(ws.data_ptr(), ws.numel(), ctypes.addressof(out), _stream(stream)),
             "vs_read_status")
     return {n: int(out[i]) for i, n in enumerate(C.STAT_NAMES)}
+
+
+def autotune(layers: Layers, views: Views, vis: torch.Tensor, ws: torch.Tensor, cache_path: Optional[str] = None,
+             count_fragments: bool = False, list_capacity: int = 0, stream=None) -> int:
+    """vs_autotune: the fastest bin size for this problem (vis and ws are overwritten)."""
+    opts = _raster_opts(0, count_fragments, False, list_capacity)
+    C.check(C.load().vs_autotune(ctypes.addressof(layers.c), layers.k, ctypes.byref(views.c), vis.data_ptr(),
+                                 ws.data_ptr(), ws.numel(), ctypes.byref(opts),
+                                 None if cache_path is None else cache_path.encode(), _stream(stream)),
+            "vs_autotune")
+    return int(opts.bin)
+
+
+def adam_step(params, grads, m, v, step: torch.Tensor, lr=1e-2, betas=(0.9, 0.999), eps=1e-8, lo=0.0, hi=1.0,
+              sse: Optional[torch.Tensor] = None, history: Optional[torch.Tensor] = None, stream=None):
+    """vs_adam_step: fused Adam + projection to [lo, hi] + gradient reset on k texture planes."""
+    k = len(params)
+    for name, arr in (("params", params), ("grads", grads), ("m", m), ("v", v)):
+        for l, t in enumerate(arr):
+            _dev(t, torch.float32, f"{name}[{l}]")
+    _dev(step, torch.int32, "step")
+    ptr = lambda arr: (ctypes.c_void_p * k)(*[t.data_ptr() for t in arr])  # noqa: E731
+    counts = (ctypes.c_int64 * k)(*[t.numel() for t in params])
+    opts = C.VsAdamOpts(lr, betas[0], betas[1], eps, lo, hi)
+    hist_len = 0 if history is None else history.numel()
+    keep = [ptr(params), ptr(grads), ptr(m), ptr(v)]
+    C.check(C.load().vs_adam_step(ctypes.addressof(keep[0]), ctypes.addressof(keep[1]), ctypes.addressof(keep[2]),
+                                  ctypes.addressof(keep[3]), ctypes.addressof(counts), k, ctypes.byref(opts),
+                                  step.data_ptr(), None if sse is None else sse.data_ptr(),
+                                  None if history is None else history.data_ptr(), hist_len, _stream(stream)),
+            "vs_adam_step")
+
+
+class Graph:
+    """A HIP graph captured from calls into the library on one (non-default) stream."""
+
+    def __init__(self, stream: torch.cuda.Stream):
+        self.stream = stream
+        self.handle = ctypes.c_void_p()
+
+    def __enter__(self):
+        C.check(C.load().vs_graph_begin(_stream(self.stream)), "vs_graph_begin")
+        return self
+
+    def __exit__(self, exc_type, exc, tb):
+        h = ctypes.c_void_p()
+        st = C.load().vs_graph_end(_stream(self.stream), ctypes.byref(h))
+        if exc_type is None:
+            C.check(st, "vs_graph_end")
+        self.handle = h
+        return False
+
+    def replay(self):
+        C.check(C.load().vs_graph_launch(self.handle, _stream(self.stream)), "vs_graph_launch")
+
+    def __del__(self):
+        try:
+            if self.handle:
+                C.load().vs_graph_destroy(self.handle)
+        except Exception:
+            pass
 
 
 class _RenderFn(torch.autograd.Function):

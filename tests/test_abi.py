@@ -42,16 +42,18 @@ def test_exports_every_declared_symbol(C):
 def test_struct_layouts_match_c(C, tmp_path):
     prog = tmp_path / "sz.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "vs.h"\nint main(void){'
-                    'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(vs_mesh), sizeof(vs_texture),'
+                    'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(vs_mesh), sizeof(vs_texture),'
                     'sizeof(vs_camera), sizeof(vs_view), sizeof(vs_views), sizeof(vs_raster_opts),'
-                    'sizeof(vs_shade_opts), offsetof(vs_view, pix_offset), offsetof(vs_shade_opts, target));'
+                    'sizeof(vs_shade_opts), offsetof(vs_view, pix_offset), offsetof(vs_shade_opts, target),'
+                    'offsetof(vs_raster_opts, list_capacity));'
                     'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(C.VsMesh), ctypes.sizeof(C.VsTexture), ctypes.sizeof(C.VsCamera),
             ctypes.sizeof(C.VsView), ctypes.sizeof(C.VsViews), ctypes.sizeof(C.VsRasterOpts),
-            ctypes.sizeof(C.VsShadeOpts), C.VsView.pix_offset.offset, C.VsShadeOpts.target.offset]
+            ctypes.sizeof(C.VsShadeOpts), C.VsView.pix_offset.offset, C.VsShadeOpts.target.offset,
+            C.VsRasterOpts.list_capacity.offset]
     assert got == want
 
 

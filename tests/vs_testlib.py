@@ -19,14 +19,16 @@ def say(*a):
     sys.stdout.flush()
 
 
-def gpu_render(scene, textures=None, bin=0, eps_T=0.0, wrap=0, count_fragments=False):
+def gpu_render(scene, textures=None, bin=0, eps_T=0.0, wrap=0, count_fragments=False, direct=False,
+               list_capacity=0):
     """Raster + render on the GPU. Returns (P, layers, views, vis, ws, rgba, textures_t)."""
     import torch
     import paper_2409_02482_amd as P
     layers = P.Layers(scene.layers)
     views = P.Views(scene.cameras)
     tex = [torch.from_numpy(np.ascontiguousarray(t)).cuda() for t in (textures or scene.textures)]
-    vis, ws = P.raster(layers, views, bin=bin, count_fragments=count_fragments)
+    vis, ws = P.raster(layers, views, bin=bin, count_fragments=count_fragments, direct=direct,
+                       list_capacity=list_capacity)
     rgba = P.render(layers, tex, views, vis, ws, eps_T=eps_T, wrap=wrap)
     torch.cuda.synchronize()
     return P, layers, views, vis, ws, rgba, tex
