@@ -33,19 +33,40 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def byte_model(scene, n_views, P_v, U):
-    """Algorithmic bytes per launch of each kernel (byte model)."""
+def byte_model(scene, n_views, P_v, U, fused=True):
+    """Algorithmic bytes per launch of each phase (byte model)."""
     k = scene.k
     P = n_views * P_v
     G = sum(12 * m.n_vert + 8 * m.n_vert + 12 * m.n_tri for m in scene.layers)
     tex_bytes = sum(16 * int(u) for u in U)
     grad_planes = sum(16 * t.shape[0] * t.shape[1] for t in scene.textures)
     return {
-        "raster": 8 * k * P + G * n_views,                     # vis write + geometry per view
-        "shade_fwd": 8 * k * P + 16 * P + tex_bytes + G,       # vis read, RGBA write, texels, geometry
-        "shade_bwd": 8 * k * P + 16 * P + tex_bytes + 2 * grad_planes + G,  # vis, target, texels, grad RMW
+        "raster": 8 * k * P + G * n_views,                     # one key store per slot + geometry per view
+        "shade_fwd": 0 if fused else 8 * k * P + 16 * P + tex_bytes + G,
+        # keys, target, image (fused), texels, gradient read-modify-write, geometry
+        "shade_bwd": 8 * k * P + 16 * P + (16 * P if fused else 0) + tex_bytes + 2 * grad_planes + G,
         "grad_zero": grad_planes,
     }
+
+
+def counter_traffic(kernel: str):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter summary, if its sources match."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(kernel)
+    except Exception:
+        return None
+    if not rec:
+        return None
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2409_02482_amd", "csrc"))):
+        h.update(open(os.path.join(ROOT, "paper_2409_02482_amd", "csrc", f), "rb").read())
+    if rec.get("csrc_sha256") != h.hexdigest():
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def cpu_baseline(scene, n_threads):
@@ -82,6 +103,7 @@ def main():
     ap.add_argument("--bin", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=8)
+    ap.add_argument("--unfused", action="store_true", help="separate forward shading pass before the adjoint")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; --gpus must be 1 (views would shard across GPUs, "
@@ -110,20 +132,27 @@ def main():
     loss_scale = 1.0 / (views.total_pixels * 3)
     stream = torch.cuda.current_stream()
 
+    sse = torch.zeros(1, dtype=torch.float64, device=dev)
+
     def step(ev=None):
+        # fused (default): the adjoint kernel recomputes the blend, writes the image and the SSE, and
+        # scatters the texture gradient; unfused: a separate forward shading pass writes the image.
         if ev is not None:
             ev[0].record(stream)
         P.raster(layers, views, vis, ws, bin=args.bin)
         if ev is not None:
             ev[1].record(stream)
-        P.render(layers, tex, views, vis, ws, out=out)
+        if args.unfused:
+            P.render(layers, tex, views, vis, ws, out=out)
         if ev is not None:
             ev[2].record(stream)
         for g in grads:
             g.zero_()
+        sse.zero_()
         if ev is not None:
             ev[3].record(stream)
-        P.render_backward(layers, tex, views, vis, ws, grad_tex=grads, target=target, loss_scale=loss_scale)
+        P.render_backward(layers, tex, views, vis, ws, grad_tex=grads, target=target, loss_scale=loss_scale,
+                          out=None if args.unfused else out, sse=sse)
         if ev is not None:
             ev[4].record(stream)
 
@@ -132,10 +161,9 @@ def main():
         step()
     torch.cuda.synchronize()
     st = P.read_status(ws)
-    visn = vis.view(torch.uint64) if hasattr(torch, "uint64") else None
     covered = int((vis != -1).sum().item())
-    # distinct texels touched per layer (for the byte model), from the visibility of this run
-    U = [int(t.shape[0] * t.shape[1]) for t in scene.textures]  # upper bound: every texel
+    # distinct texels read per layer (for the byte model): the texels that received a gradient
+    U = [int((g != 0).any(dim=-1).sum().item()) for g in grads]
     log(f"[bench] covered slots {covered} status {st}")
 
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
@@ -149,7 +177,7 @@ def main():
     ms_phase = phase.mean(0)
     ms_step = float(phase.sum(1).mean())
     ms_wall = wall / args.steps * 1e3
-    bm = byte_model(scene, nv, P_v, U)
+    bm = byte_model(scene, nv, P_v, U, fused=not args.unfused)
     names = ["raster", "shade_fwd", "grad_zero", "shade_bwd"]
     dom = int(np.argmax(ms_phase))
     dom_name = names[dom]
@@ -172,13 +200,13 @@ def main():
         "config": {"workload": f"k={k} displaced shells (101,760 tris/layer), {nv} ring views at "
                                f"{args.res}x{args.res}, 1024^2 f32 RGBA textures, raster+shade+adjoint (L2)",
                    "views": nv, "k": k, "resolution": [args.res, args.res], "covered_px_layers": covered,
-                   "bin": args.bin},
+                   "bin": args.bin, "fused_fwd_bwd": not args.unfused},
         "phases_ms": {n: float(m) for n, m in zip(names, ms_phase)},
         "triangles_per_s": tri_total / (ms_phase[0] * 1e-3),
         "alg_bytes_per_step": int(sum(bm[n] for n in names)),
         "alg_frac_of_peak_step": sum(bm[n] for n in names) / (ms_wall * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(dom_name)},
     }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

@@ -5,7 +5,7 @@ rendering of k nested UV-textured mesh shells and its texture adjoint, as
 hand-written HIP kernels behind a C ABI (include/vs.h).
 """
 from ._lib import LIB_PATH, VsError, load  # noqa: F401
-from .render import (Graph, Layers, Renderer, Views, adam_step, alloc_workspace, autotune, raster,  # noqa: F401
+from .binding import (Graph, Layers, Renderer, Views, adam_step, alloc_workspace, autotune, raster,  # noqa: F401
                      read_status, render, render_backward, workspace_bytes)
 
 __all__ = ["Layers", "Views", "Renderer", "raster", "render", "render_backward", "read_status",

@@ -24,7 +24,7 @@ from typing import List, Optional, Sequence
 import numpy as np
 import torch
 
-from . import render as R
+from . import binding as R
 
 
 def psnr_from_sse(sse: np.ndarray, n_scalars: int) -> np.ndarray:

@@ -58,7 +58,7 @@ def test_struct_layouts_match_c(C, tmp_path):
 
 
 def _cams(sizes):
-    from paper_2409_02482_amd.render import camera_struct
+    from paper_2409_02482_amd.binding import camera_struct
     cams = S.ring_cameras(3, len(sizes), sizes)
     return (C_lib().VsCamera * len(cams))(*[camera_struct(c) for c in cams]), cams
 

@@ -79,7 +79,10 @@ def test_projection_bit_exact(torch_cuda):
     P, layers, views, vis, ws, rgba, tex = gpu_render(sc)
     raw = ws.cpu().numpy()
     vpv = sum(m.n_vert for m in sc.layers)
-    rec = np.frombuffer(raw[256:256 + 16 * vpv * len(sc.cameras)].tobytes(),
+    # layout: 256-byte status block, then the 16-pixel tile -> view table (int32, 256-aligned)
+    n16 = int(views.host[views.n].tile_offset[1])
+    off0 = 256 + (n16 * 4 + 255) // 256 * 256
+    rec = np.frombuffer(raw[off0:off0 + 16 * vpv * len(sc.cameras)].tobytes(),
                         dtype=[("X", "<i4"), ("Y", "<i4"), ("w", "<f8")]).reshape(len(sc.cameras), vpv)
     for v, cam in enumerate(sc.cameras):
         off = 0
@@ -215,8 +218,13 @@ def test_autograd_function(torch_cuda):
     g = torch.from_numpy(np.random.default_rng(5).uniform(-1, 1, tuple(out.shape)).astype(np.float32)).cuda()
     (out * g).sum().backward()
     ref = P.render_backward(r.layers, [t.detach() for t in tex], r.views, r.vis, r.ws, grad_rgba=g)
+    torch.cuda.synchronize()
     for a, b in zip(tex, ref):
-        assert torch.allclose(a.grad, b, rtol=1e-5, atol=1e-6)
+        assert torch.isfinite(a.grad).all() and torch.isfinite(b).all()
+        # two runs of the same float atomics in different orders: compare normwise
+        err = (a.grad - b).abs().max().item() / max(b.abs().max().item(), 1e-30)
+        say(f"[gpu] autograd vs direct: rel err {err:.2e}")
+        assert err <= 1e-5
 
 
 # ---------------------------------------------------------------------------- raster variants
