@@ -69,12 +69,12 @@ def counter_traffic(kernel: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(scene, n_threads):
-    """The oracle as it stands, one view per thread (ctypes releases the GIL)."""
+def cpu_baseline(scene, n_threads, per_thread=2):
+    """The oracle as it stands, views spread over threads (ctypes releases the GIL)."""
     import concurrent.futures as cf
 
     import oracle as O
-    cams = scene.cameras[:n_threads]
+    cams = scene.cameras[:n_threads * per_thread]
 
     def one(v):
         cam = scene.cameras[v]
@@ -89,8 +89,8 @@ def cpu_baseline(scene, n_threads):
         covered = sum(ex.map(one, range(len(cams))))
     dt = time.perf_counter() - t0
     return {"value": covered / dt, "unit": "px*layers/s", "cores": n_threads, "kind": "oracle",
-            "sample": f"{len(cams)} of the 64 views (full 1024x1024, k=7), raster+shade+adjoint, one view per "
-                      f"thread, {dt:.1f} s wall"}
+            "sample": f"{len(cams)} of the 64 views (full 1024x1024, k=7), raster+shade+adjoint (L2), "
+                      f"{per_thread} views per thread on {n_threads} threads, {dt:.1f} s wall"}
 
 
 def main():
@@ -104,6 +104,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=8)
     ap.add_argument("--unfused", action="store_true", help="separate forward shading pass before the adjoint")
+    ap.add_argument("--workload", default="metric", choices=["metric", "cfg4"],
+                    help="metric: k=7, 64 views at 1024^2; cfg4: k=9, 299,208 tris/layer, 64 mixed-size views")
+    ap.add_argument("--graph", action="store_true", help="replay the step from a captured HIP graph")
+    ap.add_argument("--autotune", action="store_true", help="pick the raster bin size with vs_autotune")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="run one plain device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; --gpus must be 1 (views would shard across GPUs, "
@@ -116,11 +122,21 @@ def main():
     import scenes as S
 
     log("[bench] building scene")
-    scene = S.make_config(6, n_views=args.views, resolution=(args.res, args.res))
+    if args.workload == "cfg4":
+        scene = S.make_config(4, n_views=args.views)
+    else:
+        scene = S.make_config(6, n_views=args.views, resolution=(args.res, args.res))
     k = scene.k
     nv = len(scene.cameras)
-    P_v = args.res * args.res
     dev = "cuda"
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.calibrate_copy} MiB done")
+        del a, b
     layers = P.Layers(scene.layers, dev)
     views = P.Views(scene.cameras, dev)
     tex = [torch.from_numpy(t).to(dev) for t in scene.textures]
@@ -128,7 +144,10 @@ def main():
     grads = [torch.zeros_like(t) for t in tex]
     out = torch.empty(views.total_pixels, 4, dtype=torch.float32, device=dev)
     vis = torch.empty(k * views.total_pixels, dtype=torch.int64, device=dev)
-    ws = P.alloc_workspace(layers, views, args.bin, dev)
+    ws = P.alloc_workspace(layers, views, 8 if args.autotune else args.bin, dev)
+    if args.autotune:
+        args.bin = P.autotune(layers, views, vis, ws)
+        log(f"[bench] autotuned bin size {args.bin}")
     loss_scale = 1.0 / (views.total_pixels * 3)
     stream = torch.cuda.current_stream()
 
@@ -160,6 +179,14 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    graph = None
+    if args.graph:
+        # the whole step (raster, gradient reset, fused shade + adjoint) as one graph on torch's stream
+        side = torch.cuda.Stream()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            step()
+        torch.cuda.synchronize()
     st = P.read_status(ws)
     covered = int((vis != -1).sum().item())
     # distinct texels read per layer (for the byte model): the texels that received a gradient
@@ -168,15 +195,31 @@ def main():
 
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        step(evs[s])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    phase = np.array([[evs[s][i].elapsed_time(evs[s][i + 1]) for i in range(4)] for s in range(args.steps)])
+    if graph is not None:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(args.steps):
+            graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        # phase split from one eager step (graph replays are timed as a whole)
+        step(evs[0])
+        torch.cuda.synchronize()
+        phase = np.array([[evs[0][i].elapsed_time(evs[0][i + 1]) for i in range(4)]])
+        graph_ms = e0.elapsed_time(e1) / args.steps
+    else:
+        t0 = time.perf_counter()
+        for s in range(args.steps):
+            step(evs[s])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        phase = np.array([[evs[s][i].elapsed_time(evs[s][i + 1]) for i in range(4)] for s in range(args.steps)])
     ms_phase = phase.mean(0)
     ms_step = float(phase.sum(1).mean())
     ms_wall = wall / args.steps * 1e3
+    P_v = views.total_pixels / nv
     bm = byte_model(scene, nv, P_v, U, fused=not args.unfused)
     names = ["raster", "shade_fwd", "grad_zero", "shade_bwd"]
     dom = int(np.argmax(ms_phase))
@@ -197,10 +240,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"k={k} displaced shells (101,760 tris/layer), {nv} ring views at "
-                               f"{args.res}x{args.res}, 1024^2 f32 RGBA textures, raster+shade+adjoint (L2)",
-                   "views": nv, "k": k, "resolution": [args.res, args.res], "covered_px_layers": covered,
-                   "bin": args.bin, "fused_fwd_bwd": not args.unfused},
+        "config": {"workload": (f"k={k} displaced shells ({scene.layers[0].n_tri:,} tris/layer), {nv} ring views "
+                                + (f"at {args.res}x{args.res}" if args.workload == "metric" else
+                                   "of mixed size 512^2..1920x1080")
+                                + ", 1024^2 f32 RGBA textures, raster+shade+adjoint (L2)"),
+                   "views": nv, "k": k, "pixels": views.total_pixels, "covered_px_layers": covered,
+                   "bin": args.bin, "fused_fwd_bwd": not args.unfused, "graph": bool(args.graph)},
         "phases_ms": {n: float(m) for n, m in zip(names, ms_phase)},
         "triangles_per_s": tri_total / (ms_phase[0] * 1e-3),
         "alg_bytes_per_step": int(sum(bm[n] for n in names)),
@@ -208,7 +253,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(dom_name)},
     }
-    if not args.no_cpu_baseline:
+    if graph is not None:
+        res["graph_ms_per_step"] = graph_ms
+    if not args.no_cpu_baseline and args.workload == "metric":
         log("[bench] cpu baseline (oracle)")
         n = max(1, min(args.cpu_threads, os.cpu_count() or 1, nv))
         res["cpu_baseline"] = cpu_baseline(scene, n)

@@ -148,7 +148,8 @@ vs::WsLayout ws_layout(const vs::LayerTable& L, const vs_views* views, int bin, 
   w.bin_view = take((size_t)w.n_tiles_bin * 4);
   w.count = take((size_t)w.n_bins * 4);
   w.offset = take((size_t)w.n_bins * 4);
-  w.cursor = take((size_t)w.n_bins * 4);
+  w.cursor = take((size_t)w.n_bins * 8);
+  w.spans = take((size_t)n_views * (size_t)L.tri_off[L.k] * 8);
   w.partial = take((size_t)w.n_partial * 4);
   w.list = take((size_t)w.capacity * 4);
   w.total = off;
@@ -246,6 +247,7 @@ vs_status vs_raster_layers(const vs_mesh* layers, int32_t k, const vs_views* vie
   auto* count = (uint32_t*)(base + lay.count);
   auto* offset = (uint32_t*)(base + lay.offset);
   auto* cursor = (uint32_t*)(base + lay.cursor);
+  auto* spans = (uint64_t*)(base + lay.spans);
   auto* partial = (uint32_t*)(base + lay.partial);
   auto* list = (int32_t*)(base + lay.list);
   const int64_t vpv = L.vert_off[k];
@@ -269,17 +271,17 @@ vs_status vs_raster_layers(const vs_mesh* layers, int32_t k, const vs_views* vie
   hipLaunchKernelGGL(vs::k_tile_view_slot, dim3(grid_1d(lay.n_tiles_bin, 256)), dim3(256), 0, s, views->dev, nv,
                      bin_view, lay.n_tiles_bin, slot);
   hipLaunchKernelGGL(vs::k_fill_u32, dim3(fill_grid), dim3(256), 0, s, count, lay.n_bins, 0u);
-  hipLaunchKernelGGL(vs::k_fill_u32, dim3(fill_grid), dim3(256), 0, s, cursor, lay.n_bins, 0u);
+  hipLaunchKernelGGL(vs::k_fill_u32, dim3(fill_grid), dim3(256), 0, s, cursor, 2 * lay.n_bins, 0u);
   hipLaunchKernelGGL(vs::k_bin_count, dim3(grid_1d(ntri, 256), nv), dim3(256), 0, s, views->dev, L,
-                     (const vs::ProjVert*)proj, vpv, B, slot, count, status);
+                     (const vs::ProjVert*)proj, vpv, B, slot, count, spans, status);
   hipLaunchKernelGGL(vs::k_scan_local, dim3((unsigned)lay.n_partial), dim3(256), 0, s, (const uint32_t*)count,
                      offset, partial, lay.n_bins);
   hipLaunchKernelGGL(vs::k_scan_partials, dim3(1), dim3(1024), 0, s, partial, lay.n_partial);
   hipLaunchKernelGGL(vs::k_scan_add, dim3(grid_1d(lay.n_bins, 256)), dim3(256), 0, s, offset,
                      (const uint32_t*)partial, lay.n_bins);
-  hipLaunchKernelGGL(vs::k_bin_scatter, dim3(grid_1d(ntri, 256), nv), dim3(256), 0, s, views->dev, L,
-                     (const vs::ProjVert*)proj, vpv, B, slot, (const uint32_t*)count, (const uint32_t*)offset, cursor,
-                     list, lay.capacity, status);
+  hipLaunchKernelGGL(vs::k_bin_scatter, dim3(grid_1d(ntri, 256), nv), dim3(256), 0, s, views->dev, L, B, slot,
+                     (const uint64_t*)spans, (const uint32_t*)count, (const uint32_t*)offset, cursor, list,
+                     lay.capacity);
   const unsigned nblk = (unsigned)((lay.n_bins + 7) / 8 * 8);
   auto raster = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(nblk), dim3(vs::kRasterThreads), 0, s, views->dev, (const int32_t*)bin_view,

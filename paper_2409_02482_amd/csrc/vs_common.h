@@ -55,7 +55,8 @@ struct WsLayout {
   size_t proj;       // ProjVert [n_views][sum n_vert]
   size_t count;      // u32 [n_bins] triangles per bin
   size_t offset;     // u32 [n_bins] exclusive prefix of count
-  size_t cursor;     // u32 [n_bins] scatter cursors
+  size_t cursor;     // u32 [2 n_bins] scatter cursors (front from the head, others from the tail)
+  size_t spans;      // u64 [n_views][sum n_tri] packed tile span of every triangle
   size_t partial;    // u32 [ceil(n_bins / 1024)] scan block totals
   size_t list;       // int32 [capacity] triangle ids of all bins
   int64_t n_tiles16, n_tiles_bin, n_bins, n_partial;
@@ -99,6 +100,7 @@ struct TriSetup {
   int32_t vid[3];
   double area2;      // > 0
   double th[3];      // inside iff E_e >= th_e: 0 for an owned (top/left) edge, 1 otherwise
+  int orig_sign;     // sign of the screen area before normalisation
 };
 
 enum { kTriOk = 0, kTriInvalid = 1, kTriDegenerate = 2, kTriBadIndex = 3 };
@@ -121,6 +123,7 @@ __device__ inline int setup_triangle(const int32_t* ids, int32_t n_vert, const P
   double area2 = ((double)b.X - (double)a.X) * ((double)c.Y - (double)a.Y) -
                  ((double)b.Y - (double)a.Y) * ((double)c.X - (double)a.X);
   if (area2 == 0.0) return kTriDegenerate;
+  T.orig_sign = area2 < 0.0 ? -1 : 1;
   if (area2 < 0.0) {
     const ProjVert t = b; b = c; c = t;
     const int32_t ti = id[1]; id[1] = id[2]; id[2] = ti;
@@ -152,6 +155,20 @@ __device__ inline uint64_t depth_key(const TriSetup& T, double E0, double E1, do
   const double z = T.area2 / s;
   const float zf = (float)z;
   return ((uint64_t)__float_as_uint(zf) << 32) | (uint64_t)t;
+}
+
+// A key no smaller than any key this triangle can produce, for skipping the
+// exact depth of fragments that cannot win.  Inside the triangle the edge
+// values are non-negative and sum to area2, so 1/z <= max w, i.e.
+// z >= 1 / max w; the computed z (three products, two sums, one quotient,
+// each correctly rounded) is at least (1/max w)(1 - 5e-16).  The bound below
+// sits 1e-12 under that and is rounded down to float, so
+// float(z) >= lower and hence depth_key(...) >= the returned key.
+__device__ inline uint64_t depth_lower_key(const TriSetup& T, uint32_t t) {
+  const double maxw = fmax(T.w[0], fmax(T.w[1], T.w[2]));
+  const double zlo = (1.0 / maxw) * (1.0 - 1e-12);
+  const float lo = __double2float_rd(zlo);
+  return ((uint64_t)__float_as_uint(lo) << 32) | (uint64_t)t;
 }
 
 // Binary search of the view that owns flat index g in a prefix array read

@@ -5,11 +5,14 @@
 //   k_project      snapped screen positions and w = 1/z for every (view, layer, vertex)
 //   k_bin_count    per triangle: setup, cull, bounding box -> screen tiles of
 //                  B x B pixels; count triangles per bin = (view, tile, layer)
+//                  and record the triangle's packed tile span
 //   k_scan_*       exclusive prefix sum of the counts -> list offsets
-//   k_bin_scatter  write triangle ids into the bin lists
+//   k_bin_scatter  write triangle ids into the bin lists (front faces first)
 //   k_raster_bins  one block per bin: an LDS tile of keys starts EMPTY, the
 //                  bin's triangles take 64-bit LDS minima, and the finished
-//                  tile is stored once, coalesced (so no clear pass is needed)
+//                  tile is stored once, coalesced (so no clear pass is needed);
+//                  a fragment whose depth lower bound already loses to the
+//                  tile's key skips the exact FP64 depth
 // Atomics on bin counters are aggregated per wavefront: lanes that hit the
 // same bin elect one lane that adds the whole group.
 #pragma once
@@ -20,7 +23,7 @@ namespace vs {
 
 constexpr int kRasterThreads = 256;
 constexpr int kSmallSpan = 16384;   // small-triangle path: bbox extents <= 64 px, so edge values fit int32
-constexpr int kSmallArea = 64;      // ... and at most this many candidate pixels in the tile
+constexpr int kSmallArea = 256;     // ... and at most this many candidate pixels in the tile
 
 // Fill n u64 words with a value (grid-stride).
 __global__ void __launch_bounds__(256) k_fill_u64(uint64_t* __restrict__ p, int64_t n, uint64_t val) {
@@ -68,51 +71,76 @@ __device__ inline int cull_slot(int r) {
 // Bin index of (global tile g, layer l): bins of one tile are consecutive.
 __device__ inline int64_t bin_index(int64_t g, int l, int k) { return g * k + l; }
 
-// Shared front end of the count and scatter passes: the triangle handled by
-// this thread and its tile span.  Returns false if it covers no pixel.
+// Tile span of one (view, layer, triangle), packed in 64 bits:
+// tx0 | tx1 << 13 | ty0 << 26 | ty1 << 39 | front << 52 | valid << 53.
+// "front" marks a negative screen area before orientation normalisation,
+// which is the front side of an outward, counter-clockwise wound closed mesh
+// under this camera convention (y down).  It only orders the bin lists.
+constexpr uint64_t kSpanValid = 1ull << 53;
+constexpr uint64_t kSpanFront = 1ull << 52;
+
+__device__ inline uint64_t pack_span(int tx0, int tx1, int ty0, int ty1, bool front) {
+  return (uint64_t)tx0 | ((uint64_t)tx1 << 13) | ((uint64_t)ty0 << 26) | ((uint64_t)ty1 << 39) |
+         (front ? kSpanFront : 0ull) | kSpanValid;
+}
+
 struct BinWork {
   int v, l;
   int32_t t;
   int tx0, tx1, ty0, ty1;   // tile span (inclusive)
+  bool front;
   int64_t g0;               // global tile index of the view's tile (0, 0)
   int ntx;                  // tiles per row in this view
 };
 
-__device__ inline bool bin_front(const vs_view* __restrict__ views, const LayerTable& L,
-                                 const ProjVert* __restrict__ proj, int64_t vpv, int B, int slot, BinWork& w,
-                                 unsigned long long* status, bool count_culls) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int v = blockIdx.y;
+// Which (view, layer, triangle) this thread of a count/scatter launch handles
+// (grid.x over the triangles of all layers, grid.y = view).
+__device__ inline bool bin_thread(const LayerTable& L, int& v, int& l, int32_t& t, int64_t& g) {
+  g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  v = blockIdx.y;
   const int k = L.k;
   if (g >= L.tri_off[k]) return false;
-  int l = 0;
+  l = 0;
   while (l + 1 < k && L.tri_off[l + 1] <= g) ++l;
-  const int32_t t = (int32_t)(g - L.tri_off[l]);
-  const vs_view& V = views[v];
-  const int W = V.cam.width, H = V.cam.height;
-  const ProjVert* P = proj + (int64_t)v * vpv + L.vert_off[l];
-  TriSetup T;
-  const int r = setup_triangle(L.tri[l] + 3 * (int64_t)t, L.n_vert[l], P, T);
-  if (r != kTriOk) {
-    if (count_culls) atomicAdd(status + cull_slot(r), 1ull);
-    return false;
-  }
-  const PixRange pr = pixel_range(T, W, H);
-  if (pr.i0 > pr.i1 || pr.j0 > pr.j1) return false;
-  w.v = v; w.l = l; w.t = t;
-  w.tx0 = pr.i0 / B; w.tx1 = pr.i1 / B; w.ty0 = pr.j0 / B; w.ty1 = pr.j1 / B;
-  w.g0 = V.tile_offset[slot];
-  w.ntx = (W + B - 1) / B;
+  t = (int32_t)(g - L.tri_off[l]);
   return true;
 }
 
-// Count triangles per bin.
+// Count triangles per bin and record each triangle's tile span.
 __global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ views, LayerTable L,
                                                    const ProjVert* __restrict__ proj, int64_t vpv, int B, int slot,
-                                                   uint32_t* __restrict__ count, unsigned long long* __restrict__ status) {
-  BinWork w;
-  const bool ok = bin_front(views, L, proj, vpv, B, slot, w, status, true);
+                                                   uint32_t* __restrict__ count, uint64_t* __restrict__ spans,
+                                                   unsigned long long* __restrict__ status) {
+  int v = 0, l = 0;
+  int32_t t = 0;
+  int64_t g = 0;
+  bool ok = bin_thread(L, v, l, t, g);
   const int k = L.k;
+  BinWork w;
+  uint64_t span = 0;
+  if (ok) {
+    const vs_view& V = views[v];
+    const int W = V.cam.width, H = V.cam.height;
+    const ProjVert* P = proj + (int64_t)v * vpv + L.vert_off[l];
+    TriSetup T;
+    const int r = setup_triangle(L.tri[l] + 3 * (int64_t)t, L.n_vert[l], P, T);
+    if (r != kTriOk) {
+      atomicAdd(status + cull_slot(r), 1ull);
+      ok = false;
+    } else {
+      const PixRange pr = pixel_range(T, W, H);
+      if (pr.i0 > pr.i1 || pr.j0 > pr.j1) {
+        ok = false;
+      } else {
+        w.l = l; w.t = t;
+        w.tx0 = pr.i0 / B; w.tx1 = pr.i1 / B; w.ty0 = pr.j0 / B; w.ty1 = pr.j1 / B;
+        w.g0 = V.tile_offset[slot];
+        w.ntx = (W + B - 1) / B;
+        span = pack_span(w.tx0, w.tx1, w.ty0, w.ty1, T.orig_sign < 0);
+      }
+    }
+    spans[(int64_t)v * L.tri_off[k] + g] = span;
+  }
   // first bin of every lane: aggregated across the wavefront
   int64_t b0 = ok ? bin_index(w.g0 + (int64_t)w.ty0 * w.ntx + w.tx0, w.l, k) : -1;
   uint64_t active = __ballot(b0 >= 0);
@@ -192,42 +220,61 @@ __global__ void __launch_bounds__(256) k_scan_add(uint32_t* __restrict__ out, co
   if (i < n) out[i] += partial[i / 1024];
 }
 
-// Write triangle ids into the bin lists.  A bin whose list would end past the
-// capacity is left unwritten; the raster of that bin then scans every
+// Write triangle ids into the bin lists: front-facing triangles from the
+// head of a bin's list, the others from its tail.  A bin whose list would end
+// past the capacity is left unwritten; the raster of that bin then scans every
 // triangle of its layer instead (slow but exact) and the overflow is counted.
-__global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__ views, LayerTable L,
-                                                     const ProjVert* __restrict__ proj, int64_t vpv, int B, int slot,
+__global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__ views, LayerTable L, int B, int slot,
+                                                     const uint64_t* __restrict__ spans,
                                                      const uint32_t* __restrict__ count,
                                                      const uint32_t* __restrict__ offset,
                                                      uint32_t* __restrict__ cursor, int32_t* __restrict__ list,
-                                                     uint64_t capacity, unsigned long long* __restrict__ status) {
-  BinWork w;
-  const bool ok = bin_front(views, L, proj, vpv, B, slot, w, status, false);
+                                                     uint64_t capacity) {
+  int v = 0, l = 0;
+  int32_t t = 0;
+  int64_t g = 0;
+  bool ok = bin_thread(L, v, l, t, g);
   const int k = L.k;
-  int64_t b0 = ok ? bin_index(w.g0 + (int64_t)w.ty0 * w.ntx + w.tx0, w.l, k) : -1;
-  uint64_t active = __ballot(b0 >= 0);
+  uint64_t span = ok ? spans[(int64_t)v * L.tri_off[k] + g] : 0ull;
+  ok = ok && (span & kSpanValid);
+  int tx0 = 0, tx1 = 0, ty0 = 0, ty1 = 0, ntx = 0;
+  int64_t g0 = 0;
+  bool front = false;
+  if (ok) {
+    tx0 = (int)(span & 8191); tx1 = (int)((span >> 13) & 8191);
+    ty0 = (int)((span >> 26) & 8191); ty1 = (int)((span >> 39) & 8191);
+    front = (span & kSpanFront) != 0;
+    const vs_view& V = views[v];
+    g0 = V.tile_offset[slot];
+    ntx = (V.cam.width + B - 1) / B;
+  }
+  // cursors: [2 b] counts front entries from the head, [2 b + 1] the others from the tail
+  const int64_t b0 = ok ? bin_index(g0 + (int64_t)ty0 * ntx + tx0, l, k) : -1;
+  const int64_t c0 = ok ? 2 * b0 + (front ? 0 : 1) : -1;
+  uint64_t active = __ballot(c0 >= 0);
   const uint64_t lt = __lanemask_lt();
   while (active) {
     const int leader = __ffsll((unsigned long long)active) - 1;
-    const int64_t lb = __shfl(b0, leader);
-    const uint64_t same = __ballot(b0 == lb);
+    const int64_t lc = __shfl(c0, leader);
+    const uint64_t same = __ballot(c0 == lc);
     uint32_t base = 0;
-    if ((int)__lane_id() == leader) base = atomicAdd(cursor + lb, (uint32_t)__popcll(same));
+    if ((int)__lane_id() == leader) base = atomicAdd(cursor + lc, (uint32_t)__popcll(same));
     base = __shfl(base, leader);
-    if (b0 == lb) {
-      const uint64_t end = (uint64_t)offset[lb] + count[lb];
-      if (end <= capacity) list[offset[lb] + base + __popcll(same & lt)] = w.t;
+    if (c0 == lc) {
+      const uint32_t rank = base + (uint32_t)__popcll(same & lt);
+      const uint64_t end = (uint64_t)offset[b0] + count[b0];
+      if (end <= capacity) list[front ? offset[b0] + rank : end - 1 - rank] = t;
     }
     active &= ~same;
   }
   if (!ok) return;
-  for (int ty = w.ty0; ty <= w.ty1; ++ty)
-    for (int tx = w.tx0; tx <= w.tx1; ++tx) {
-      if (ty == w.ty0 && tx == w.tx0) continue;
-      const int64_t b = bin_index(w.g0 + (int64_t)ty * w.ntx + tx, w.l, k);
-      const uint32_t pos = atomicAdd(cursor + b, 1u);
+  for (int ty = ty0; ty <= ty1; ++ty)
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      if (ty == ty0 && tx == tx0) continue;
+      const int64_t b = bin_index(g0 + (int64_t)ty * ntx + tx, l, k);
+      const uint32_t rank = atomicAdd(cursor + 2 * b + (front ? 0 : 1), 1u);
       const uint64_t end = (uint64_t)offset[b] + count[b];
-      if (end <= capacity) list[offset[b] + pos] = w.t;
+      if (end <= capacity) list[front ? offset[b] + rank : end - 1 - rank] = t;
     }
 }
 
@@ -293,6 +340,7 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
           const double spany = fmax(T.Y[0], fmax(T.Y[1], T.Y[2])) - fmin(T.Y[0], fmin(T.Y[1], T.Y[2]));
           const int area = (ci1 - ci0 + 1) * (cj1 - cj0 + 1);
           if (spanx <= kSmallSpan && spany <= kSmallSpan && area <= kSmallArea) {
+            const unsigned long long lbkey = depth_lower_key(T, (uint32_t)t);
             // exact int32 edge walk: every edge value inside the bbox is below 2^30 in magnitude
             double E[3];
             edge_values(T, 256.0 * ci0 + 128.0, 256.0 * cj0 + 128.0, E);
@@ -306,9 +354,12 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
               int32_t e0 = er0, e1 = er1, e2 = er2;
               for (int i = ci0; i <= ci1; ++i) {
                 if ((e0 | e1 | e2) >= 0) {
-                  const double E0 = (double)e0 + T.th[0], E1 = (double)e1 + T.th[1], E2 = (double)e2 + T.th[2];
-                  atomicMin(&tile[(j - y0) * B + (i - x0)],
-                            (unsigned long long)depth_key(T, E0, E1, E2, (uint32_t)t));
+                  unsigned long long* slotp = &tile[(j - y0) * B + (i - x0)];
+                  // keys only decrease, so a single-copy-atomic read at or below the bound proves a loss
+                  if (__hip_atomic_load(slotp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) > lbkey) {
+                    const double E0 = (double)e0 + T.th[0], E1 = (double)e1 + T.th[1], E2 = (double)e2 + T.th[2];
+                    atomicMin(slotp, (unsigned long long)depth_key(T, E0, E1, E2, (uint32_t)t));
+                  }
                   ++frags;
                 }
                 e0 += ax0; e1 += ax1; e2 += ax2;
@@ -327,13 +378,15 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
       const int32_t t = queue[q];
       TriSetup T;
       setup_triangle(tri + 3 * (int64_t)t, nvert, P, T);
+      const unsigned long long lbkey = depth_lower_key(T, (uint32_t)t);
       for (int p = tid; p < B * B; p += kRasterThreads) {
         const int i = x0 + (p % B), j = y0 + (p / B);
         if (i > x1 || j > y1) continue;
         double E[3];
         edge_values(T, 256.0 * i + 128.0, 256.0 * j + 128.0, E);
         if (E[0] >= T.th[0] && E[1] >= T.th[1] && E[2] >= T.th[2]) {
-          atomicMin(&tile[p], (unsigned long long)depth_key(T, E[0], E[1], E[2], (uint32_t)t));
+          if (__hip_atomic_load(&tile[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) > lbkey)
+            atomicMin(&tile[p], (unsigned long long)depth_key(T, E[0], E[1], E[2], (uint32_t)t));
           ++frags;
         }
       }

@@ -170,8 +170,20 @@ __global__ void __launch_bounds__(256) k_shade_fwd(const vs_view* __restrict__ v
   const ProjVert* pview = proj + (int64_t)c.v * vpv;
   const double px = 256.0 * c.x + 128.0, py = 256.0 * c.y + 128.0;
   float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = c.valid ? 1.0f : 0.0f;
+  // keys of the first layers are requested together (several loads in flight)
+  constexpr int kPre = 4;
+  uint64_t pre[kPre];
+#pragma unroll
+  for (int l = 0; l < kPre; ++l) pre[l] = (l < k && c.valid) ? vrow[l * P] : kEmpty;
   for (int l = 0; l < k; ++l) {
-    const uint64_t key = c.valid ? vrow[l * P] : kEmpty;
+    uint64_t key;
+    if (l < kPre) {
+      key = pre[0];
+#pragma unroll
+      for (int q = 1; q < kPre; ++q) key = (l == q) ? pre[q] : key;
+    } else {
+      key = c.valid ? vrow[l * P] : kEmpty;
+    }
     if (key != kEmpty) {
       Foot f;
       const int32_t Wt = X.w[l], Ht = X.h[l];
@@ -206,17 +218,57 @@ __device__ inline int32_t abs_index(int32_t r, int32_t d, int32_t n, int wrap) {
   return i;
 }
 
+// Wavefront min / max without the LDS pipe: inclusive row scans with DPP
+// row shifts (lanes outside the row contribute the identity), then the four
+// row results are combined from lanes 15, 31, 47 and 63.  Call with every
+// lane active.
+__device__ inline int32_t wave_min(int32_t v) {
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+  const int32_t a = __builtin_amdgcn_readlane(v, 15), b = __builtin_amdgcn_readlane(v, 31);
+  const int32_t c = __builtin_amdgcn_readlane(v, 47), d = __builtin_amdgcn_readlane(v, 63);
+  return min(min(a, b), min(c, d));
+}
+
+__device__ inline int32_t wave_max(int32_t v) {
+  v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x111, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x112, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x114, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x118, 0xf, 0xf, false));
+  const int32_t a = __builtin_amdgcn_readlane(v, 15), b = __builtin_amdgcn_readlane(v, 31);
+  const int32_t c = __builtin_amdgcn_readlane(v, 47), d = __builtin_amdgcn_readlane(v, 63);
+  return max(max(a, b), max(c, d));
+}
+
+// Value of v in lane (lane ^ 1) / (lane ^ 2) of the same quad (DPP quad_perm).
+__device__ inline int32_t quad_xor1(int32_t v) { return __builtin_amdgcn_mov_dpp(v, 0xb1, 0xf, 0xf, false); }
+__device__ inline int32_t quad_xor2(int32_t v) { return __builtin_amdgcn_mov_dpp(v, 0x4e, 0xf, 0xf, false); }
+__device__ inline float quad_xor1(float v) { return __int_as_float(quad_xor1(__float_as_int(v))); }
+__device__ inline float quad_xor2(float v) { return __int_as_float(quad_xor2(__float_as_int(v))); }
+
+// Orders this wavefront's LDS accesses (issued in program order by one wave).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kWaveWin = 256;   // texels in each wavefront's LDS gradient window (4 KB)
+
 // Backward: recompute the layers front to back (keeping c, a, T and the
 // footprint of each hit layer), form dL/d(RGB, A), then walk back to front:
 //   dL/dc_l = g_rgb a_l T_l,  dL/da_l = T_l <g_rgb, c_l - S_l> + g_A T_l prod_{m>l}(1 - a_m),
 // S_l the colour blended behind layer l.  Division-free (a = 1 is fine).
 // Each of the 4 corner texels receives its bilinear weight times these.
 //
-// Scatter: per layer, the block's footprints are gathered into an LDS texel
-// window (relative to a reference texel, wrap-aware) with LDS atomics, then
-// the window is flushed with coalesced global atomics, skipping untouched
-// texels.  A layer whose footprint does not fit the window falls back to
-// direct global atomics for that block.
+// Scatter, per wavefront (16 x 4 pixels) and layer: a wave that hits the
+// layer reduces its footprints to a texel window (wrap-aware, relative to
+// the smallest hit texel) with shuffles, accumulates its 16 contributions per
+// pixel there with LDS float atomics, and flushes the window with global
+// float atomics, skipping untouched texels.  No block-wide barrier is
+// involved.  A footprint larger than the window uses direct global atomics.
 template <int KMAX>
 __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ views, int n_views,
                                                    const int32_t* __restrict__ tile_view, int64_t n_tiles,
@@ -227,11 +279,13 @@ __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ v
                                                    float4* __restrict__ out, double* __restrict__ sse, int wrap,
                                                    unsigned long long* __restrict__ status) {
 #pragma clang fp contract(fast)
-  __shared__ float win[kWinTexels * 4];
-  __shared__ int red[8];
+  __shared__ float win_all[4][kWaveWin * 4];
   __shared__ double sred[4];
   const TileCoord c = shade_tile_coord(views, n_views, tile_view, n_tiles);
   if (!c.live) return;  // uniform per block
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  float* win = win_all[tid >> 6];
   const vs_view& V = views[c.v];
   const int W = V.cam.width, H = V.cam.height;
   const int64_t P = (int64_t)W * H;
@@ -240,29 +294,30 @@ __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ v
   const uint64_t* vrow = vis + (int64_t)k * V.pix_offset + pix;
   const ProjVert* pview = proj + (int64_t)c.v * vpv;
   const double px = 256.0 * c.x + 128.0, py = 256.0 * c.y + 128.0;
+  // every layer's key is requested before any is used (k loads in flight)
+  uint64_t keys[KMAX];
+#pragma unroll
+  for (int l = 0; l < KMAX; ++l) keys[l] = (l < k && c.valid) ? vrow[l * P] : kEmpty;
   float cr[KMAX], cg[KMAX], cb[KMAX], ca[KMAX], Tl[KMAX], fxs[KMAX], fys[KMAX];
   int32_t ii[KMAX], jj[KMAX];   // packed (i1 << 16 | i0), (j1 << 16 | j0)
   uint32_t hitmask = 0;
   float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.0f;
 #pragma unroll
   for (int l = 0; l < KMAX; ++l) {
-    if (l < k && c.valid) {
-      const uint64_t key = vrow[l * P];
-      Foot f;
-      if (key != kEmpty &&
-          slot_footprint(L.tri[l], L.n_tri[l], L.n_vert[l], pview + L.vert_off[l],
-                         reinterpret_cast<const float2*>(L.uv[l]), key, px, py, X.w[l], X.h[l], X.inv_w[l],
-                         X.inv_h[l], wrap, f, status)) {
-        const float4 s = bilinear(X.tex[l], X.w[l], f);
-        hitmask |= 1u << l;
-        cr[l] = s.x; cg[l] = s.y; cb[l] = s.z; ca[l] = s.w; Tl[l] = T;
-        fxs[l] = f.fx; fys[l] = f.fy;
-        ii[l] = (f.i1 << 16) | f.i0;
-        jj[l] = (f.j1 << 16) | f.j0;
-        const float ta = T * s.w;
-        Cr += ta * s.x; Cg += ta * s.y; Cb += ta * s.z;
-        T *= (1.0f - s.w);
-      }
+    Foot f;
+    if (keys[l] != kEmpty &&
+        slot_footprint(L.tri[l], L.n_tri[l], L.n_vert[l], pview + L.vert_off[l],
+                       reinterpret_cast<const float2*>(L.uv[l]), keys[l], px, py, X.w[l], X.h[l], X.inv_w[l],
+                       X.inv_h[l], wrap, f, status)) {
+      const float4 s = bilinear(X.tex[l], X.w[l], f);
+      hitmask |= 1u << l;
+      cr[l] = s.x; cg[l] = s.y; cb[l] = s.z; ca[l] = s.w; Tl[l] = T;
+      fxs[l] = f.fx; fys[l] = f.fy;
+      ii[l] = (f.i1 << 16) | f.i0;
+      jj[l] = (f.j1 << 16) | f.j0;
+      const float ta = T * s.w;
+      Cr += ta * s.x; Cg += ta * s.y; Cb += ta * s.z;
+      T *= (1.0f - s.w);
     }
   }
   float gr = 0.f, gg = 0.f, gb = 0.f, gA = 0.f;
@@ -282,11 +337,11 @@ __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ v
     if (out) out[gp] = make_float4(Cr, Cg, Cb, 1.0f - T);
   }
   float Sr = 0.f, Sg = 0.f, Sb = 0.f, Pm = 1.0f;
-  const int tid = threadIdx.x;
 #pragma unroll
   for (int l = KMAX - 1; l >= 0; --l) {
     if (l >= k) continue;  // uniform
     const bool hit = (hitmask >> l) & 1u;
+    if (!__any(hit)) continue;  // uniform per wavefront
     float d[4] = {0.f, 0.f, 0.f, 0.f};   // dL/d(r, g, b, a) of this layer's sample
     float wq[4] = {0.f, 0.f, 0.f, 0.f};
     int32_t i0 = 0, i1 = 0, j0 = 0, j1 = 0;
@@ -305,46 +360,74 @@ __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ v
     }
     float* G = X.grad[l];
     const int32_t Wt = X.w[l], Ht = X.h[l];
-    // --- window extent: reference texel = min packed index over hit lanes
-    if (tid == 0) { red[0] = INT32_MAX; red[1] = INT32_MAX; red[2] = INT32_MIN; red[3] = INT32_MAX; red[4] = INT32_MIN; }
-    __syncthreads();
-    if (hit) atomicMin(&red[0], j0 * Wt + i0);
-    __syncthreads();
-    const int32_t refp = red[0];
-    if (refp == INT32_MAX) { __syncthreads(); continue; }   // no lane of the block hit this layer
+    // window: relative to the smallest packed texel index among the wave's hits
+    const int32_t refp = wave_min(hit ? j0 * Wt + i0 : INT32_MAX);
     const int32_t rj = refp / Wt, ri = refp - rj * Wt;
     int32_t di0 = 0, di1 = 0, dj0 = 0, dj1 = 0;
     if (hit) {
       di0 = rel_index(i0, ri, Wt, wrap); di1 = rel_index(i1, ri, Wt, wrap);
       dj0 = rel_index(j0, rj, Ht, wrap); dj1 = rel_index(j1, rj, Ht, wrap);
-      atomicMin(&red[1], min(di0, di1)); atomicMax(&red[2], max(di0, di1));
-      atomicMin(&red[3], min(dj0, dj1)); atomicMax(&red[4], max(dj0, dj1));
     }
-    __syncthreads();
-    const int32_t dmin_i = red[1], dmin_j = red[3];
-    const int32_t ww = red[2] - dmin_i + 1, wh = red[4] - dmin_j + 1;
-    if (ww * wh <= kWinTexels) {
-      for (int e = tid; e < ww * wh * 4; e += 256) win[e] = 0.0f;
-      __syncthreads();
+    const int32_t dmin_i = wave_min(hit ? min(di0, di1) : INT32_MAX);
+    const int32_t dmax_i = wave_max(hit ? max(di0, di1) : INT32_MIN);
+    const int32_t dmin_j = wave_min(hit ? min(dj0, dj1) : INT32_MAX);
+    const int32_t dmax_j = wave_max(hit ? max(dj0, dj1) : INT32_MIN);
+    const int32_t ww = dmax_i - dmin_i + 1, wh = dmax_j - dmin_j + 1;
+    if (ww * wh <= kWaveWin) {
+      // channel-major window: win[ch * kWaveWin + cell], so neighbouring cells sit in neighbouring banks
+      const int32_t ncell = ww * wh;
+      for (int e = lane; e < ncell; e += 64) {
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) win[ch * kWaveWin + e] = 0.0f;
+      }
+      int32_t cell[4] = {-1, -1, -1, -1};
+      float val[4][4];
       if (hit) {
         const int32_t x0 = di0 - dmin_i, x1 = di1 - dmin_i, y0 = dj0 - dmin_j, y1 = dj1 - dmin_j;
-        const int32_t s[4] = {(y0 * ww + x0) * 4, (y0 * ww + x1) * 4, (y1 * ww + x0) * 4, (y1 * ww + x1) * 4};
+        cell[0] = y0 * ww + x0; cell[1] = y0 * ww + x1; cell[2] = y1 * ww + x0; cell[3] = y1 * ww + x1;
+      }
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) val[n][ch] = wq[n] * d[ch];
+      }
+      // Neighbouring pixels (x, x^1), then (x, x^2), often share a corner texel: the lower
+      // lane of a matching pair takes the partner's contribution and the upper lane drops its own.
+#pragma unroll
+      for (int step = 0; step < 2; ++step) {
+        const int bit = 1 << step;
+        const bool upper = (lane & bit) != 0;
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
+          const int32_t other = step == 0 ? quad_xor1(cell[n]) : quad_xor2(cell[n]);
+          const bool same = cell[n] >= 0 && other == cell[n];
 #pragma unroll
-          for (int ch = 0; ch < 4; ++ch) atomicAdd(&win[s[n] + ch], wq[n] * d[ch]);
+          for (int ch = 0; ch < 4; ++ch) {
+            const float ov = step == 0 ? quad_xor1(val[n][ch]) : quad_xor2(val[n][ch]);
+            if (same && !upper) val[n][ch] += ov;
+          }
+          if (same && upper) cell[n] = -1;
         }
       }
-      __syncthreads();
-      for (int e = tid; e < ww * wh * 4; e += 256) {
-        const float val = win[e];
-        if (val != 0.0f) {
-          const int32_t cell = e >> 2, ch = e & 3;
-          const int32_t y = cell / ww, x = cell - y * ww;
+      wave_lds_sync();
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        if (cell[n] >= 0) {
+#pragma unroll
+          for (int ch = 0; ch < 4; ++ch) atomicAdd(&win[ch * kWaveWin + cell[n]], val[n][ch]);
+        }
+      }
+      wave_lds_sync();
+      for (int e = lane; e < ncell * 4; e += 64) {
+        const int32_t cl = e >> 2, ch = e & 3;
+        const float v = win[ch * kWaveWin + cl];
+        if (v != 0.0f) {
+          const int32_t y = cl / ww, x = cl - y * ww;
           const int32_t ti = abs_index(ri, dmin_i + x, Wt, wrap), tj = abs_index(rj, dmin_j + y, Ht, wrap);
-          unsafeAtomicAdd(G + ((int64_t)tj * Wt + ti) * 4 + ch, val);
+          unsafeAtomicAdd(G + ((int64_t)tj * Wt + ti) * 4 + ch, v);
         }
       }
+      wave_lds_sync();   // the window is reused by the next layer
     } else if (hit) {
       const int32_t q[4] = {j0 * Wt + i0, j0 * Wt + i1, j1 * Wt + i0, j1 * Wt + i1};
 #pragma unroll
@@ -353,13 +436,12 @@ __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ v
         for (int ch = 0; ch < 4; ++ch) unsafeAtomicAdd(G + (int64_t)q[n] * 4 + ch, wq[n] * d[ch]);
       }
     }
-    __syncthreads();  // red[] and win[] are reused by the next layer
   }
   if (sse) {
     // block reduction of the squared error, one atomic per block
     double v = my_sse;
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if ((tid & 63) == 0) sred[tid >> 6] = v;
+    if (lane == 0) sred[tid >> 6] = v;
     __syncthreads();
     if (tid == 0) unsafeAtomicAdd(sse, (sred[0] + sred[1]) + (sred[2] + sred[3]));
   }
