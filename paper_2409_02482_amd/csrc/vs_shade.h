@@ -19,7 +19,6 @@ namespace vs {
 constexpr int kShadeTile = 16;      // 16 x 16 pixel tiles, one 256-thread block each
 constexpr int kShadeTileSlot = 1;   // vs_view::tile_offset slot of 16-pixel tiles
 constexpr int kNumXcd = 8;
-constexpr int kWinTexels = 1024;    // LDS gradient window of the adjoint (16 KB)
 
 struct Foot {
   int32_t i0, i1, j0, j1;  // wrapped texel indices of the 2x2 footprint
@@ -133,8 +132,11 @@ __device__ inline TileCoord shade_tile_coord(const vs_view* __restrict__ views, 
   const int tiles_x = (V.cam.width + kShadeTile - 1) / kShadeTile;
   const int64_t ty = local / tiles_x, tx = local - ty * tiles_x;
   if (local < 0 || ty * kShadeTile >= V.cam.height) { c.live = false; return c; }
-  c.x = (int)tx * kShadeTile + (threadIdx.x % kShadeTile);
-  c.y = (int)ty * kShadeTile + (threadIdx.x / kShadeTile);
+  // lane bits: 0 = dx, 1 = dy, 2..4 = 2-pixel column, 5 = 2-pixel row; wave w covers rows 4w..4w+3.
+  // Every wave still reads whole 16-pixel row segments, and each DPP quad is a 2 x 2 pixel block.
+  const int t = threadIdx.x, lane = t & 63;
+  c.x = (int)tx * kShadeTile + ((lane >> 2) & 7) * 2 + (lane & 1);
+  c.y = (int)ty * kShadeTile + (t >> 6) * 4 + ((lane >> 5) & 1) * 2 + ((lane >> 1) & 1);
   c.valid = c.x < V.cam.width && c.y < V.cam.height;
   return c;
 }
@@ -202,6 +204,40 @@ __global__ void __launch_bounds__(256) k_shade_fwd(const vs_view* __restrict__ v
 }
 
 // Relative texel offset of index i from reference r in [-n/2, n/2) (repeat) or plain difference (clamp).
+
+
+// Wavefront min / max without the LDS pipe: inclusive row scans with DPP
+// row shifts (row_shr:n moves lane i - n into lane i; lanes with no source
+// keep the identity), then the four row results from lanes 15, 31, 47, 63.
+// Call with every lane active.
+__device__ inline int32_t wave_min(int32_t v) {
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x111, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x112, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x114, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x118, 0xf, 0xf, false));
+  const int32_t a = __builtin_amdgcn_readlane(v, 15), b = __builtin_amdgcn_readlane(v, 31);
+  const int32_t c = __builtin_amdgcn_readlane(v, 47), d = __builtin_amdgcn_readlane(v, 63);
+  return min(min(a, b), min(c, d));
+}
+
+__device__ inline int32_t wave_max(int32_t v) {
+  v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x111, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x112, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x114, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x118, 0xf, 0xf, false));
+  const int32_t a = __builtin_amdgcn_readlane(v, 15), b = __builtin_amdgcn_readlane(v, 31);
+  const int32_t c = __builtin_amdgcn_readlane(v, 47), d = __builtin_amdgcn_readlane(v, 63);
+  return max(max(a, b), max(c, d));
+}
+
+// Orders this wavefront's LDS accesses (a wave's LDS instructions execute in order).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Relative texel offset of index i from reference r in [-n/2, n/2) (repeat) or plain difference (clamp).
 __device__ inline int32_t rel_index(int32_t i, int32_t r, int32_t n, int wrap) {
   int32_t d = i - r;
   if (wrap == kWrapClamp) return d;
@@ -218,57 +254,52 @@ __device__ inline int32_t abs_index(int32_t r, int32_t d, int32_t n, int wrap) {
   return i;
 }
 
-// Wavefront min / max without the LDS pipe: inclusive row scans with DPP
-// row shifts (lanes outside the row contribute the identity), then the four
-// row results are combined from lanes 15, 31, 47 and 63.  Call with every
-// lane active.
-__device__ inline int32_t wave_min(int32_t v) {
-  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x111, 0xf, 0xf, false));  // row_shr:1
-  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x112, 0xf, 0xf, false));  // row_shr:2
-  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x114, 0xf, 0xf, false));  // row_shr:4
-  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x118, 0xf, 0xf, false));  // row_shr:8
-  const int32_t a = __builtin_amdgcn_readlane(v, 15), b = __builtin_amdgcn_readlane(v, 31);
-  const int32_t c = __builtin_amdgcn_readlane(v, 47), d = __builtin_amdgcn_readlane(v, 63);
-  return min(min(a, b), min(c, d));
+constexpr int kWaveWin = 256;     // texels in each wavefront's LDS gradient window
+constexpr bool kMergeX2 = true;   // third butterfly step (x +- 2) before the window
+
+// Value of v in lane (lane ^ 1), (lane ^ 2) or (lane ^ 4), with DPP (no LDS):
+// quad_perm [1,0,3,2], quad_perm [2,3,0,1], and row_shl:4 / row_shr:4 picked by lane bit 2.
+__device__ inline int32_t lane_xor1(int32_t v) { return __builtin_amdgcn_mov_dpp(v, 0xb1, 0xf, 0xf, false); }
+__device__ inline int32_t lane_xor2(int32_t v) { return __builtin_amdgcn_mov_dpp(v, 0x4e, 0xf, 0xf, false); }
+__device__ inline int32_t lane_xor4(int32_t v, bool bit2) {
+  const int32_t up = __builtin_amdgcn_mov_dpp(v, 0x104, 0xf, 0xf, false);    // row_shl:4 -> lane + 4
+  const int32_t down = __builtin_amdgcn_mov_dpp(v, 0x114, 0xf, 0xf, false);  // row_shr:4 -> lane - 4
+  return bit2 ? down : up;
 }
 
-__device__ inline int32_t wave_max(int32_t v) {
-  v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x111, 0xf, 0xf, false));
-  v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x112, 0xf, 0xf, false));
-  v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x114, 0xf, 0xf, false));
-  v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x118, 0xf, 0xf, false));
-  const int32_t a = __builtin_amdgcn_readlane(v, 15), b = __builtin_amdgcn_readlane(v, 31);
-  const int32_t c = __builtin_amdgcn_readlane(v, 47), d = __builtin_amdgcn_readlane(v, 63);
-  return max(max(a, b), max(c, d));
+// One butterfly step of merging contributions by base texel: lanes (lane, lane ^ 2^step)
+// holding the same key combine their 16 values in the lower lane; the upper lane drops out.
+template <int STEP>
+__device__ inline void merge_by_key(int32_t& key, float (&v)[16], int lane) {
+  const bool bit = (lane >> STEP) & 1;
+  auto x = [&](int32_t q) { return STEP == 0 ? lane_xor1(q) : STEP == 1 ? lane_xor2(q) : lane_xor4(q, bit); };
+  const int32_t other = x(key);
+  const bool same = key >= 0 && other == key;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const float ov = __int_as_float(x(__float_as_int(v[q])));
+    if (same && !bit) v[q] += ov;
+  }
+  if (same && bit) key = -1;
 }
 
-// Value of v in lane (lane ^ 1) / (lane ^ 2) of the same quad (DPP quad_perm).
-__device__ inline int32_t quad_xor1(int32_t v) { return __builtin_amdgcn_mov_dpp(v, 0xb1, 0xf, 0xf, false); }
-__device__ inline int32_t quad_xor2(int32_t v) { return __builtin_amdgcn_mov_dpp(v, 0x4e, 0xf, 0xf, false); }
-__device__ inline float quad_xor1(float v) { return __int_as_float(quad_xor1(__float_as_int(v))); }
-__device__ inline float quad_xor2(float v) { return __int_as_float(quad_xor2(__float_as_int(v))); }
 
-// Orders this wavefront's LDS accesses (issued in program order by one wave).
-__device__ inline void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-constexpr int kWaveWin = 256;   // texels in each wavefront's LDS gradient window (4 KB)
-
-// Backward: recompute the layers front to back (keeping c, a, T and the
-// footprint of each hit layer), form dL/d(RGB, A), then walk back to front:
+// Backward: recompute the layers front to back (keeping T and the footprint
+// of each hit layer), form dL/d(RGB, A), then walk back to front:
 //   dL/dc_l = g_rgb a_l T_l,  dL/da_l = T_l <g_rgb, c_l - S_l> + g_A T_l prod_{m>l}(1 - a_m),
 // S_l the colour blended behind layer l.  Division-free (a = 1 is fine).
 // Each of the 4 corner texels receives its bilinear weight times these.
 //
-// Scatter, per wavefront (16 x 4 pixels) and layer: a wave that hits the
-// layer reduces its footprints to a texel window (wrap-aware, relative to
-// the smallest hit texel) with shuffles, accumulates its 16 contributions per
-// pixel there with LDS float atomics, and flushes the window with global
-// float atomics, skipping untouched texels.  No block-wide barrier is
-// involved.  A footprint larger than the window uses direct global atomics.
+// Scatter, per wavefront (16 x 4 pixels) and layer: neighbouring pixels
+// mostly share their base texel (a texel spans several pixels when
+// magnified), so the lanes of each 4 x 2 pixel group that share a base
+// texel first sum their 16 contributions in registers (DPP butterfly steps:
+// x +- 1, y +- 1, x +- 2).  The survivors add into an LDS texel window
+// (wrap-aware, relative to the smallest base texel) with plain
+// read-modify-writes, one lane per cell and corner per round (owner words
+// elect it), and the window is flushed row by row with global float atomics
+// whose lanes cover consecutive floats.  A footprint larger than the window
+// uses direct global atomics.
 template <int KMAX>
 __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ views, int n_views,
                                                    const int32_t* __restrict__ tile_view, int64_t n_tiles,
@@ -279,7 +310,7 @@ __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ v
                                                    float4* __restrict__ out, double* __restrict__ sse, int wrap,
                                                    unsigned long long* __restrict__ status) {
 #pragma clang fp contract(fast)
-  __shared__ float win_all[4][kWaveWin * 4];
+  __shared__ __align__(16) float win_all[4][kWaveWin * 8];   // per wave: RGBA sums, then 4 owner planes
   __shared__ double sred[4];
   const TileCoord c = shade_tile_coord(views, n_views, tile_view, n_tiles);
   if (!c.live) return;  // uniform per block
@@ -298,7 +329,10 @@ __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ v
   uint64_t keys[KMAX];
 #pragma unroll
   for (int l = 0; l < KMAX; ++l) keys[l] = (l < k && c.valid) ? vrow[l * P] : kEmpty;
-  float cr[KMAX], cg[KMAX], cb[KMAX], ca[KMAX], Tl[KMAX], fxs[KMAX], fys[KMAX];
+  // Kept per hit layer for the backward walk: T in front of it and the footprint; the
+  // sample itself is re-read there (four texels, still cache resident), which keeps the
+  // register count, and so the number of resident wavefronts, up.
+  float Tl[KMAX], fxs[KMAX], fys[KMAX];
   int32_t ii[KMAX], jj[KMAX];   // packed (i1 << 16 | i0), (j1 << 16 | j0)
   uint32_t hitmask = 0;
   float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.0f;
@@ -311,7 +345,7 @@ __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ v
                        X.inv_h[l], wrap, f, status)) {
       const float4 s = bilinear(X.tex[l], X.w[l], f);
       hitmask |= 1u << l;
-      cr[l] = s.x; cg[l] = s.y; cb[l] = s.z; ca[l] = s.w; Tl[l] = T;
+      Tl[l] = T;
       fxs[l] = f.fx; fys[l] = f.fy;
       ii[l] = (f.i1 << 16) | f.i0;
       jj[l] = (f.j1 << 16) | f.j0;
@@ -342,106 +376,114 @@ __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ v
     if (l >= k) continue;  // uniform
     const bool hit = (hitmask >> l) & 1u;
     if (!__any(hit)) continue;  // uniform per wavefront
-    float d[4] = {0.f, 0.f, 0.f, 0.f};   // dL/d(r, g, b, a) of this layer's sample
-    float wq[4] = {0.f, 0.f, 0.f, 0.f};
-    int32_t i0 = 0, i1 = 0, j0 = 0, j1 = 0;
+    float v[16];
+    int32_t key = -1, i0 = 0, i1 = 0, j0 = 0, j1 = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = 0.0f;
     if (hit) {
-      const float a = ca[l], Tv = Tl[l];
-      const float aT = a * Tv;
-      d[0] = gr * aT; d[1] = gg * aT; d[2] = gb * aT;
-      d[3] = Tv * (gr * (cr[l] - Sr) + gg * (cg[l] - Sg) + gb * (cb[l] - Sb)) + gA * Tv * Pm;
-      Sr = a * cr[l] + (1.0f - a) * Sr;
-      Sg = a * cg[l] + (1.0f - a) * Sg;
-      Sb = a * cb[l] + (1.0f - a) * Sb;
-      Pm *= (1.0f - a);
-      const float fx = fxs[l], fy = fys[l], gx = 1.0f - fx, gy = 1.0f - fy;
-      wq[0] = gx * gy; wq[1] = fx * gy; wq[2] = gx * fy; wq[3] = fx * fy;
       i0 = ii[l] & 0xffff; i1 = ii[l] >> 16; j0 = jj[l] & 0xffff; j1 = jj[l] >> 16;
+      Foot f;
+      f.i0 = i0; f.i1 = i1; f.j0 = j0; f.j1 = j1; f.fx = fxs[l]; f.fy = fys[l];
+      const float4 smp = bilinear(X.tex[l], X.w[l], f);   // the same sample as the forward walk
+      const float a = smp.w, Tv = Tl[l];
+      const float aT = a * Tv;
+      float d[4];
+      d[0] = gr * aT; d[1] = gg * aT; d[2] = gb * aT;
+      d[3] = Tv * (gr * (smp.x - Sr) + gg * (smp.y - Sg) + gb * (smp.z - Sb)) + gA * Tv * Pm;
+      Sr = a * smp.x + (1.0f - a) * Sr;
+      Sg = a * smp.y + (1.0f - a) * Sg;
+      Sb = a * smp.z + (1.0f - a) * Sb;
+      Pm *= (1.0f - a);
+      const float fx = f.fx, fy = f.fy, gx = 1.0f - fx, gy = 1.0f - fy;
+      const float wq[4] = {gx * gy, fx * gy, gx * fy, fx * fy};
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) v[n * 4 + ch] = wq[n] * d[ch];
+      }
+      key = j0 * X.w[l] + i0;
     }
+    // all lanes take part in the exchanges (uniform control flow here)
+    merge_by_key<0>(key, v, lane);
+    merge_by_key<1>(key, v, lane);
+    if (kMergeX2) merge_by_key<2>(key, v, lane);
+    const bool live = key >= 0;
     float* G = X.grad[l];
     const int32_t Wt = X.w[l], Ht = X.h[l];
-    // window: relative to the smallest packed texel index among the wave's hits
-    const int32_t refp = wave_min(hit ? j0 * Wt + i0 : INT32_MAX);
+    // window relative to the smallest surviving base texel, wrap-aware; corners add +1
+    const int32_t refp = wave_min(live ? key : INT32_MAX);
     const int32_t rj = refp / Wt, ri = refp - rj * Wt;
     int32_t di0 = 0, di1 = 0, dj0 = 0, dj1 = 0;
-    if (hit) {
+    if (live) {
       di0 = rel_index(i0, ri, Wt, wrap); di1 = rel_index(i1, ri, Wt, wrap);
       dj0 = rel_index(j0, rj, Ht, wrap); dj1 = rel_index(j1, rj, Ht, wrap);
     }
-    const int32_t dmin_i = wave_min(hit ? min(di0, di1) : INT32_MAX);
-    const int32_t dmax_i = wave_max(hit ? max(di0, di1) : INT32_MIN);
-    const int32_t dmin_j = wave_min(hit ? min(dj0, dj1) : INT32_MAX);
-    const int32_t dmax_j = wave_max(hit ? max(dj0, dj1) : INT32_MIN);
+    const int32_t dmin_i = wave_min(live ? min(di0, di1) : INT32_MAX);
+    const int32_t dmax_i = wave_max(live ? max(di0, di1) : INT32_MIN);
+    const int32_t dmin_j = wave_min(live ? min(dj0, dj1) : INT32_MAX);
+    const int32_t dmax_j = wave_max(live ? max(dj0, dj1) : INT32_MIN);
     const int32_t ww = dmax_i - dmin_i + 1, wh = dmax_j - dmin_j + 1;
     if (ww * wh <= kWaveWin) {
-      // channel-major window: win[ch * kWaveWin + cell], so neighbouring cells sit in neighbouring banks
+      float4* wg = reinterpret_cast<float4*>(win);            // [cell] RGBA sums
+      int32_t* owner = reinterpret_cast<int32_t*>(win + kWaveWin * 4);   // [corner][cell]
       const int32_t ncell = ww * wh;
-      for (int e = lane; e < ncell; e += 64) {
+      for (int e = lane; e < ncell; e += 64) wg[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+      const int32_t x0 = di0 - dmin_i, x1 = di1 - dmin_i, y0 = dj0 - dmin_j, y1 = dj1 - dmin_j;
+      const int32_t cells[4] = {y0 * ww + x0, y0 * ww + x1, y1 * ww + x0, y1 * ww + x1};
+      // Owner election for the four corners at once (one owner word per corner and cell), then
+      // the four read-modify-writes in sequence: within one corner the owners' cells are
+      // distinct, and a wave's LDS instructions complete in order, so no atomics are needed.
+      // Lanes that lost an election retry in later rounds.
+      uint32_t pend = live ? 0xfu : 0u;
+      while (__any(pend != 0u)) {
 #pragma unroll
-        for (int ch = 0; ch < 4; ++ch) win[ch * kWaveWin + e] = 0.0f;
-      }
-      int32_t cell[4] = {-1, -1, -1, -1};
-      float val[4][4];
-      if (hit) {
-        const int32_t x0 = di0 - dmin_i, x1 = di1 - dmin_i, y0 = dj0 - dmin_j, y1 = dj1 - dmin_j;
-        cell[0] = y0 * ww + x0; cell[1] = y0 * ww + x1; cell[2] = y1 * ww + x0; cell[3] = y1 * ww + x1;
-      }
+        for (int n = 0; n < 4; ++n)
+          if ((pend >> n) & 1u) owner[n * kWaveWin + cells[n]] = lane;
+        wave_lds_sync();
+        uint32_t mine = 0;
 #pragma unroll
-      for (int n = 0; n < 4; ++n) {
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch) val[n][ch] = wq[n] * d[ch];
-      }
-      // Neighbouring pixels (x, x^1), then (x, x^2), often share a corner texel: the lower
-      // lane of a matching pair takes the partner's contribution and the upper lane drops its own.
-#pragma unroll
-      for (int step = 0; step < 2; ++step) {
-        const int bit = 1 << step;
-        const bool upper = (lane & bit) != 0;
+        for (int n = 0; n < 4; ++n)
+          if (((pend >> n) & 1u) && owner[n * kWaveWin + cells[n]] == lane) mine |= 1u << n;
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
-          const int32_t other = step == 0 ? quad_xor1(cell[n]) : quad_xor2(cell[n]);
-          const bool same = cell[n] >= 0 && other == cell[n];
-#pragma unroll
-          for (int ch = 0; ch < 4; ++ch) {
-            const float ov = step == 0 ? quad_xor1(val[n][ch]) : quad_xor2(val[n][ch]);
-            if (same && !upper) val[n][ch] += ov;
+          if ((mine >> n) & 1u) {
+            float4 acc = wg[cells[n]];
+            acc.x += v[n * 4 + 0]; acc.y += v[n * 4 + 1]; acc.z += v[n * 4 + 2]; acc.w += v[n * 4 + 3];
+            wg[cells[n]] = acc;
           }
-          if (same && upper) cell[n] = -1;
         }
+        pend &= ~mine;
+        wave_lds_sync();
       }
-      wave_lds_sync();
-#pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        if (cell[n] >= 0) {
-#pragma unroll
-          for (int ch = 0; ch < 4; ++ch) atomicAdd(&win[ch * kWaveWin + cell[n]], val[n][ch]);
-        }
-      }
-      wave_lds_sync();
-      for (int e = lane; e < ncell * 4; e += 64) {
-        const int32_t cl = e >> 2, ch = e & 3;
-        const float v = win[ch * kWaveWin + cl];
-        if (v != 0.0f) {
-          const int32_t y = cl / ww, x = cl - y * ww;
-          const int32_t ti = abs_index(ri, dmin_i + x, Wt, wrap), tj = abs_index(rj, dmin_j + y, Ht, wrap);
-          unsafeAtomicAdd(G + ((int64_t)tj * Wt + ti) * 4 + ch, v);
+      // flush row by row: consecutive lanes write consecutive floats of one texture row
+      const int32_t row = ww * 4;
+      for (int32_t y = 0; y < wh; ++y) {
+        const int32_t tj = abs_index(rj, dmin_j + y, Ht, wrap);
+        float* grow = G + (int64_t)tj * Wt * 4;
+        for (int e = lane; e < row; e += 64) {
+          const float val = win[(y * ww) * 4 + e];
+          if (val != 0.0f) {
+            const int32_t ti = abs_index(ri, dmin_i + (e >> 2), Wt, wrap);
+            unsafeAtomicAdd(grow + ti * 4 + (e & 3), val);
+          }
         }
       }
       wave_lds_sync();   // the window is reused by the next layer
-    } else if (hit) {
-      const int32_t q[4] = {j0 * Wt + i0, j0 * Wt + i1, j1 * Wt + i0, j1 * Wt + i1};
+    } else if (live) {
+      const int64_t q[4] = {((int64_t)j0 * Wt + i0) * 4, ((int64_t)j0 * Wt + i1) * 4,
+                            ((int64_t)j1 * Wt + i0) * 4, ((int64_t)j1 * Wt + i1) * 4};
 #pragma unroll
       for (int n = 0; n < 4; ++n) {
 #pragma unroll
-        for (int ch = 0; ch < 4; ++ch) unsafeAtomicAdd(G + (int64_t)q[n] * 4 + ch, wq[n] * d[ch]);
+        for (int ch = 0; ch < 4; ++ch) unsafeAtomicAdd(G + q[n] + ch, v[n * 4 + ch]);
       }
     }
   }
   if (sse) {
     // block reduction of the squared error, one atomic per block
-    double v = my_sse;
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if (lane == 0) sred[tid >> 6] = v;
+    double sv = my_sse;
+    for (int off = 32; off > 0; off >>= 1) sv += __shfl_xor(sv, off);
+    if (lane == 0) sred[tid >> 6] = sv;
     __syncthreads();
     if (tid == 0) unsafeAtomicAdd(sse, (sred[0] + sred[1]) + (sred[2] + sred[3]));
   }
