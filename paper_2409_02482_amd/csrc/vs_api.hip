@@ -124,7 +124,7 @@ vs_status build_textures(const vs_texture* tex, int32_t k, vs::TexTable& X) {
 
 int bin_slot(int bin) { return bin == 8 ? 0 : bin == 16 ? 1 : bin == 32 ? 2 : bin == 64 ? 3 : -1; }
 
-constexpr int kDefaultBin = 16;
+constexpr int kDefaultBin = 64;
 
 vs::WsLayout ws_layout(const vs::LayerTable& L, const vs_views* views, int bin, int64_t capacity = 0) {
   vs::WsLayout w;

@@ -267,22 +267,27 @@ __device__ inline int32_t lane_xor4(int32_t v, bool bit2) {
   return bit2 ? down : up;
 }
 
+// Value of v in lane (lane + 2^STEP) for the lower lane of each pair (the only
+// reader); lanes whose source falls outside their row read 0.
+template <int STEP>
+__device__ inline float from_upper(float v) {
+  constexpr int ctrl = STEP == 0 ? 0xb1 : STEP == 1 ? 0x4e : 0x104;
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xf, 0xf, true));
+}
+
 // One butterfly step of merging contributions by base texel: lanes (lane, lane ^ 2^step)
 // holding the same key combine their 16 values in the lower lane; the upper lane drops out.
+// The add is a fused multiply-add by 1 or 0 so that the lane exchange folds into it.
 template <int STEP>
 __device__ inline void merge_by_key(int32_t& key, float (&v)[16], int lane) {
   const bool bit = (lane >> STEP) & 1;
-  auto x = [&](int32_t q) { return STEP == 0 ? lane_xor1(q) : STEP == 1 ? lane_xor2(q) : lane_xor4(q, bit); };
-  const int32_t other = x(key);
+  const int32_t other = STEP == 0 ? lane_xor1(key) : STEP == 1 ? lane_xor2(key) : lane_xor4(key, bit);
   const bool same = key >= 0 && other == key;
+  const float take = (same && !bit) ? 1.0f : 0.0f;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const float ov = __int_as_float(x(__float_as_int(v[q])));
-    if (same && !bit) v[q] += ov;
-  }
+  for (int q = 0; q < 16; ++q) v[q] = __builtin_fmaf(from_upper<STEP>(v[q]), take, v[q]);
   if (same && bit) key = -1;
 }
-
 
 // Backward: recompute the layers front to back (keeping T and the footprint
 // of each hit layer), form dL/d(RGB, A), then walk back to front:

@@ -208,6 +208,44 @@ def test_ragged_gradient_matches_oracle(torch_cuda):
     assert grad_rel_err(got, want) <= GRAD_RTOL
 
 
+# texture sizes that exercise each scatter path of the adjoint: the LDS window (magnified
+# texels), degenerate widths and heights (corners that coincide or wrap onto themselves), and
+# the direct-atomic fallback (minified texels: a wavefront's footprint exceeds the window)
+_TEX_CASES = {
+    "window": ((64, 64), (48, 80), (64, 64)),
+    "degenerate": ((1, 1), (3, 2), (1, 5)),
+    "minified": ((1024, 1024), (2048, 256), (256, 2048)),
+}
+
+
+@pytest.mark.parametrize("wrap", [0, 1], ids=["repeat", "clamp"])
+@pytest.mark.parametrize("case", sorted(_TEX_CASES))
+def test_gradient_scatter_paths(torch_cuda, case, wrap):
+    torch = torch_cuda
+    base = small_mixed_scene(config=96, sizes=((96, 80), (37, 53), (64, 64)))
+    textures = [S.uniform_texture(96, l, w, h, opaque=(l == base.k - 1)) for l, (w, h) in enumerate(_TEX_CASES[case])]
+    sc = S.Scene(base.name, base.layers, textures, base.cameras)
+    say(f"[gpu] scatter paths: {case} wrap={wrap}")
+    P, layers, views, vis, ws, rgba, tex = gpu_render(sc, wrap=wrap)
+    gs = [S.upstream_grad(96, c, v) for v, c in enumerate(sc.cameras)]
+    flat = torch.from_numpy(np.concatenate([g.reshape(-1, 4) for g in gs])).cuda()
+    got = _gpu_backward(P, layers, views, vis, ws, tex, grad_rgba=flat, wrap=wrap)
+    want = [np.zeros(t.shape) for t in sc.textures]
+    for v, cam in enumerate(sc.cameras):
+        w = O.backward(sc.layers, sc.textures, cam, vis_numpy(views, vis, sc.k, v), grad_out=gs[v].astype(np.float64),
+                       wrap=wrap)
+        want = [a + b for a, b in zip(want, w)]
+    err = grad_rel_err(got, want)
+    say(f"[gpu] scatter paths: {case} wrap={wrap} grad rel err {err:.2e}")
+    assert err <= GRAD_RTOL
+    # per layer too, so that a small layer cannot hide behind a large one
+    for l in range(sc.k):
+        if np.abs(want[l]).max() == 0:
+            assert np.abs(got[l]).max() == 0, f"layer {l}"
+        else:
+            assert grad_rel_err([got[l]], [want[l]]) <= GRAD_RTOL, f"layer {l}"
+
+
 def test_autograd_function(torch_cuda):
     torch = torch_cuda
     import paper_2409_02482_amd as P
