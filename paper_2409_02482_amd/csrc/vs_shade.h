@@ -300,10 +300,9 @@ __device__ inline void merge_by_key(int32_t& key, float (&v)[16], int lane) {
 // magnified), so the lanes of each 4 x 2 pixel group that share a base
 // texel first sum their 16 contributions in registers (DPP butterfly steps:
 // x +- 1, y +- 1, x +- 2).  The survivors add into an LDS texel window
-// (wrap-aware, relative to the smallest base texel) with plain
-// read-modify-writes, one lane per cell and corner per round (owner words
-// elect it), and the window is flushed row by row with global float atomics
-// whose lanes cover consecutive floats.  A footprint larger than the window
+// (wrap-aware) with plain read-modify-writes, one lane per base texel and
+// round (an owner word per cell elects it), and the window is flushed with
+// global float atomics whose lanes cover consecutive floats.  A footprint larger than the window
 // uses direct global atomics.
 template <int KMAX>
 __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ views, int n_views,
@@ -406,6 +405,16 @@ __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ v
 #pragma unroll
         for (int ch = 0; ch < 4; ++ch) v[n * 4 + ch] = wq[n] * d[ch];
       }
+      // clamped at the last column or row, corners coincide: fold them onto the base texel's
+      // row or column (the window skips the folded corners; the direct path adds zeros)
+      if (i1 == i0) {
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) { v[ch] += v[4 + ch]; v[4 + ch] = 0.f; v[8 + ch] += v[12 + ch]; v[12 + ch] = 0.f; }
+      }
+      if (j1 == j0) {
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) { v[ch] += v[8 + ch]; v[8 + ch] = 0.f; v[4 + ch] += v[12 + ch]; v[12 + ch] = 0.f; }
+      }
       key = j0 * X.w[l] + i0;
     }
     // all lanes take part in the exchanges (uniform control flow here)
@@ -415,9 +424,10 @@ __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ v
     const bool live = key >= 0;
     float* G = X.grad[l];
     const int32_t Wt = X.w[l], Ht = X.h[l];
-    // window relative to the smallest surviving base texel, wrap-aware; corners add +1
-    const int32_t refp = wave_min(live ? key : INT32_MAX);
-    const int32_t rj = refp / Wt, ri = refp - rj * Wt;
+    // window relative to the base texel of the first surviving lane (one exists: the lower
+    // lane of every merged pair survives), wrap-aware; corners add +1
+    const int first = __builtin_ctzll(__ballot(live));
+    const int32_t ri = __builtin_amdgcn_readlane(i0, first), rj = __builtin_amdgcn_readlane(j0, first);
     int32_t di0 = 0, di1 = 0, dj0 = 0, dj1 = 0;
     if (live) {
       di0 = rel_index(i0, ri, Wt, wrap); di1 = rel_index(i1, ri, Wt, wrap);
@@ -429,48 +439,48 @@ __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ v
     const int32_t dmax_j = wave_max(live ? max(dj0, dj1) : INT32_MIN);
     const int32_t ww = dmax_i - dmin_i + 1, wh = dmax_j - dmin_j + 1;
     if (ww * wh <= kWaveWin) {
-      float4* wg = reinterpret_cast<float4*>(win);            // [cell] RGBA sums
-      int32_t* owner = reinterpret_cast<int32_t*>(win + kWaveWin * 4);   // [corner][cell]
+      float4* wg = reinterpret_cast<float4*>(win);                     // [cell] RGBA sums
+      int32_t* owner = reinterpret_cast<int32_t*>(win + kWaveWin * 4);  // [cell]
       const int32_t ncell = ww * wh;
       for (int e = lane; e < ncell; e += 64) wg[e] = make_float4(0.f, 0.f, 0.f, 0.f);
       const int32_t x0 = di0 - dmin_i, x1 = di1 - dmin_i, y0 = dj0 - dmin_j, y1 = dj1 - dmin_j;
       const int32_t cells[4] = {y0 * ww + x0, y0 * ww + x1, y1 * ww + x0, y1 * ww + x1};
-      // Owner election for the four corners at once (one owner word per corner and cell), then
-      // the four read-modify-writes in sequence: within one corner the owners' cells are
-      // distinct, and a wave's LDS instructions complete in order, so no atomics are needed.
-      // Lanes that lost an election retry in later rounds.
-      uint32_t pend = live ? 0xfu : 0u;
-      while (__any(pend != 0u)) {
-#pragma unroll
-        for (int n = 0; n < 4; ++n)
-          if ((pend >> n) & 1u) owner[n * kWaveWin + cells[n]] = lane;
+      // Corners that coincide (clamped at the last column or row) were folded onto the base
+      // texel's, so for each corner distinct base texels give distinct cells.  One owner word
+      // per base cell elects one lane per base texel and round; the winners then apply the four
+      // corners' read-modify-writes one corner at a time.  A wave's LDS instructions complete
+      // in order, so no atomics are needed; lanes that lost (equal base texel) retry.
+      const uint32_t skip = (i1 == i0 ? 0xau : 0u) | (j1 == j0 ? 0xcu : 0u);
+      bool pend = live;
+      while (__any(pend)) {
+        if (pend) owner[cells[0]] = lane;
         wave_lds_sync();
-        uint32_t mine = 0;
-#pragma unroll
-        for (int n = 0; n < 4; ++n)
-          if (((pend >> n) & 1u) && owner[n * kWaveWin + cells[n]] == lane) mine |= 1u << n;
+        const bool mine = pend && owner[cells[0]] == lane;
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
-          if ((mine >> n) & 1u) {
+          if (mine && !((skip >> n) & 1u)) {
             float4 acc = wg[cells[n]];
             acc.x += v[n * 4 + 0]; acc.y += v[n * 4 + 1]; acc.z += v[n * 4 + 2]; acc.w += v[n * 4 + 3];
             wg[cells[n]] = acc;
           }
+          __asm__ volatile("" ::: "memory");   // keep the corners' LDS accesses in program order
         }
-        pend &= ~mine;
-        wave_lds_sync();
+        pend = pend && !mine;
       }
-      // flush row by row: consecutive lanes write consecutive floats of one texture row
-      const int32_t row = ww * 4;
-      for (int32_t y = 0; y < wh; ++y) {
-        const int32_t tj = abs_index(rj, dmin_j + y, Ht, wrap);
-        float* grow = G + (int64_t)tj * Wt * 4;
-        for (int e = lane; e < row; e += 64) {
-          const float val = win[(y * ww) * 4 + e];
-          if (val != 0.0f) {
-            const int32_t ti = abs_index(ri, dmin_i + (e >> 2), Wt, wrap);
-            unsafeAtomicAdd(grow + ti * 4 + (e & 3), val);
-          }
+      wave_lds_sync();
+      // flush: consecutive lanes take consecutive floats of the window (row-major), so each
+      // atomic instruction covers whole texture row segments
+      const int32_t row = ww * 4, total = row * wh;
+      const float inv_row = 1.0f / (float)row;
+      for (int e = lane; e < total; e += 64) {
+        const float val = win[e];
+        if (val != 0.0f) {
+          int32_t y = (int32_t)((float)e * inv_row);
+          int32_t xe = e - y * row;
+          if (xe < 0) { --y; xe += row; } else if (xe >= row) { ++y; xe -= row; }
+          const int32_t tj = abs_index(rj, dmin_j + y, Ht, wrap);
+          const int32_t ti = abs_index(ri, dmin_i + (xe >> 2), Wt, wrap);
+          unsafeAtomicAdd(G + ((int64_t)tj * Wt + ti) * 4 + (xe & 3), val);
         }
       }
       wave_lds_sync();   // the window is reused by the next layer
