@@ -69,7 +69,7 @@ def counter_traffic(kernel: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(scene, n_threads, per_thread=1):
+def cpu_baseline(scene, n_threads, per_thread=3):
     """The oracle as it stands, views spread over threads (ctypes releases the GIL)."""
     import concurrent.futures as cf
 
