@@ -272,14 +272,15 @@ vs_status vs_raster_layers(const vs_mesh* layers, int32_t k, const vs_views* vie
                      bin_view, lay.n_tiles_bin, slot);
   hipLaunchKernelGGL(vs::k_fill_u32, dim3(fill_grid), dim3(256), 0, s, count, lay.n_bins, 0u);
   hipLaunchKernelGGL(vs::k_fill_u32, dim3(fill_grid), dim3(256), 0, s, cursor, 2 * lay.n_bins, 0u);
-  hipLaunchKernelGGL(vs::k_bin_count, dim3(grid_1d(ntri, 256), nv), dim3(256), 0, s, views->dev, L,
+  const unsigned bin_blocks = (unsigned)vs::bin_grid_blocks(ntri, nv);
+  hipLaunchKernelGGL(vs::k_bin_count, dim3(bin_blocks), dim3(256), 0, s, views->dev, nv, L,
                      (const vs::ProjVert*)proj, vpv, B, slot, count, spans, status);
   hipLaunchKernelGGL(vs::k_scan_local, dim3((unsigned)lay.n_partial), dim3(256), 0, s, (const uint32_t*)count,
                      offset, partial, lay.n_bins);
   hipLaunchKernelGGL(vs::k_scan_partials, dim3(1), dim3(1024), 0, s, partial, lay.n_partial);
   hipLaunchKernelGGL(vs::k_scan_add, dim3(grid_1d(lay.n_bins, 256)), dim3(256), 0, s, offset,
                      (const uint32_t*)partial, lay.n_bins);
-  hipLaunchKernelGGL(vs::k_bin_scatter, dim3(grid_1d(ntri, 256), nv), dim3(256), 0, s, views->dev, L, B, slot,
+  hipLaunchKernelGGL(vs::k_bin_scatter, dim3(bin_blocks), dim3(256), 0, s, views->dev, nv, L, B, slot,
                      (const uint64_t*)spans, (const uint32_t*)count, (const uint32_t*)offset, cursor, list,
                      lay.capacity);
   const unsigned nblk = (unsigned)((lay.n_bins + 7) / 8 * 8);

@@ -93,12 +93,24 @@ struct BinWork {
   int ntx;                  // tiles per row in this view
 };
 
-// Which (view, layer, triangle) this thread of a count/scatter launch handles
-// (grid.x over the triangles of all layers, grid.y = view).
-__device__ inline bool bin_thread(const LayerTable& L, int& v, int& l, int32_t& t, int64_t& g) {
-  g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  v = blockIdx.y;
+// Blocks of a count/scatter launch: per view, ceil(triangles of all layers / 256),
+// the total rounded up to a multiple of the XCD count.
+__host__ __device__ inline int64_t bin_grid_blocks(int64_t n_tri, int n_views) {
+  return ((n_tri + 255) / 256 * n_views + 7) / 8 * 8;
+}
+
+// Which (view, layer, triangle) this thread of a count/scatter launch handles.
+// Blocks are dealt round-robin to the 8 XCDs; the remap gives each XCD a
+// contiguous range of (view, triangle block)s, so that triangles sharing
+// vertices share that XCD's L2.
+__device__ inline bool bin_thread(const LayerTable& L, int n_views, int& v, int& l, int32_t& t, int64_t& g) {
   const int k = L.k;
+  const int64_t per_view = (L.tri_off[k] + 255) / 256;
+  const int64_t chunk = (int64_t)gridDim.x / 8;
+  const int64_t bid = ((int64_t)blockIdx.x % 8) * chunk + (int64_t)blockIdx.x / 8;
+  v = (int)(bid / per_view);
+  if (v >= n_views) return false;
+  g = (bid - (int64_t)v * per_view) * 256 + threadIdx.x;
   if (g >= L.tri_off[k]) return false;
   l = 0;
   while (l + 1 < k && L.tri_off[l + 1] <= g) ++l;
@@ -107,14 +119,14 @@ __device__ inline bool bin_thread(const LayerTable& L, int& v, int& l, int32_t& 
 }
 
 // Count triangles per bin and record each triangle's tile span.
-__global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ views, LayerTable L,
+__global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ views, int n_views, LayerTable L,
                                                    const ProjVert* __restrict__ proj, int64_t vpv, int B, int slot,
                                                    uint32_t* __restrict__ count, uint64_t* __restrict__ spans,
                                                    unsigned long long* __restrict__ status) {
   int v = 0, l = 0;
   int32_t t = 0;
   int64_t g = 0;
-  bool ok = bin_thread(L, v, l, t, g);
+  bool ok = bin_thread(L, n_views, v, l, t, g);
   const int k = L.k;
   BinWork w;
   uint64_t span = 0;
@@ -224,7 +236,8 @@ __global__ void __launch_bounds__(256) k_scan_add(uint32_t* __restrict__ out, co
 // head of a bin's list, the others from its tail.  A bin whose list would end
 // past the capacity is left unwritten; the raster of that bin then scans every
 // triangle of its layer instead (slow but exact) and the overflow is counted.
-__global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__ views, LayerTable L, int B, int slot,
+__global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__ views, int n_views, LayerTable L,
+                                                     int B, int slot,
                                                      const uint64_t* __restrict__ spans,
                                                      const uint32_t* __restrict__ count,
                                                      const uint32_t* __restrict__ offset,
@@ -233,7 +246,7 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__
   int v = 0, l = 0;
   int32_t t = 0;
   int64_t g = 0;
-  bool ok = bin_thread(L, v, l, t, g);
+  bool ok = bin_thread(L, n_views, v, l, t, g);
   const int k = L.k;
   uint64_t span = ok ? spans[(int64_t)v * L.tri_off[k] + g] : 0ull;
   ok = ok && (span & kSpanValid);
