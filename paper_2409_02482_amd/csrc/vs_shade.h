@@ -48,6 +48,11 @@ __device__ inline void split_coord(double x, int32_t n, double inv_n, int wrap, 
   i1 = i + 1 == n ? 0 : i + 1;
 }
 
+// The second texel index of a footprint from the first (as split_coord pairs them).
+__device__ inline int32_t next_index(int32_t i0, int32_t n, int wrap) {
+  return wrap == kWrapClamp ? (i0 + 1 < n ? i0 + 1 : n - 1) : (i0 + 1 == n ? 0 : i0 + 1);
+}
+
 __device__ inline float4 bilinear(const float4* __restrict__ tex, int32_t W, const Foot& f) {
 #pragma clang fp contract(fast)
   const float4 t00 = tex[f.j0 * W + f.i0];
@@ -304,8 +309,10 @@ __device__ inline void merge_by_key(int32_t& key, float (&v)[16], int lane) {
 // round (an owner word per cell elects it), and the window is flushed with
 // global float atomics whose lanes cover consecutive floats.  A footprint larger than the window
 // uses direct global atomics.
+// The scatter is latency bound, so up to 8 layers the register budget is held
+// to 6 wavefronts per SIMD (a few bytes of spill cost less than the lost waves).
 template <int KMAX>
-__global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ views, int n_views,
+__global__ void __launch_bounds__(256, KMAX <= 8 ? 6 : 3) k_shade_bwd(const vs_view* __restrict__ views, int n_views,
                                                    const int32_t* __restrict__ tile_view, int64_t n_tiles,
                                                    LayerTable L, TexTable X, const ProjVert* __restrict__ proj,
                                                    int64_t vpv, const uint64_t* __restrict__ vis,
@@ -314,7 +321,7 @@ __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ v
                                                    float4* __restrict__ out, double* __restrict__ sse, int wrap,
                                                    unsigned long long* __restrict__ status) {
 #pragma clang fp contract(fast)
-  __shared__ __align__(16) float win_all[4][kWaveWin * 8];   // per wave: RGBA sums, then 4 owner planes
+  __shared__ __align__(16) float win_all[4][kWaveWin * 5];   // per wave: RGBA sums, then the owner words
   __shared__ double sred[4];
   const TileCoord c = shade_tile_coord(views, n_views, tile_view, n_tiles);
   if (!c.live) return;  // uniform per block
@@ -337,7 +344,7 @@ __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ v
   // sample itself is re-read there (four texels, still cache resident), which keeps the
   // register count, and so the number of resident wavefronts, up.
   float Tl[KMAX], fxs[KMAX], fys[KMAX];
-  int32_t ii[KMAX], jj[KMAX];   // packed (i1 << 16 | i0), (j1 << 16 | j0)
+  int32_t ij[KMAX];   // packed (j0 << 16 | i0); i1, j1 follow from them
   uint32_t hitmask = 0;
   float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.0f;
 #pragma unroll
@@ -351,8 +358,7 @@ __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ v
       hitmask |= 1u << l;
       Tl[l] = T;
       fxs[l] = f.fx; fys[l] = f.fy;
-      ii[l] = (f.i1 << 16) | f.i0;
-      jj[l] = (f.j1 << 16) | f.j0;
+      ij[l] = (f.j0 << 16) | f.i0;
       const float ta = T * s.w;
       Cr += ta * s.x; Cg += ta * s.y; Cb += ta * s.z;
       T *= (1.0f - s.w);
@@ -385,7 +391,8 @@ __global__ void __launch_bounds__(256) k_shade_bwd(const vs_view* __restrict__ v
 #pragma unroll
     for (int q = 0; q < 16; ++q) v[q] = 0.0f;
     if (hit) {
-      i0 = ii[l] & 0xffff; i1 = ii[l] >> 16; j0 = jj[l] & 0xffff; j1 = jj[l] >> 16;
+      i0 = ij[l] & 0xffff; j0 = ij[l] >> 16;
+      i1 = next_index(i0, X.w[l], wrap); j1 = next_index(j0, X.h[l], wrap);
       Foot f;
       f.i0 = i0; f.i1 = i1; f.j0 = j0; f.j1 = j1; f.fx = fxs[l]; f.fy = fys[l];
       const float4 smp = bilinear(X.tex[l], X.w[l], f);   // the same sample as the forward walk
