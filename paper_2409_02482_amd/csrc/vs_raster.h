@@ -301,8 +301,10 @@ __global__ void __launch_bounds__(256) k_tile_view_slot(const vs_view* __restric
 
 // One block per bin.  Small triangles (bounding box <= 64 px on each side and
 // few candidate pixels) are walked by one lane with exact int32 edge values;
-// larger ones are queued in LDS and tested by the whole block, each thread
-// owning B*B/256 pixels, with exact FP64 edge values.
+// larger ones are tested by the lane's whole wavefront, each lane owning
+// B*B/64 pixels, with exact FP64 edge values.  Wavefronts work independently
+// on the LDS tile (64-bit atomic minimum), so the tile is the block's only LDS
+// and, at B = 64, five blocks fit a CU.
 template <int B>
 __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
     const vs_view* __restrict__ views, const int32_t* __restrict__ bin_view, int64_t n_tiles, LayerTable L,
@@ -310,8 +312,6 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
     const uint32_t* __restrict__ offset, const int32_t* __restrict__ list, uint64_t capacity,
     unsigned long long* __restrict__ vis, unsigned long long* __restrict__ status, int count_frags) {
   __shared__ unsigned long long tile[B * B];
-  __shared__ int32_t queue[kRasterThreads];
-  __shared__ int nq;
   const int k = L.k;
   const int64_t n_bins = n_tiles * k;
   // XCD-contiguous remap of the block index
@@ -328,9 +328,8 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
   const int ty = (int)(tl / ntx), tx = (int)(tl - (int64_t)ty * ntx);
   const int x0 = tx * B, y0 = ty * B;
   const int x1 = min(x0 + B, W) - 1, y1 = min(y0 + B, H) - 1;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   for (int p = tid; p < B * B; p += kRasterThreads) tile[p] = kEmpty;
-  if (tid == 0) nq = 0;
   const ProjVert* P = proj + (int64_t)v * vpv + L.vert_off[l];
   const int32_t* tri = L.tri[l];
   const int32_t nvert = L.n_vert[l];
@@ -342,6 +341,7 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
   __syncthreads();
   for (uint32_t c0 = 0; c0 < n; c0 += kRasterThreads) {
     const uint32_t c = c0 + tid;
+    int32_t big = -1;   // a triangle for the whole wavefront
     if (c < n) {
       const int32_t t = overflow ? (int32_t)c : lst[c];
       TriSetup T;
@@ -380,19 +380,17 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
               er0 += ay0; er1 += ay1; er2 += ay2;
             }
           } else {
-            queue[atomicAdd(&nq, 1)] = t;
+            big = t;
           }
         }
       }
     }
-    __syncthreads();
-    const int nbig = nq;
-    for (int q = 0; q < nbig; ++q) {
-      const int32_t t = queue[q];
+    for (uint64_t bm = __ballot(big >= 0); bm; bm &= bm - 1) {
+      const int32_t t = __builtin_amdgcn_readlane(big, __builtin_ctzll(bm));
       TriSetup T;
       setup_triangle(tri + 3 * (int64_t)t, nvert, P, T);
       const unsigned long long lbkey = depth_lower_key(T, (uint32_t)t);
-      for (int p = tid; p < B * B; p += kRasterThreads) {
+      for (int p = lane; p < B * B; p += 64) {
         const int i = x0 + (p % B), j = y0 + (p / B);
         if (i > x1 || j > y1) continue;
         double E[3];
@@ -404,10 +402,8 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
         }
       }
     }
-    __syncthreads();
-    if (tid == 0) nq = 0;
-    __syncthreads();
   }
+  __syncthreads();
   // coalesced store of the finished tile
   unsigned long long* plane = vis + (int64_t)k * V.pix_offset + (int64_t)l * W * H;
   for (int p = tid; p < B * B; p += kRasterThreads) {
