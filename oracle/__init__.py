@@ -47,6 +47,10 @@ class _Layer(ctypes.Structure):
                 ("tex", ctypes.c_void_p), ("tex_w", ctypes.c_int32), ("tex_h", ctypes.c_int32)]
 
 
+class _ShLayer(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -65,10 +69,14 @@ def lib():
         L.vso_shade.argtypes = [i32, vp, vp, vp, ctypes.c_int, vp, vp, vp]
         L.vso_backward.argtypes = [i32, vp, vp, vp, ctypes.c_int, vp, vp, vp]
         L.vso_fd.argtypes = [i32, vp, vp, vp, ctypes.c_int, vp, vp, i32, vp, dbl, vp]
-        for f in ("vso_raster", "vso_coverage", "vso_shade", "vso_backward", "vso_fd"):
+        L.vso_sh_basis.argtypes = [vp, vp]
+        L.vso_sh_layer_bytes.restype = ctypes.c_int
+        L.vso_shade_sh.argtypes = [i32, vp, vp, vp, vp, ctypes.c_int, dbl, dbl, ctypes.c_int, ctypes.c_int, vp]
+        for f in ("vso_raster", "vso_coverage", "vso_shade", "vso_backward", "vso_fd", "vso_shade_sh"):
             getattr(L, f).restype = ctypes.c_int
         assert L.vso_camera_bytes() == ctypes.sizeof(_Cam), "camera layout mismatch"
         assert L.vso_layer_bytes() == ctypes.sizeof(_Layer), "layer layout mismatch"
+        assert L.vso_sh_layer_bytes() == ctypes.sizeof(_ShLayer), "SH layer layout mismatch"
         _lib = L
     return _lib
 
@@ -204,3 +212,32 @@ def render(meshes, textures, cam, wrap: int = 0, mode: str = "bbox"):
     """Visibility [k, H, W] and image [H, W, 4] of one view."""
     vis = raster_layers(meshes, cam, mode)
     return vis, shade(meshes, textures, cam, vis, wrap)
+
+
+# ----------------------------------------------------------------------------- baked SH appearance
+def sh_basis(d) -> np.ndarray:
+    """Real orthonormal spherical harmonics (degree <= 3, 16 values) of unit directions d [..., 3]."""
+    d = np.ascontiguousarray(d, np.float64).reshape(-1, 3)
+    out = np.empty((d.shape[0], 16), np.float64)
+    for n in range(d.shape[0]):
+        lib().vso_sh_basis(_ptr(d[n]), out[n].ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def shade_sh(meshes, sh_textures, cam, vis, degree: int = 3, vmin: float = -15.0, vmax: float = 15.0,
+             wrap: int = 0, view_alpha: bool = True):
+    """[H, W, 4] f64 RGBA of one view under the baked SH appearance.
+
+    sh_textures[l] has .data (uint8, packed levels), .width and .height (level 0)."""
+    k = len(meshes)
+    L = _Layers(meshes)
+    keep = [np.ascontiguousarray(t.data, np.uint8) for t in sh_textures]
+    S = (_ShLayer * k)(*[_ShLayer(a.ctypes.data, t.width, t.height) for a, t in zip(keep, sh_textures)])
+    cc = _cam(cam)
+    vis = np.ascontiguousarray(vis, np.uint64)
+    out = np.empty((cam.height, cam.width, 4), np.float64)
+    err = lib().vso_shade_sh(k, L.ptr(), S, ctypes.byref(cc), _ptr(vis), int(degree), float(vmin), float(vmax),
+                             int(wrap), int(bool(view_alpha)), _ptr(out))
+    if err:
+        raise RuntimeError("oracle: visibility key names an invalid triangle" if err == 1 else "oracle: bad degree")
+    return out

@@ -22,7 +22,8 @@
 //
 // Parity pins: see tests/test_oracle_pins.py (watertightness, analytic
 // spheres, ray-plane barycentrics, affine textures, closed-form blending,
-// exact finite differences, brute == bbox, edge cases).
+// exact finite differences, brute == bbox, edge cases) and
+// tests/test_oracle_sh_pins.py (the baked SH appearance).
 
 #include <cmath>
 #include <cstdint>
@@ -235,14 +236,13 @@ struct Hit {
 // Shade one (pixel, layer) slot: rebuild the triangle from the key, compute
 // perspective-correct barycentrics lambda_q = E_q w_q / s, interpolate UV and
 // fetch the texture bilinearly.
-Hit shade_slot(const Layer& L, int32_t layer, const std::vector<Vtx>& vt, uint64_t key, int64_t i, int64_t j,
-               int wrap, const Perturb* pt, int* err) {
-  Hit h;
+// The UV part of shade_slot: barycentrics and interpolated UV of the slot.
+bool slot_uv(const Layer& L, const std::vector<Vtx>& vt, uint64_t key, int64_t i, int64_t j, Hit& h, int* err) {
   h.hit = false;
-  if (key == kEmpty) return h;
+  if (key == kEmpty) return false;
   const int32_t t = (int32_t)(key & 0xffffffffu);
   Tri T;
-  if (t < 0 || t >= L.n_tri || setup_triangle(L, vt, t, T) != kTriOk) { *err = 1; return h; }
+  if (t < 0 || t >= L.n_tri || setup_triangle(L, vt, t, T) != kTriOk) { *err = 1; return false; }
   int64_t E[3];
   edge_values(T, i, j, E);
   const double s = ((double)E[0] * T.w[0] + (double)E[1] * T.w[1]) + (double)E[2] * T.w[2];
@@ -254,6 +254,13 @@ Hit shade_slot(const Layer& L, int32_t layer, const std::vector<Vtx>& vt, uint64
     h.u += h.lam[q] * (double)L.uv[2 * T.vid[q]];
     h.v += h.lam[q] * (double)L.uv[2 * T.vid[q] + 1];
   }
+  return true;
+}
+
+Hit shade_slot(const Layer& L, int32_t layer, const std::vector<Vtx>& vt, uint64_t key, int64_t i, int64_t j,
+               int wrap, const Perturb* pt, int* err) {
+  Hit h;
+  if (!slot_uv(L, vt, key, i, j, h, err)) return h;
   h.f = footprint(h.u, h.v, L.tex_w, L.tex_h, wrap);
   for (int ch = 0; ch < 4; ++ch) {
     double acc = 0.0;
@@ -283,6 +290,122 @@ void blend_pixel(int k, const Hit* hits, double out[4]) {
 }
 
 Cam to_cam(const void* p) { Cam c; std::memcpy(&c, p, sizeof(Cam)); return c; }
+
+// ---------------------------------------------------------------- baked SH appearance
+// The paper's baked representation (Sec. 4.3): per shell, spherical-harmonic
+// coefficients of RGBA up to degree 3, (deg+1)^2 per channel, stored as 8-bit
+// values that decode linearly to [vmin, vmax] ("Squeezing and Quantization",
+// [-15, 15] in the paper).  Degree l is stored at the base resolution halved
+// l times ("Mixed Resolutions": base colour at the highest resolution, the top
+// degree at the lowest).  Each coefficient is read bilinearly from the four
+// surrounding texel centres of its own level, each texel decoded first (the
+// texel-centre predictions are interpolated, Sec. 4.3 and Fig. 5); the
+// coefficients are then decoded with the view direction into RGBA.
+// Readings where the paper is silent:
+//   * the SH basis is the real, orthonormal one, index l^2 + l + m, with no
+//     Condon-Shortley phase in the real form (Y_1^{-1}, Y_1^0, Y_1^1 are
+//     proportional to y, z, x);
+//   * the decoded sum passes through a sigmoid to give RGBA in (0, 1) (the
+//     representation's values are unbounded before squeezing, and alpha must
+//     lie in [0, 1], Sec. 4.1);
+//   * v is the unit world-space direction of the pixel-centre ray, from the
+//     camera through the pixel; n is the hit triangle's unit world-space face
+//     normal; the grazing-angle weight 2 sigmoid(10 |v.n|) - 1 of Sec. 4.2
+//     ("Transparency Attenuation") multiplies alpha when enabled;
+//   * level l has max(1, W >> l) x max(1, H >> l) texels; bytes are stored
+//     level after level, texel-major, the 2l+1 coefficients of a texel
+//     adjacent, each as R, G, B, A.
+struct ShLayer { const uint8_t* data; int32_t width, height; };
+
+void sh_basis(const double d[3], double Y[16]) {
+  const double x = d[0], y = d[1], z = d[2];
+  const double pi = 3.14159265358979323846;
+  Y[0] = 0.5 * std::sqrt(1.0 / pi);
+  const double c1 = std::sqrt(3.0 / (4.0 * pi));
+  Y[1] = c1 * y;
+  Y[2] = c1 * z;
+  Y[3] = c1 * x;
+  const double c2a = 0.5 * std::sqrt(15.0 / pi), c2b = 0.25 * std::sqrt(5.0 / pi), c2c = 0.25 * std::sqrt(15.0 / pi);
+  Y[4] = c2a * x * y;
+  Y[5] = c2a * y * z;
+  Y[6] = c2b * (3.0 * z * z - 1.0);
+  Y[7] = c2a * x * z;
+  Y[8] = c2c * (x * x - y * y);
+  const double c3a = 0.25 * std::sqrt(35.0 / (2.0 * pi)), c3b = 0.5 * std::sqrt(105.0 / pi);
+  const double c3c = 0.25 * std::sqrt(21.0 / (2.0 * pi)), c3d = 0.25 * std::sqrt(7.0 / pi);
+  const double c3e = 0.25 * std::sqrt(105.0 / pi);
+  Y[9] = c3a * y * (3.0 * x * x - y * y);
+  Y[10] = c3b * x * y * z;
+  Y[11] = c3c * y * (5.0 * z * z - 1.0);
+  Y[12] = c3d * z * (5.0 * z * z - 3.0);
+  Y[13] = c3c * x * (5.0 * z * z - 1.0);
+  Y[14] = c3e * z * (x * x - y * y);
+  Y[15] = c3a * x * (x * x - 3.0 * y * y);
+}
+
+int64_t level_dim(int32_t n, int l) { return std::max<int64_t>(1, (int64_t)n >> l); }
+
+size_t level_offset(const ShLayer& S, int l) {
+  size_t off = 0;
+  for (int m = 0; m < l; ++m) off += (size_t)level_dim(S.width, m) * level_dim(S.height, m) * (2 * m + 1) * 4;
+  return off;
+}
+
+// Unit world-space direction of the ray through the centre of pixel (i, j).
+void pixel_ray(const Cam& c, int64_t i, int64_t j, double d[3]) {
+  const double xc = ((double)i + 0.5 - c.cx) / c.fx, yc = ((double)j + 0.5 - c.cy) / c.fy, zc = 1.0;
+  for (int q = 0; q < 3; ++q) d[q] = (c.R[q] * xc + c.R[3 + q] * yc) + c.R[6 + q] * zc;  // R^T (xc, yc, zc)
+  const double n = std::sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+  for (int q = 0; q < 3; ++q) d[q] /= n;
+}
+
+// Unit face normal of triangle t from its world-space corners (zero if degenerate).
+void face_normal(const Layer& L, int32_t t, double n[3]) {
+  const int32_t* id = L.tri + 3 * (size_t)t;
+  double p[3][3];
+  for (int q = 0; q < 3; ++q)
+    for (int e = 0; e < 3; ++e) p[q][e] = (double)L.xyz[3 * (size_t)id[q] + e];
+  const double e1[3] = {p[1][0] - p[0][0], p[1][1] - p[0][1], p[1][2] - p[0][2]};
+  const double e2[3] = {p[2][0] - p[0][0], p[2][1] - p[0][1], p[2][2] - p[0][2]};
+  n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+  n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+  n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+  const double len = std::sqrt((n[0] * n[0] + n[1] * n[1]) + n[2] * n[2]);
+  for (int q = 0; q < 3; ++q) n[q] = len > 0.0 ? n[q] / len : 0.0;
+}
+
+double sigmoid(double x) { return 1.0 / (1.0 + std::exp(-x)); }
+
+// RGBA of one hit slot under the baked SH appearance.
+void sh_rgba(const Layer& L, const ShLayer& S, const Hit& h, int32_t t, const double d[3], int degree, double vmin,
+             double vmax, int wrap, int view_alpha, double rgba[4]) {
+  double Y[16];
+  sh_basis(d, Y);
+  double raw[4] = {0, 0, 0, 0};
+  for (int l = 0; l <= degree; ++l) {
+    const int64_t Wl = level_dim(S.width, l), Hl = level_dim(S.height, l);
+    const Footprint f = footprint(h.u, h.v, (int32_t)Wl, (int32_t)Hl, wrap);
+    const uint8_t* base = S.data + level_offset(S, l);
+    for (int m = 0; m < 2 * l + 1; ++m)
+      for (int ch = 0; ch < 4; ++ch) {
+        double sh = 0.0;
+        for (int dj = 0; dj < 2; ++dj)
+          for (int di = 0; di < 2; ++di) {
+            const size_t texel = (size_t)f.j[dj] * Wl + (size_t)f.i[di];
+            const double q = (double)base[(texel * (2 * l + 1) + m) * 4 + ch];
+            sh += corner_weight(f, dj, di) * (vmin + (vmax - vmin) * q / 255.0);
+          }
+        raw[ch] += sh * Y[l * l + m];
+      }
+  }
+  for (int ch = 0; ch < 4; ++ch) rgba[ch] = sigmoid(raw[ch]);
+  if (view_alpha) {
+    double n[3];
+    face_normal(L, t, n);
+    const double vn = std::fabs((d[0] * n[0] + d[1] * n[1]) + d[2] * n[2]);
+    rgba[3] *= 2.0 * sigmoid(10.0 * vn) - 1.0;
+  }
+}
 
 }  // namespace
 
@@ -515,6 +638,40 @@ int vso_fd(int32_t k, const void* layers, const void* cam, const uint64_t* vis, 
     }
     out[e] = acc / (2.0 * h);
   }
+  return err;
+}
+
+// Real spherical harmonics (degree <= 3) of a unit direction, for the pins.
+void vso_sh_basis(const double* d, double* Y) { sh_basis(d, Y); }
+
+int vso_sh_layer_bytes() { return (int)sizeof(ShLayer); }
+
+// Baked SH appearance, forward: [H][W][4] f64 RGBA of one view (RGB over
+// black, A = 1 - T), the layers blended as in vso_shade.
+int vso_shade_sh(int32_t k, const void* layers, const void* sh_layers, const void* cam, const uint64_t* vis,
+                 int degree, double vmin, double vmax, int wrap, int view_alpha, double* out) {
+  const Layer* L = (const Layer*)layers;
+  const ShLayer* S = (const ShLayer*)sh_layers;
+  const Cam c = to_cam(cam);
+  if (degree < 0 || degree > 3) return 2;
+  std::vector<std::vector<Vtx>> vt(k);
+  for (int l = 0; l < k; ++l) project_all(L[l], c, vt[l]);
+  const size_t P = (size_t)c.width * c.height;
+  std::vector<Hit> hits(k);
+  int err = 0;
+  for (int64_t j = 0; j < c.height; ++j)
+    for (int64_t i = 0; i < c.width; ++i) {
+      const size_t p = (size_t)j * c.width + i;
+      double d[3];
+      pixel_ray(c, i, j, d);
+      for (int l = 0; l < k; ++l) {
+        const uint64_t key = vis[(size_t)l * P + p];
+        if (slot_uv(L[l], vt[l], key, i, j, hits[l], &err))
+          sh_rgba(L[l], S[l], hits[l], (int32_t)(key & 0xffffffffu), d, degree, vmin, vmax, wrap, view_alpha,
+                  hits[l].rgba);
+      }
+      blend_pixel(k, hits.data(), out + 4 * p);
+    }
   return err;
 }
 

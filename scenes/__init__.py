@@ -40,6 +40,7 @@ P_TARGET = 4
 P_GT_TEXTURE = 5
 P_UPSTREAM = 6
 P_PICK = 7
+P_SH = 8
 
 Z_NEAR = 0.01
 
@@ -359,6 +360,62 @@ def constant_texture(w: int, h: int, rgba: Sequence[float]) -> np.ndarray:
     t = np.empty((h, w, 4), np.float32)
     t[...] = np.asarray(rgba, np.float32)
     return t
+
+
+@dataclasses.dataclass
+class ShTexture:
+    """A shell's baked spherical-harmonic texture: 8-bit coefficients, packed by level.
+
+    Degree l (0..degree) is stored at level l of max(1, width >> l) x max(1, height >> l)
+    texels, levels one after another, each texel-major [H_l][W_l][2l+1][4] (the 2l+1
+    coefficients of a texel adjacent, each as R, G, B, A bytes)."""
+    data: np.ndarray      # uint8 [total bytes]
+    width: int            # level-0 size
+    height: int
+    degree: int
+
+
+def sh_level_dims(width: int, height: int, level: int) -> Tuple[int, int]:
+    return max(1, width >> level), max(1, height >> level)
+
+
+def sh_pack(levels: Sequence[np.ndarray], width: int, height: int) -> ShTexture:
+    """Pack per-level arrays [H_l][W_l][2l+1][4] (uint8) into an ShTexture."""
+    for l, a in enumerate(levels):
+        w, h = sh_level_dims(width, height, l)
+        assert a.shape == (h, w, 2 * l + 1, 4) and a.dtype == np.uint8, (l, a.shape)
+    data = np.concatenate([np.ascontiguousarray(a).reshape(-1) for a in levels])
+    return ShTexture(data, width, height, len(levels) - 1)
+
+
+def sh_unpack(t: ShTexture) -> List[np.ndarray]:
+    out, off = [], 0
+    for l in range(t.degree + 1):
+        w, h = sh_level_dims(t.width, t.height, l)
+        n = h * w * (2 * l + 1) * 4
+        out.append(t.data[off:off + n].reshape(h, w, 2 * l + 1, 4))
+        off += n
+    return out
+
+
+def sh_texture(config: int, layer: int, width: int, height: int, degree: int = 3, opaque: bool = False) -> ShTexture:
+    """Seeded 8-bit SH coefficients, i.i.d. per texel (the hardest case for filtering).
+
+    With the decoding range [-15, 15]: degree-0 RGB bytes in [68, 187] (the DC term alone
+    gives colours sigmoid([-2, 2])), degree-0 alpha bytes in [105, 187] (255 if opaque), and
+    every higher-degree byte in [115, 140] (coefficients within +-1.5)."""
+    rng = np.random.default_rng([config, P_SH, layer])
+    levels = []
+    for l in range(degree + 1):
+        w, h = sh_level_dims(width, height, l)
+        if l == 0:
+            a = np.empty((h, w, 1, 4), np.uint8)
+            a[..., :3] = rng.integers(68, 188, (h, w, 1, 3), dtype=np.uint8)
+            a[..., 3] = 255 if opaque else rng.integers(105, 188, (h, w, 1), dtype=np.uint8)
+        else:
+            a = rng.integers(115, 141, (h, w, 2 * l + 1, 4), dtype=np.uint8)
+        levels.append(a)
+    return sh_pack(levels, width, height)
 
 
 def uniform_targets(config: int, cams: Sequence[Camera]) -> List[np.ndarray]:
