@@ -93,6 +93,104 @@ def cpu_baseline(scene, n_threads, per_thread=3):
                       f"{per_thread} views per thread on {n_threads} threads, {dt:.1f} s wall"}
 
 
+SH_METRIC = ("shaded px·layers/s fwd, baked SH degree 3 (k=7, 1024², 64 views, 8-bit 2048² mixed-resolution "
+             "textures); % HBM peak")
+
+
+def sh_cpu_baseline(scene, sh, n_threads, per_thread=2):
+    """The oracle's baked-SH forward (raster + shade) on a bounded sample of views, one per thread."""
+    import concurrent.futures as cf
+
+    import oracle as O
+    cams = scene.cameras[:n_threads * per_thread]
+
+    def one(v):
+        cam = scene.cameras[v]
+        vis = O.raster_layers(scene.layers, cam)
+        O.shade_sh(scene.layers, sh, cam, vis)
+        return int((vis != np.uint64(0xFFFFFFFFFFFFFFFF)).sum())
+
+    O.build(force=False)
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(n_threads) as ex:
+        covered = sum(ex.map(one, range(len(cams))))
+    dt = time.perf_counter() - t0
+    return {"value": covered / dt, "unit": "px*layers/s", "cores": n_threads, "kind": "oracle",
+            "sample": f"{len(cams)} of the {len(scene.cameras)} views (full size, k={scene.k}), raster + baked SH "
+                      f"shading, {per_thread} view(s) per thread on {n_threads} threads, {dt:.1f} s wall"}
+
+
+def run_sh(args):
+    """Forward rendering of the baked representation: raster + vs_render_sh per step."""
+    import torch
+
+    import paper_2409_02482_amd as P
+    import scenes as S
+    log("[bench] building scene (baked SH textures)")
+    scene = S.make_config(6, n_views=args.views, resolution=(args.res, args.res), with_targets=False)
+    k, nv, dev = scene.k, len(scene.cameras), "cuda"
+    sh = [S.sh_texture(60, l, 2048, 2048, degree=3, opaque=(l == k - 1)) for l in range(k)]
+    layers = P.Layers(scene.layers, dev)
+    views = P.Views(scene.cameras, dev)
+    sh_dev = [(torch.from_numpy(t.data).to(dev), t.width, t.height) for t in sh]
+    out = torch.empty(views.total_pixels, 4, dtype=torch.float32, device=dev)
+    vis = torch.empty(k * views.total_pixels, dtype=torch.int64, device=dev)
+    ws = P.alloc_workspace(layers, views, args.bin, dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        P.raster(layers, views, vis, ws, bin=args.bin)
+        if ev is not None:
+            ev[1].record(stream)
+        P.render_sh(layers, sh_dev, views, vis, ws, degree=3, out=out)
+        if ev is not None:
+            ev[2].record(stream)
+
+    log("[bench] warmup")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    covered = int((vis != -1).sum().item())
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for st in range(args.steps):
+        step(evs[st])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    phase = np.array([[evs[st][i].elapsed_time(evs[st][i + 1]) for i in range(2)] for st in range(args.steps)])
+    ms_phase = phase.mean(0)
+    ms_wall = wall / args.steps * 1e3
+    P_v = views.total_pixels / nv
+    G = sum(12 * m.n_vert + 8 * m.n_vert + 12 * m.n_tri for m in scene.layers)
+    tex_bytes = sum(int(t.data.nbytes) for t in sh)
+    bm = {"raster": 8 * k * views.total_pixels + G * nv,
+          # keys, image, every coefficient byte once (all texels are seen by the 64 ring views), geometry
+          "shade_sh": 8 * k * views.total_pixels + 16 * views.total_pixels + tex_bytes + G}
+    names = ["raster", "shade_sh"]
+    dom = int(np.argmax(ms_phase))
+    achieved = bm[names[dom]] / (ms_phase[dom] * 1e-3) / 1e9
+    res = {
+        "metric": SH_METRIC, "value": covered / (ms_wall * 1e-3), "unit": "px*layers/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_wall, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"k={k} displaced shells ({scene.layers[0].n_tri:,} tris/layer), {nv} ring views at "
+                               f"{args.res}x{args.res}, SH degree 3 in 8 bits, levels 2048^2..256^2, raster + "
+                               "baked SH shading", "views": nv, "k": k, "pixels": views.total_pixels,
+                   "covered_px_layers": covered, "bin": args.bin, "sh_texture_bytes": tex_bytes},
+        "phases_ms": {n: float(m) for n, m in zip(names, ms_phase)},
+        "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(names[dom])},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        n = max(1, min(args.cpu_threads, os.cpu_count() or 1, nv))
+        res["cpu_baseline"] = sh_cpu_baseline(scene, sh, n)
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,8 +202,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=8)
     ap.add_argument("--unfused", action="store_true", help="separate forward shading pass before the adjoint")
-    ap.add_argument("--workload", default="metric", choices=["metric", "cfg4"],
-                    help="metric: k=7, 64 views at 1024^2; cfg4: k=9, 299,208 tris/layer, 64 mixed-size views")
+    ap.add_argument("--workload", default="metric", choices=["metric", "cfg4", "sh"],
+                    help="metric: k=7, 64 views at 1024^2; cfg4: k=9, 299,208 tris/layer, 64 mixed-size views; "
+                         "sh: the metric scene rendered forward with baked 8-bit SH textures (degree 3, 2048^2 base)")
     ap.add_argument("--graph", action="store_true", help="replay the step from a captured HIP graph")
     ap.add_argument("--autotune", action="store_true", help="pick the raster bin size with vs_autotune")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -115,6 +214,9 @@ def main():
         print("bench.py: this build measures one GPU only; --gpus must be 1 (views would shard across GPUs, "
               "with one all-reduce of the texture gradients per step)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "sh":
+        return run_sh(args)
 
     import torch
 

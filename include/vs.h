@@ -217,6 +217,54 @@ vs_status vs_render_backward(const vs_mesh* layers, const vs_texture* tex, int32
                              float* const* grad_tex, float* out_rgba, double* sse, const vs_shade_opts* opts,
                              void* stream);
 
+/* ---- baked view-dependent appearance (Sec. 4.3 "Texturing Meshes", "Mixed
+ *      Resolutions", "Squeezing and Quantization", "Baking Textures"; Sec. 4.2
+ *      "Transparency Attenuation") ---- */
+
+/* One shell's baked spherical-harmonic texture (device memory, 8-bit).
+ * With SH degree D (vs_sh_opts.degree, 0..3) a texel carries (D+1)^2
+ * coefficients per RGBA channel.  The coefficients of degree l live at level
+ * l, of max(1, width >> l) x max(1, height >> l) texels: the base colour at
+ * full resolution, each higher degree at half the previous one.  Levels
+ * follow each other from level 0; level l is texel-major,
+ * [H_l][W_l][2l+1][4] bytes: the 2l+1 coefficients (m = -l..l) of a texel are
+ * adjacent, each as R, G, B, A bytes.  Byte q decodes to
+ * vmin + (vmax - vmin) q / 255.  Size: sum_{l<=D} W_l H_l (2l+1) 4 bytes,
+ * 4-byte aligned. */
+typedef struct vs_sh_texture {
+  const uint8_t* data;
+  int32_t width, height;   /* level-0 size, 1..VS_MAX_TEX_DIM */
+} vs_sh_texture;
+
+/* Options of vs_render_sh.
+ * vmin, vmax: decoding range of the 8-bit coefficients (the paper uses -15, 15).
+ * eps_T, wrap: as in vs_shade_opts.
+ * degree:     0..3, the same for every layer.
+ * view_alpha: 1 multiplies each layer's alpha by 2 sigmoid(10 |v.n|) - 1
+ *             (v the pixel's unit view ray, n the hit triangle's unit
+ *             world-space face normal); 0 keeps the decoded alpha. */
+typedef struct vs_sh_opts {
+  float vmin, vmax;
+  float eps_T;
+  int32_t wrap;
+  int32_t degree;
+  int32_t view_alpha;
+} vs_sh_opts;
+
+/* Shade and blend with baked SH textures (forward).
+ * For each hit layer, every coefficient is read bilinearly at the slot's UV
+ * from the four surrounding texel centres of its level (texels decoded
+ * first), the layer's RGBA is sigmoid(sum_i sh_i Y_i(v)) with Y_i the real,
+ * orthonormal spherical harmonics (index l^2 + l + m, Y_1^{-1}, Y_1^0, Y_1^1
+ * proportional to y, z, x: no Condon-Shortley phase) of v, the unit
+ * world-space direction from the camera through the pixel centre, and the
+ * layers are blended as in vs_render.
+ * tex: host array [k] of device textures.  vis, ws, out_rgba and stream as in
+ * vs_render.  opts must not be NULL. */
+vs_status vs_render_sh(const vs_mesh* layers, const vs_sh_texture* tex, int32_t k, const vs_views* views,
+                       const uint64_t* vis, const void* ws, size_t ws_bytes, float* out_rgba,
+                       const vs_sh_opts* opts, void* stream);
+
 /* Copy the status block (VS_STAT_COUNT int64 counters) to host memory.
  * Synchronises the stream. */
 vs_status vs_read_status(const void* ws, size_t ws_bytes, int64_t* out, void* stream);

@@ -6,7 +6,7 @@ hand-written HIP kernels behind a C ABI (include/vs.h).
 """
 from ._lib import LIB_PATH, VsError, load  # noqa: F401
 from .binding import (Graph, Layers, Renderer, Views, adam_step, alloc_workspace, autotune, raster,  # noqa: F401
-                     read_status, render, render_backward, workspace_bytes)
+                     read_status, render, render_backward, render_sh, workspace_bytes)
 
-__all__ = ["Layers", "Views", "Renderer", "raster", "render", "render_backward", "read_status",
+__all__ = ["Layers", "Views", "Renderer", "raster", "render", "render_backward", "render_sh", "read_status",
            "workspace_bytes", "alloc_workspace", "autotune", "adam_step", "Graph", "load", "VsError", "LIB_PATH"]

@@ -57,6 +57,15 @@ class VsShadeOpts(ctypes.Structure):
     _fields_ = [("eps_T", c_f32), ("wrap", c_i32), ("target", c_vp), ("loss_scale", c_f32), ("reserved", c_i32)]
 
 
+class VsShTexture(ctypes.Structure):
+    _fields_ = [("data", c_vp), ("width", c_i32), ("height", c_i32)]
+
+
+class VsShOpts(ctypes.Structure):
+    _fields_ = [("vmin", c_f32), ("vmax", c_f32), ("eps_T", c_f32), ("wrap", c_i32), ("degree", c_i32),
+                ("view_alpha", c_i32)]
+
+
 # name -> (restype, argtypes); every symbol declared in include/vs.h
 SIGNATURES = {
     "vs_version": (ctypes.c_char_p, []),
@@ -66,6 +75,7 @@ SIGNATURES = {
     "vs_raster_workspace_bytes": (c_sz, [c_vp, c_i32, c_vp, c_vp]),
     "vs_raster_layers": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp, c_vp]),
     "vs_render": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp, c_vp, c_vp]),
+    "vs_render_sh": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp, c_vp, c_vp]),
     "vs_render_backward": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "vs_read_status": (c_i32, [c_vp, c_sz, c_vp, c_vp]),
     "vs_autotune": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp, ctypes.c_char_p, c_vp]),

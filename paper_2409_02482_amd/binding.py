@@ -160,6 +160,30 @@ def render(layers: Layers, textures, views: Views, vis: torch.Tensor, ws: torch.
     return out
 
 
+def sh_textures_struct(sh_textures: Sequence) -> ctypes.Array:
+    """sh_textures[l] = (data, width, height): data a contiguous uint8 device tensor of packed levels."""
+    arr = (C.VsShTexture * len(sh_textures))()
+    for l, (data, w, h) in enumerate(sh_textures):
+        _dev(data, torch.uint8, f"SH texture {l}")
+        arr[l] = C.VsShTexture(data.data_ptr(), int(w), int(h))
+    return arr
+
+
+def render_sh(layers: Layers, sh_textures, views: Views, vis: torch.Tensor, ws: torch.Tensor, degree: int = 3,
+              vmin: float = -15.0, vmax: float = 15.0, view_alpha: bool = True, out: Optional[torch.Tensor] = None,
+              eps_T: float = 0.0, wrap: int = 0, stream=None) -> torch.Tensor:
+    """vs_render_sh: [sum_v H_v W_v, 4] RGBA from baked 8-bit SH textures (A = 1 - transmittance)."""
+    if out is None:
+        out = torch.empty(views.total_pixels, 4, dtype=torch.float32, device=vis.device)
+    _dev(out, torch.float32, "out")
+    tex = sh_textures_struct(sh_textures)
+    opts = C.VsShOpts(float(vmin), float(vmax), float(eps_T), int(wrap), int(degree), int(bool(view_alpha)))
+    C.check(C.load().vs_render_sh(ctypes.addressof(layers.c), ctypes.addressof(tex), layers.k, ctypes.byref(views.c),
+                                  vis.data_ptr(), ws.data_ptr(), ws.numel(), out.data_ptr(), ctypes.byref(opts),
+                                  _stream(stream)), "vs_render_sh")
+    return out
+
+
 def render_backward(layers: Layers, textures, views: Views, vis: torch.Tensor, ws: torch.Tensor,
                     grad_rgba: Optional[torch.Tensor] = None, grad_tex: Optional[List[torch.Tensor]] = None,
                     target: Optional[torch.Tensor] = None, loss_scale: float = 1.0,

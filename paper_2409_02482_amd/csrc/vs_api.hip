@@ -16,6 +16,7 @@
 #include "vs_common.h"
 #include "vs_raster.h"
 #include "vs_shade.h"
+#include "vs_sh.h"
 #include "vs_fit.h"
 
 namespace {
@@ -327,6 +328,73 @@ vs_status vs_render(const vs_mesh* layers, const vs_texture* tex, int32_t k, con
                      views->n_views, tile_view, tiles, L, X, proj, L.vert_off[k], vis, (float4*)out_rgba, eps, wrap,
                      status);
   if ((st = check_launch("vs_render"))) return st;
+  return ok();
+}
+
+vs_status vs_render_sh(const vs_mesh* layers, const vs_sh_texture* tex, int32_t k, const vs_views* views,
+                       const uint64_t* vis, const void* ws, size_t ws_bytes, float* out_rgba,
+                       const vs_sh_opts* opts, void* stream) {
+  vs::LayerTable L;
+  vs_status st = build_layers(layers, k, L);
+  if (st) return st;
+  if ((st = check_views(views))) return st;
+  if (!vis || !out_rgba) return fail(VS_ERR_ARG, "vis/out_rgba: null");
+  if (!opts) return fail(VS_ERR_ARG, "vs_render_sh: opts must not be NULL");
+  if (!tex) return fail(VS_ERR_ARG, "SH textures: null");
+  const int deg = opts->degree;
+  if (deg < 0 || deg > 3) return fail(VS_ERR_UNSUPPORTED, "SH degree %d outside 0..3", deg);
+  if (opts->wrap != 0 && opts->wrap != 1) return fail(VS_ERR_UNSUPPORTED, "wrap = %d", opts->wrap);
+  if (opts->view_alpha != 0 && opts->view_alpha != 1) return fail(VS_ERR_ARG, "view_alpha must be 0 or 1");
+  if (!(opts->eps_T >= 0.0f && opts->eps_T < 1.0f)) return fail(VS_ERR_ARG, "eps_T must be in [0, 1)");
+  if (!(std::isfinite(opts->vmin) && std::isfinite(opts->vmax) && opts->vmin < opts->vmax))
+    return fail(VS_ERR_ARG, "need finite vmin < vmax");
+  vs::ShTable S;
+  std::memset(&S, 0, sizeof(S));
+  for (int l = 0; l < k; ++l) {
+    const vs_sh_texture& t = tex[l];
+    if (!t.data) return fail(VS_ERR_ARG, "SH texture %d: null", l);
+    if ((uintptr_t)t.data % 4) return fail(VS_ERR_ARG, "SH texture %d: data not 4-byte aligned", l);
+    if (t.width < 1 || t.height < 1 || t.width > VS_MAX_TEX_DIM || t.height > VS_MAX_TEX_DIM)
+      return fail(VS_ERR_SIZE, "SH texture %d: size %dx%d outside 1..%d", l, t.width, t.height, VS_MAX_TEX_DIM);
+    S.data[l] = t.data;
+    int64_t off = 0;
+    for (int d = 0; d < vs::kShLevels; ++d) {
+      const int32_t w = std::max(1, t.width >> d), h = std::max(1, t.height >> d);
+      S.w[l][d] = w;
+      S.h[l][d] = h;
+      S.off[l][d] = off;
+      S.inv_w[l][d] = 1.0 / w;
+      S.inv_h[l][d] = 1.0 / h;
+      off += (int64_t)w * h * (2 * d + 1) * 4;
+    }
+  }
+  const vs::WsLayout lay = ws_layout(L, views, 0);
+  if ((st = check_ws(ws, ws_bytes, lay.proj + (size_t)views->n_views * L.vert_off[k] * sizeof(vs::ProjVert))))
+    return st;
+  vs::ShParams prm;
+  prm.mid = 0.5f * (opts->vmin + opts->vmax);
+  prm.scale = (opts->vmax - opts->vmin) / 255.0f;
+  prm.eps_T = opts->eps_T;
+  prm.wrap = opts->wrap;
+  prm.view_alpha = opts->view_alpha;
+  const char* base = (const char*)ws;
+  auto* status = (unsigned long long*)(base + lay.status);
+  const auto* proj = (const vs::ProjVert*)(base + lay.proj);
+  const auto* tile_view = (const int32_t*)(base + lay.tile_view);
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t tiles = total_tiles(views, vs::kShadeTileSlot);
+  auto launch = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)vs::shade_grid_blocks(tiles)), dim3(256), 0, s, views->dev,
+                       views->n_views, tile_view, tiles, L, S, proj, L.vert_off[k], vis, (float4*)out_rgba, prm,
+                       status);
+  };
+  switch (deg) {
+    case 0: launch(vs::k_shade_sh<0>); break;
+    case 1: launch(vs::k_shade_sh<1>); break;
+    case 2: launch(vs::k_shade_sh<2>); break;
+    default: launch(vs::k_shade_sh<3>); break;
+  }
+  if ((st = check_launch("vs_render_sh"))) return st;
   return ok();
 }
 

@@ -71,15 +71,14 @@ __device__ inline float4 bilinear(const float4* __restrict__ tex, int32_t W, con
 
 struct Tri3 { int32_t a, b, c; };
 
-// Rebuild the triangle a key names and compute its UV footprint at the pixel
-// centre (px, py) (1/256 px units).  Barycentrics are perspective-correct:
+// Rebuild the triangle a key names and interpolate its UV at the pixel centre
+// (px, py) (1/256 px units).  Barycentrics are perspective-correct:
 // lambda_q = E_q w_q / sum_r E_r w_r, which does not depend on the winding,
 // so no orientation normalisation is needed here.  Returns false (and counts
 // a bad key) if the key names no valid triangle.
-__device__ inline bool slot_footprint(const int32_t* __restrict__ tri, int32_t n_tri, int32_t n_vert,
-                                      const ProjVert* __restrict__ P, const float2* __restrict__ uv, uint64_t key,
-                                      double px, double py, int32_t W, int32_t H, double invW, double invH, int wrap,
-                                      Foot& f, unsigned long long* status) {
+__device__ inline bool slot_uv(const int32_t* __restrict__ tri, int32_t n_tri, int32_t n_vert,
+                               const ProjVert* __restrict__ P, const float2* __restrict__ uv, uint64_t key,
+                               double px, double py, double& u, double& v, unsigned long long* status) {
 #pragma clang fp contract(fast)
   const uint32_t t = (uint32_t)(key & 0xffffffffu);
   if (t >= (uint32_t)n_tri) {
@@ -105,8 +104,18 @@ __device__ inline bool slot_footprint(const int32_t* __restrict__ tri, int32_t n
   r = r * (2.0 - s * r);
   r = r * (2.0 - s * r);
   const double la = q0 * r, lb = q1 * r, lc = q2 * r;
-  const double u = la * (double)ua.x + lb * (double)ub.x + lc * (double)uc.x;
-  const double v = la * (double)ua.y + lb * (double)ub.y + lc * (double)uc.y;
+  u = la * (double)ua.x + lb * (double)ub.x + lc * (double)uc.x;
+  v = la * (double)ua.y + lb * (double)ub.y + lc * (double)uc.y;
+  return true;
+}
+
+// The slot's bilinear footprint in a W x H texture.
+__device__ inline bool slot_footprint(const int32_t* __restrict__ tri, int32_t n_tri, int32_t n_vert,
+                                      const ProjVert* __restrict__ P, const float2* __restrict__ uv, uint64_t key,
+                                      double px, double py, int32_t W, int32_t H, double invW, double invH, int wrap,
+                                      Foot& f, unsigned long long* status) {
+  double u, v;
+  if (!slot_uv(tri, n_tri, n_vert, P, uv, key, px, py, u, v, status)) return false;
   split_coord(u * (double)W - 0.5, W, invW, wrap, f.i0, f.i1, f.fx);
   split_coord(v * (double)H - 0.5, H, invH, wrap, f.j0, f.j1, f.fy);
   return true;

@@ -42,10 +42,11 @@ def test_exports_every_declared_symbol(C):
 def test_struct_layouts_match_c(C, tmp_path):
     prog = tmp_path / "sz.c"
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "vs.h"\nint main(void){'
-                    'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(vs_mesh), sizeof(vs_texture),'
-                    'sizeof(vs_camera), sizeof(vs_view), sizeof(vs_views), sizeof(vs_raster_opts),'
+                    'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(vs_mesh),'
+                    'sizeof(vs_texture), sizeof(vs_camera), sizeof(vs_view), sizeof(vs_views), sizeof(vs_raster_opts),'
                     'sizeof(vs_shade_opts), offsetof(vs_view, pix_offset), offsetof(vs_shade_opts, target),'
-                    'offsetof(vs_raster_opts, list_capacity));'
+                    'offsetof(vs_raster_opts, list_capacity), sizeof(vs_sh_texture), sizeof(vs_sh_opts),'
+                    'offsetof(vs_sh_opts, view_alpha));'
                     'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
@@ -53,7 +54,8 @@ def test_struct_layouts_match_c(C, tmp_path):
     want = [ctypes.sizeof(C.VsMesh), ctypes.sizeof(C.VsTexture), ctypes.sizeof(C.VsCamera),
             ctypes.sizeof(C.VsView), ctypes.sizeof(C.VsViews), ctypes.sizeof(C.VsRasterOpts),
             ctypes.sizeof(C.VsShadeOpts), C.VsView.pix_offset.offset, C.VsShadeOpts.target.offset,
-            C.VsRasterOpts.list_capacity.offset]
+            C.VsRasterOpts.list_capacity.offset, ctypes.sizeof(C.VsShTexture), ctypes.sizeof(C.VsShOpts),
+            C.VsShOpts.view_alpha.offset]
     assert got == want
 
 
@@ -160,6 +162,29 @@ def test_render_validation_without_gpu(C):
     # neither grad_rgba nor a target
     assert L.vs_render_backward(ctypes.addressof(meshes), ctypes.addressof(tex), 2, ctypes.byref(views), 0x5000,
                                 0x100000, need, None, ctypes.addressof(gp), None, None, None, None) == C.VS_ERR_ARG
+
+
+def test_render_sh_validation_without_gpu(C):
+    L = C.load()
+    host, views, meshes, _ = _fake_call_args(C)
+    need = L.vs_raster_workspace_bytes(ctypes.addressof(meshes), 2, ctypes.byref(views), None)
+    tex = (C.VsShTexture * 2)(*[C.VsShTexture(0x4000, 16, 8) for _ in range(2)])
+
+    def call(opts, t=tex):
+        return L.vs_render_sh(ctypes.addressof(meshes), ctypes.addressof(t), 2, ctypes.byref(views), 0x5000,
+                              0x100000, need, 0x6000, None if opts is None else ctypes.byref(opts), None)
+
+    assert call(None) == C.VS_ERR_ARG
+    assert call(C.VsShOpts(-15.0, 15.0, 0.0, 0, 4, 1)) == C.VS_ERR_UNSUPPORTED      # degree 4
+    assert call(C.VsShOpts(-15.0, 15.0, 0.0, 2, 3, 1)) == C.VS_ERR_UNSUPPORTED      # wrap 2
+    assert call(C.VsShOpts(15.0, -15.0, 0.0, 0, 3, 1)) == C.VS_ERR_ARG              # vmin >= vmax
+    assert call(C.VsShOpts(-15.0, 15.0, 0.0, 0, 3, 2)) == C.VS_ERR_ARG              # view_alpha 2
+    tex[1].data = 0x4002
+    assert call(C.VsShOpts(-15.0, 15.0, 0.0, 0, 3, 1)) == C.VS_ERR_ARG              # misaligned bytes
+    tex[1].data = 0x4000
+    tex[0].height = 0
+    assert call(C.VsShOpts(-15.0, 15.0, 0.0, 0, 3, 1)) == C.VS_ERR_SIZE
+    assert b"SH texture 0" in L.vs_last_error()
 
 
 def test_status_strings(C):
