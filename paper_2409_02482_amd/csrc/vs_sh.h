@@ -85,8 +85,10 @@ __device__ inline float bil_byte(uint32_t q00, uint32_t q01, uint32_t q10, uint3
 //   raw_c = mid * sum_i Y_i + scale * sum_i Y_i (b_i,c - 127.5),
 // b the interpolated byte.  The bytes of a texel's coefficients of one degree
 // are adjacent, so a corner costs 2l+1 consecutive words.
+// At degree 3 the register budget is held to 4 wavefronts per SIMD (a few
+// bytes of spill cost less than the lost latency hiding).
 template <int DEG>
-__global__ void __launch_bounds__(256) k_shade_sh(const vs_view* __restrict__ views, int n_views,
+__global__ void __launch_bounds__(256, DEG == 3 ? 4 : 1) k_shade_sh(const vs_view* __restrict__ views, int n_views,
                                                   const int32_t* __restrict__ tile_view, int64_t n_tiles,
                                                   LayerTable L, ShTable S, const ProjVert* __restrict__ proj,
                                                   int64_t vpv, const uint64_t* __restrict__ vis,
