@@ -67,8 +67,8 @@ def lib():
         L.vso_raster.argtypes = [vp, vp, ctypes.c_int, vp, vp]
         L.vso_coverage.argtypes = [vp, vp, vp, vp]
         L.vso_shade.argtypes = [i32, vp, vp, vp, ctypes.c_int, vp, vp, vp]
-        L.vso_backward.argtypes = [i32, vp, vp, vp, ctypes.c_int, vp, vp, vp]
-        L.vso_fd.argtypes = [i32, vp, vp, vp, ctypes.c_int, vp, vp, i32, vp, dbl, vp]
+        L.vso_backward.argtypes = [i32, vp, vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, vp]
+        L.vso_fd.argtypes = [i32, vp, vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, i32, vp, dbl, vp]
         L.vso_sh_basis.argtypes = [vp, vp]
         L.vso_sh_layer_bytes.restype = ctypes.c_int
         L.vso_shade_sh.argtypes = [i32, vp, vp, vp, vp, ctypes.c_int, dbl, dbl, ctypes.c_int, ctypes.c_int, vp]
@@ -174,8 +174,14 @@ def shade(meshes, textures, cam, vis, wrap: int = 0, debug: bool = False):
     return (out, lam, uvo) if debug else out
 
 
-def backward(meshes, textures, cam, vis, grad_out=None, target=None, wrap: int = 0) -> List[np.ndarray]:
-    """Analytic texture gradient (f64, one array per layer) of one view."""
+_LOSSES = {"l2": 0, "l1": 1}
+
+
+def backward(meshes, textures, cam, vis, grad_out=None, target=None, wrap: int = 0, loss: str = "l2") -> List[np.ndarray]:
+    """Analytic texture gradient (f64, one array per layer) of one view.
+
+    With a target the loss is sum_p ||RGB_p - target_p||^2 (loss="l2") or sum_p |RGB_p - target_p|_1
+    (loss="l1"); otherwise sum_p <grad_out_p, out_p>."""
     k = len(meshes)
     L = _Layers(meshes, textures)
     cc = _cam(cam)
@@ -184,14 +190,14 @@ def backward(meshes, textures, cam, vis, grad_out=None, target=None, wrap: int =
     gp = (ctypes.c_void_p * k)(*[g.ctypes.data for g in grads])
     go = None if grad_out is None else np.ascontiguousarray(grad_out, np.float64)
     tg = None if target is None else np.ascontiguousarray(target, np.float32)
-    err = lib().vso_backward(k, L.ptr(), ctypes.byref(cc), _ptr(vis), wrap, _ptr(go), _ptr(tg), gp)
+    err = lib().vso_backward(k, L.ptr(), ctypes.byref(cc), _ptr(vis), wrap, _ptr(go), _ptr(tg), _LOSSES[loss], gp)
     if err:
         raise RuntimeError("oracle: visibility key names an invalid triangle")
     return grads
 
 
 def finite_diff(meshes, textures, cam, vis, entries, h: float = 1e-3, grad_out=None, target=None,
-                wrap: int = 0) -> np.ndarray:
+                wrap: int = 0, loss: str = "l2") -> np.ndarray:
     """Central FD (FP64) of the loss w.r.t. texel scalars entries[n] = (layer, j, i, ch)."""
     k = len(meshes)
     L = _Layers(meshes, textures)
@@ -201,8 +207,8 @@ def finite_diff(meshes, textures, cam, vis, entries, h: float = 1e-3, grad_out=N
     out = np.empty(ent.shape[0], np.float64)
     go = None if grad_out is None else np.ascontiguousarray(grad_out, np.float64)
     tg = None if target is None else np.ascontiguousarray(target, np.float32)
-    err = lib().vso_fd(k, L.ptr(), ctypes.byref(cc), _ptr(vis), wrap, _ptr(go), _ptr(tg), ent.shape[0], _ptr(ent),
-                       float(h), _ptr(out))
+    err = lib().vso_fd(k, L.ptr(), ctypes.byref(cc), _ptr(vis), wrap, _ptr(go), _ptr(tg), _LOSSES[loss], ent.shape[0],
+                       _ptr(ent), float(h), _ptr(out))
     if err:
         raise RuntimeError("oracle: visibility key names an invalid triangle")
     return out
@@ -241,3 +247,13 @@ def shade_sh(meshes, sh_textures, cam, vis, degree: int = 3, vmin: float = -15.0
     if err:
         raise RuntimeError("oracle: visibility key names an invalid triangle" if err == 1 else "oracle: bad degree")
     return out
+
+
+# ----------------------------------------------------------------------------- squeezing and quantisation
+def squeeze_quantize(theta, levels: int = 255) -> np.ndarray:
+    """Texture from logits (Sec. 4.3 "Squeezing and Quantization"): q(sigmoid(theta)),
+    q(x) = round(levels x) / levels with ties to even, decided in FP64; levels = 0: no quantisation."""
+    s = 1.0 / (1.0 + np.exp(-np.asarray(theta, np.float64)))
+    if levels:
+        s = np.rint(levels * s) / levels
+    return s.astype(np.float32)

@@ -529,7 +529,7 @@ int vso_shade(int32_t k, const void* layers, const void* cam, const uint64_t* vi
 // with S_l the colour blended behind layer l; both follow from differentiating
 // the blend above.  Each corner texel q receives its bilinear weight times these.
 int vso_backward(int32_t k, const void* layers, const void* cam, const uint64_t* vis, int wrap,
-                 const double* grad_out, const float* target, double* const* grad_tex) {
+                 const double* grad_out, const float* target, int loss, double* const* grad_tex) {
   const Layer* L = (const Layer*)layers;
   const Cam c = to_cam(cam);
   std::vector<std::vector<Vtx>> vt(k);
@@ -552,7 +552,11 @@ int vso_backward(int32_t k, const void* layers, const void* cam, const uint64_t*
       }
       double g[4];
       if (target) {
-        for (int ch = 0; ch < 3; ++ch) g[ch] = 2.0 * (C[ch] - (double)target[4 * p + ch]);
+        // L2: d/dC (C - t)^2 = 2 (C - t);  L1 (Sec. 4.3): d/dC |C - t| = sign(C - t), 0 at a tie
+        for (int ch = 0; ch < 3; ++ch) {
+          const double d = C[ch] - (double)target[4 * p + ch];
+          g[ch] = loss == 1 ? (double)((d > 0.0) - (d < 0.0)) : 2.0 * d;
+        }
         g[3] = 0.0;
       } else {
         for (int ch = 0; ch < 4; ++ch) g[ch] = grad_out[4 * p + ch];
@@ -586,11 +590,12 @@ int vso_backward(int32_t k, const void* layers, const void* cam, const uint64_t*
 // Central finite differences of the loss with respect to single texel scalars,
 // straight from the forward model (no adjoint involved).  entries [n][4] =
 // (layer, row j, column i, channel).  Loss: if target is non-null, the RGB L2
-// loss; otherwise sum_p <g_p, out_p> with g = grad_out.  Only pixels whose
+// loss (loss = 0) or L1 loss (loss = 1); otherwise sum_p <g_p, out_p> with
+// g = grad_out.  Only pixels whose
 // footprint on that layer contains the texel can change, so only they are
 // re-evaluated: out[e] = (L(+h) - L(-h)) / (2h).
 int vso_fd(int32_t k, const void* layers, const void* cam, const uint64_t* vis, int wrap, const double* grad_out,
-           const float* target, int32_t n_entries, const int32_t* entries, double h, double* out) {
+           const float* target, int loss_kind, int32_t n_entries, const int32_t* entries, double h, double* out) {
   const Layer* L = (const Layer*)layers;
   const Cam c = to_cam(cam);
   std::vector<std::vector<Vtx>> vt(k);
@@ -627,7 +632,7 @@ int vso_fd(int32_t k, const void* layers, const void* cam, const uint64_t* vis, 
         if (target) {
           for (int ch = 0; ch < 3; ++ch) {
             const double d = o[ch] - (double)target[4 * p + ch];
-            lv += d * d;
+            lv += loss_kind == 1 ? std::fabs(d) : d * d;
           }
         } else {
           for (int ch = 0; ch < 4; ++ch) lv += grad_out[4 * p + ch] * o[ch];
