@@ -143,15 +143,20 @@ typedef struct vs_raster_opts {
  *         colour changes by at most eps_T * max|c|.
  * wrap:   0 = repeat (the OpenGL default), 1 = clamp to edge.
  * target: device f32 [sum_v H_v W_v][4] or NULL.  When set, the backward
- *         pass uses the RGB L2 loss  loss_scale * sum_p ||RGB_p - target_p||^2
- *         instead of grad_rgba (A of the target is ignored).
- * loss_scale: multiplies the fused L2 loss (e.g. 1/number of pixels). */
+ *         pass uses the fused RGB loss selected by `loss` instead of
+ *         grad_rgba (A of the target is ignored):
+ *           VS_LOSS_L2: loss_scale * sum_p ||RGB_p - target_p||_2^2
+ *           VS_LOSS_L1: loss_scale * sum_p ||RGB_p - target_p||_1  (the
+ *                       paper's texturing loss, Sec. 4.3; gradient sign(.),
+ *                       0 at a tie)
+ * loss_scale: multiplies the fused loss (e.g. 1/number of scalars). */
+enum { VS_LOSS_L2 = 0, VS_LOSS_L1 = 1 };
 typedef struct vs_shade_opts {
   float eps_T;
   int32_t wrap;
   const float* target;
   float loss_scale;
-  int32_t reserved;
+  int32_t loss;
 } vs_shade_opts;
 
 /* Status block counters (vs_read_status). */
@@ -211,7 +216,8 @@ vs_status vs_render(const vs_mesh* layers, const vs_texture* tex, int32_t k, con
  * out_rgba:  optional device f32 [sum_v H_v W_v][4]: when non-NULL the
  *            forward image is written too (same values as vs_render).
  * sse:       optional device f64 [1]: when non-NULL and opts->target is set,
- *            sum_p ||RGB_p - target_p||^2 is ACCUMULATED into it. */
+ *            the unscaled loss sum_p ||RGB_p - target_p||^2 (L2) or
+ *            sum_p ||RGB_p - target_p||_1 (L1) is ACCUMULATED into it. */
 vs_status vs_render_backward(const vs_mesh* layers, const vs_texture* tex, int32_t k, const vs_views* views,
                              const uint64_t* vis, const void* ws, size_t ws_bytes, const float* grad_rgba,
                              float* const* grad_tex, float* out_rgba, double* sse, const vs_shade_opts* opts,
@@ -298,6 +304,27 @@ typedef struct vs_adam_opts {
 vs_status vs_adam_step(float* const* params, float* const* grads, float* const* m, float* const* v,
                        const int64_t* counts, int32_t k, const vs_adam_opts* opts, int32_t* step, double* sse,
                        double* history, int32_t hist_len, void* stream);
+
+/* Squeezing and quantisation (Sec. 4.3 "Squeezing and Quantization"): the
+ * texture a logit stands for is q(sigmoid(param)) with
+ * q(x) = round(levels * x) / levels, ties to even, decided in FP64
+ * (levels = 255 for 8-bit storage; 0 = no quantisation).  params and tex:
+ * host arrays [k] of device f32 buffers of counts[l] scalars (multiples of
+ * 4, 16-byte aligned).  0 <= levels <= 65535. */
+vs_status vs_squeeze(const float* const* params, float* const* tex, const int64_t* counts, int32_t k,
+                     int32_t levels, void* stream);
+
+/* Quantisation-aware fitting step: Adam on the logits of squeezed, quantised
+ * textures.  grads hold dL/dtex (e.g. from vs_render_backward on tex); the
+ * quantiser is passed straight through, so the logit gradient is
+ * dL/dtex * s (1 - s), s = sigmoid(param).  After the update tex is rewritten
+ * as vs_squeeze does, the gradient is reset and the bookkeeping of
+ * vs_adam_step runs.  opts->lo and opts->hi are not used (logits are
+ * unbounded).  Other arguments as in vs_adam_step. */
+vs_status vs_adam_step_squeezed(float* const* params, float* const* grads, float* const* m, float* const* v,
+                                float* const* tex, const int64_t* counts, int32_t k, int32_t levels,
+                                const vs_adam_opts* opts, int32_t* step, double* sse, double* history,
+                                int32_t hist_len, void* stream);
 
 /* ---- HIP graphs: capture a sequence of the calls above on one stream ---- */
 typedef struct vs_graph_s* vs_graph;

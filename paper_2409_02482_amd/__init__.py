@@ -5,8 +5,9 @@ rendering of k nested UV-textured mesh shells and its texture adjoint, as
 hand-written HIP kernels behind a C ABI (include/vs.h).
 """
 from ._lib import LIB_PATH, VsError, load  # noqa: F401
-from .binding import (Graph, Layers, Renderer, Views, adam_step, alloc_workspace, autotune, raster,  # noqa: F401
-                     read_status, render, render_backward, render_sh, workspace_bytes)
+from .binding import (Graph, Layers, Renderer, Views, adam_step, adam_step_squeezed, alloc_workspace,  # noqa: F401
+                     autotune, raster, read_status, render, render_backward, render_sh, squeeze, workspace_bytes)
 
 __all__ = ["Layers", "Views", "Renderer", "raster", "render", "render_backward", "render_sh", "read_status",
-           "workspace_bytes", "alloc_workspace", "autotune", "adam_step", "Graph", "load", "VsError", "LIB_PATH"]
+           "workspace_bytes", "alloc_workspace", "autotune", "adam_step", "adam_step_squeezed", "squeeze", "Graph",
+           "load", "VsError", "LIB_PATH"]

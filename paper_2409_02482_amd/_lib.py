@@ -54,7 +54,10 @@ class VsAdamOpts(ctypes.Structure):
 
 
 class VsShadeOpts(ctypes.Structure):
-    _fields_ = [("eps_T", c_f32), ("wrap", c_i32), ("target", c_vp), ("loss_scale", c_f32), ("reserved", c_i32)]
+    _fields_ = [("eps_T", c_f32), ("wrap", c_i32), ("target", c_vp), ("loss_scale", c_f32), ("loss", c_i32)]
+
+
+VS_LOSS = {"l2": 0, "l1": 1}
 
 
 class VsShTexture(ctypes.Structure):
@@ -80,6 +83,9 @@ SIGNATURES = {
     "vs_read_status": (c_i32, [c_vp, c_sz, c_vp, c_vp]),
     "vs_autotune": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp, ctypes.c_char_p, c_vp]),
     "vs_adam_step": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp]),
+    "vs_squeeze": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_vp]),
+    "vs_adam_step_squeezed": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_i32,
+                                      c_vp]),
     "vs_graph_begin": (c_i32, [c_vp]),
     "vs_graph_end": (c_i32, [c_vp, c_vp]),
     "vs_graph_launch": (c_i32, [c_vp, c_vp]),

@@ -142,8 +142,9 @@ def raster(layers: Layers, views: Views, vis: Optional[torch.Tensor] = None, ws:
     return vis, ws
 
 
-def _shade_opts(eps_T=0.0, wrap=0, target=None, loss_scale=1.0):
-    return C.VsShadeOpts(float(eps_T), int(wrap), 0 if target is None else target.data_ptr(), float(loss_scale), 0)
+def _shade_opts(eps_T=0.0, wrap=0, target=None, loss_scale=1.0, loss="l2"):
+    return C.VsShadeOpts(float(eps_T), int(wrap), 0 if target is None else target.data_ptr(), float(loss_scale),
+                         C.VS_LOSS[loss])
 
 
 def render(layers: Layers, textures, views: Views, vis: torch.Tensor, ws: torch.Tensor,
@@ -188,6 +189,7 @@ def render_backward(layers: Layers, textures, views: Views, vis: torch.Tensor, w
                     grad_rgba: Optional[torch.Tensor] = None, grad_tex: Optional[List[torch.Tensor]] = None,
                     target: Optional[torch.Tensor] = None, loss_scale: float = 1.0,
                     out: Optional[torch.Tensor] = None, sse: Optional[torch.Tensor] = None, wrap: int = 0,
+                    loss: str = "l2",
                     stream=None) -> List[torch.Tensor]:
     """vs_render_backward: accumulates dL/dtexture into grad_tex (zeros if None) and returns it."""
     if grad_tex is None:
@@ -204,7 +206,7 @@ def render_backward(layers: Layers, textures, views: Views, vis: torch.Tensor, w
         _dev(sse, torch.float64, "sse")
     tex = textures_struct(textures)
     gp = (ctypes.c_void_p * layers.k)(*[g.data_ptr() for g in grad_tex])
-    opts = _shade_opts(0.0, wrap, target, loss_scale)
+    opts = _shade_opts(0.0, wrap, target, loss_scale, loss)
     C.check(C.load().vs_render_backward(
         ctypes.addressof(layers.c), ctypes.addressof(tex), layers.k, ctypes.byref(views.c), vis.data_ptr(),
         ws.data_ptr(), ws.numel(), None if grad_rgba is None else grad_rgba.data_ptr(), ctypes.addressof(gp),
@@ -249,6 +251,38 @@ def adam_step(params, grads, m, v, step: torch.Tensor, lr=1e-2, betas=(0.9, 0.99
                                   step.data_ptr(), None if sse is None else sse.data_ptr(),
                                   None if history is None else history.data_ptr(), hist_len, _stream(stream)),
             "vs_adam_step")
+
+
+def squeeze(params, tex, levels: int = 255, stream=None):
+    """vs_squeeze: tex = q(sigmoid(params)) (q: rounding to levels steps; 0 = none)."""
+    k = len(params)
+    for name, arr in (("params", params), ("tex", tex)):
+        for l, t in enumerate(arr):
+            _dev(t, torch.float32, f"{name}[{l}]")
+    keep = [(ctypes.c_void_p * k)(*[t.data_ptr() for t in a]) for a in (params, tex)]
+    counts = (ctypes.c_int64 * k)(*[t.numel() for t in params])
+    C.check(C.load().vs_squeeze(ctypes.addressof(keep[0]), ctypes.addressof(keep[1]), ctypes.addressof(counts), k,
+                                int(levels), _stream(stream)), "vs_squeeze")
+
+
+def adam_step_squeezed(params, grads, m, v, tex, step: torch.Tensor, levels: int = 255, lr=1e-2, betas=(0.9, 0.999),
+                       eps=1e-8, sse: Optional[torch.Tensor] = None, history: Optional[torch.Tensor] = None,
+                       stream=None):
+    """vs_adam_step_squeezed: Adam on logits (straight-through quantiser), tex rewritten, gradient reset."""
+    k = len(params)
+    for name, arr in (("params", params), ("grads", grads), ("m", m), ("v", v), ("tex", tex)):
+        for l, t in enumerate(arr):
+            _dev(t, torch.float32, f"{name}[{l}]")
+    _dev(step, torch.int32, "step")
+    keep = [(ctypes.c_void_p * k)(*[t.data_ptr() for t in a]) for a in (params, grads, m, v, tex)]
+    counts = (ctypes.c_int64 * k)(*[t.numel() for t in params])
+    opts = C.VsAdamOpts(lr, betas[0], betas[1], eps, 0.0, 0.0)
+    hist_len = 0 if history is None else history.numel()
+    C.check(C.load().vs_adam_step_squeezed(*[ctypes.addressof(a) for a in keep], ctypes.addressof(counts), k,
+                                           int(levels), ctypes.byref(opts), step.data_ptr(),
+                                           None if sse is None else sse.data_ptr(),
+                                           None if history is None else history.data_ptr(), hist_len,
+                                           _stream(stream)), "vs_adam_step_squeezed")
 
 
 class Graph:

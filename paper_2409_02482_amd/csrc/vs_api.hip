@@ -419,6 +419,8 @@ vs_status vs_render_backward(const vs_mesh* layers, const vs_texture* tex, int32
   const float scale = opts ? opts->loss_scale : 1.0f;
   const int wrap = opts ? opts->wrap : 0;
   if (wrap != 0 && wrap != 1) return fail(VS_ERR_UNSUPPORTED, "wrap = %d", wrap);
+  const int loss = opts ? opts->loss : VS_LOSS_L2;
+  if (loss != VS_LOSS_L2 && loss != VS_LOSS_L1) return fail(VS_ERR_UNSUPPORTED, "loss = %d", loss);
   const vs::WsLayout lay = ws_layout(L, views, 0);
   if ((st = check_ws(ws, ws_bytes, lay.proj + (size_t)views->n_views * L.vert_off[k] * sizeof(vs::ProjVert))))
     return st;
@@ -431,7 +433,7 @@ vs_status vs_render_backward(const vs_mesh* layers, const vs_texture* tex, int32
   auto launch = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3((unsigned)vs::shade_grid_blocks(tiles)), dim3(256), 0, s, views->dev,
                        views->n_views, tile_view, tiles, L, X, proj,
-                       L.vert_off[k], vis, (const float4*)grad_rgba, (const float4*)target, scale,
+                       L.vert_off[k], vis, (const float4*)grad_rgba, (const float4*)target, scale, loss,
                        (float4*)out_rgba, target ? sse : nullptr, wrap, status);
   };
   if (k <= 4) launch(vs::k_shade_bwd<4>);
@@ -566,35 +568,100 @@ extern "C" vs_status vs_autotune(const vs_mesh* layers, int32_t k, const vs_view
 
 // ------------------------------------------------------------------ fitting
 
-extern "C" vs_status vs_adam_step(float* const* params, float* const* grads, float* const* m, float* const* v,
-                                  const int64_t* counts, int32_t k, const vs_adam_opts* opts, int32_t* step,
-                                  double* sse, double* history, int32_t hist_len, void* stream) {
-  if (!params || !grads || !m || !v || !counts || !opts || !step) return fail(VS_ERR_ARG, "vs_adam_step: null pointer");
-  if (k < 1 || k > VS_MAX_LAYERS) return fail(VS_ERR_SIZE, "vs_adam_step: k = %d", k);
-  vs::AdamTable A;
+namespace {
+
+// Per-layer buffers of a fitting step; any of the pointer arrays may be absent (NULL) when unused.
+vs_status build_adam(const char* who, float* const* params, float* const* grads, float* const* m, float* const* v,
+                     float* const* tex, const int64_t* counts, int32_t k, vs::AdamTable& A, vs::TexOut& T) {
+  if (!params || !counts) return fail(VS_ERR_ARG, "%s: null pointer", who);
+  if (k < 1 || k > VS_MAX_LAYERS) return fail(VS_ERR_SIZE, "%s: k = %d", who, k);
   std::memset(&A, 0, sizeof(A));
+  std::memset(&T, 0, sizeof(T));
   A.k = k;
   for (int l = 0; l < k; ++l) {
-    if (!params[l] || !grads[l] || !m[l] || !v[l]) return fail(VS_ERR_ARG, "vs_adam_step: layer %d null", l);
-    if (counts[l] <= 0 || counts[l] % 4) return fail(VS_ERR_SIZE, "vs_adam_step: count %d not a positive multiple of 4", l);
-    for (const void* p : {(const void*)params[l], (const void*)grads[l], (const void*)m[l], (const void*)v[l]})
-      if ((uintptr_t)p % 16) return fail(VS_ERR_ARG, "vs_adam_step: layer %d buffer not 16-byte aligned", l);
-    A.p[l] = params[l]; A.g[l] = grads[l]; A.m[l] = m[l]; A.v[l] = v[l];
+    const float* bufs[5] = {params[l], grads ? grads[l] : nullptr, m ? m[l] : nullptr, v ? v[l] : nullptr,
+                            tex ? tex[l] : nullptr};
+    const bool need[5] = {true, grads != nullptr, m != nullptr, v != nullptr, tex != nullptr};
+    for (int b = 0; b < 5; ++b) {
+      if (!need[b]) continue;
+      if (!bufs[b]) return fail(VS_ERR_ARG, "%s: layer %d null", who, l);
+      if ((uintptr_t)bufs[b] % 16) return fail(VS_ERR_ARG, "%s: layer %d buffer not 16-byte aligned", who, l);
+    }
+    if (counts[l] <= 0 || counts[l] % 4) return fail(VS_ERR_SIZE, "%s: count %d not a positive multiple of 4", who, l);
+    A.p[l] = params[l];
+    if (grads) A.g[l] = grads[l];
+    if (m) A.m[l] = m[l];
+    if (v) A.v[l] = v[l];
+    if (tex) T.t[l] = tex[l];
     A.off[l + 1] = A.off[l] + counts[l];
   }
   for (int l = k + 1; l <= VS_MAX_LAYERS; ++l) A.off[l] = A.off[k];
+  return VS_OK;
+}
+
+vs_status check_adam_opts(const char* who, const vs_adam_opts* opts) {
+  if (!opts) return fail(VS_ERR_ARG, "%s: null opts", who);
   if (!(opts->lr >= 0.f) || !(opts->beta1 >= 0.f && opts->beta1 < 1.f) || !(opts->beta2 >= 0.f && opts->beta2 < 1.f) ||
       !(opts->eps > 0.f) || !(opts->lo <= opts->hi))
-    return fail(VS_ERR_ARG, "vs_adam_step: bad hyper-parameters");
+    return fail(VS_ERR_ARG, "%s: bad hyper-parameters", who);
+  return VS_OK;
+}
+
+unsigned adam_grid(const vs::AdamTable& A) {
+  return (unsigned)std::min<int64_t>(grid_1d(A.off[A.k] / 4, 256), 8192);
+}
+
+}  // namespace
+
+extern "C" vs_status vs_adam_step(float* const* params, float* const* grads, float* const* m, float* const* v,
+                                  const int64_t* counts, int32_t k, const vs_adam_opts* opts, int32_t* step,
+                                  double* sse, double* history, int32_t hist_len, void* stream) {
+  if (!grads || !m || !v || !step) return fail(VS_ERR_ARG, "vs_adam_step: null pointer");
+  vs::AdamTable A;
+  vs::TexOut T;
+  vs_status st = build_adam("vs_adam_step", params, grads, m, v, nullptr, counts, k, A, T);
+  if (st) return st;
+  if ((st = check_adam_opts("vs_adam_step", opts))) return st;
   if (history && hist_len < 0) return fail(VS_ERR_ARG, "vs_adam_step: hist_len < 0");
   hipStream_t s = (hipStream_t)stream;
-  const int64_t n4 = A.off[k] / 4;
-  const unsigned grid = (unsigned)std::min<int64_t>(grid_1d(n4, 256), 8192);
-  hipLaunchKernelGGL(vs::k_adam, dim3(grid), dim3(256), 0, s, A, opts->lr, opts->beta1, opts->beta2, opts->eps, opts->lo,
-                     opts->hi, (const int32_t*)step);
+  hipLaunchKernelGGL(vs::k_adam, dim3(adam_grid(A)), dim3(256), 0, s, A, opts->lr, opts->beta1, opts->beta2, opts->eps,
+                     opts->lo, opts->hi, (const int32_t*)step);
   hipLaunchKernelGGL(vs::k_fit_bookkeep, dim3(1), dim3(64), 0, s, sse, history, hist_len, step);
-  vs_status st = check_launch("vs_adam_step");
+  if ((st = check_launch("vs_adam_step"))) return st;
+  return ok();
+}
+
+extern "C" vs_status vs_squeeze(const float* const* params, float* const* tex, const int64_t* counts, int32_t k,
+                                int32_t levels, void* stream) {
+  if (!tex) return fail(VS_ERR_ARG, "vs_squeeze: null tex");
+  if (levels < 0 || levels > 65535) return fail(VS_ERR_ARG, "vs_squeeze: levels = %d outside 0..65535", levels);
+  vs::AdamTable A;
+  vs::TexOut T;
+  vs_status st = build_adam("vs_squeeze", const_cast<float* const*>(params), nullptr, nullptr, nullptr, tex, counts, k,
+                            A, T);
   if (st) return st;
+  hipLaunchKernelGGL(vs::k_squeeze, dim3(adam_grid(A)), dim3(256), 0, (hipStream_t)stream, A, T, (int)levels);
+  if ((st = check_launch("vs_squeeze"))) return st;
+  return ok();
+}
+
+extern "C" vs_status vs_adam_step_squeezed(float* const* params, float* const* grads, float* const* m, float* const* v,
+                                           float* const* tex, const int64_t* counts, int32_t k, int32_t levels,
+                                           const vs_adam_opts* opts, int32_t* step, double* sse, double* history,
+                                           int32_t hist_len, void* stream) {
+  if (!grads || !m || !v || !tex || !step) return fail(VS_ERR_ARG, "vs_adam_step_squeezed: null pointer");
+  if (levels < 0 || levels > 65535) return fail(VS_ERR_ARG, "vs_adam_step_squeezed: levels = %d outside 0..65535", levels);
+  vs::AdamTable A;
+  vs::TexOut T;
+  vs_status st = build_adam("vs_adam_step_squeezed", params, grads, m, v, tex, counts, k, A, T);
+  if (st) return st;
+  if ((st = check_adam_opts("vs_adam_step_squeezed", opts))) return st;
+  if (history && hist_len < 0) return fail(VS_ERR_ARG, "vs_adam_step_squeezed: hist_len < 0");
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(vs::k_adam_squeezed, dim3(adam_grid(A)), dim3(256), 0, s, A, T, opts->lr, opts->beta1,
+                     opts->beta2, opts->eps, (int)levels, (const int32_t*)step);
+  hipLaunchKernelGGL(vs::k_fit_bookkeep, dim3(1), dim3(64), 0, s, sse, history, hist_len, step);
+  if ((st = check_launch("vs_adam_step_squeezed"))) return st;
   return ok();
 }
 

@@ -327,6 +327,7 @@ __global__ void __launch_bounds__(256, KMAX <= 8 ? 6 : 3) k_shade_bwd(const vs_v
                                                    int64_t vpv, const uint64_t* __restrict__ vis,
                                                    const float4* __restrict__ grad_out,
                                                    const float4* __restrict__ target, float loss_scale,
+                                                   int loss,
                                                    float4* __restrict__ out, double* __restrict__ sse, int wrap,
                                                    unsigned long long* __restrict__ status) {
 #pragma clang fp contract(fast)
@@ -380,9 +381,16 @@ __global__ void __launch_bounds__(256, KMAX <= 8 ? 6 : 3) k_shade_bwd(const vs_v
     if (target) {
       const float4 tg = target[gp];
       const float dr = Cr - tg.x, dg = Cg - tg.y, db = Cb - tg.z;
-      const float s2 = 2.0f * loss_scale;
-      gr = s2 * dr; gg = s2 * dg; gb = s2 * db;
-      my_sse = (double)dr * dr + (double)dg * dg + (double)db * db;
+      if (loss == VS_LOSS_L1) {
+        // d|x|/dx = sign(x), 0 at a tie
+        auto sgn = [](float x) { return (float)((x > 0.0f) - (x < 0.0f)); };
+        gr = loss_scale * sgn(dr); gg = loss_scale * sgn(dg); gb = loss_scale * sgn(db);
+        my_sse = (double)fabsf(dr) + (double)fabsf(dg) + (double)fabsf(db);
+      } else {
+        const float s2 = 2.0f * loss_scale;
+        gr = s2 * dr; gg = s2 * dg; gb = s2 * db;
+        my_sse = (double)dr * dr + (double)dg * dg + (double)db * db;
+      }
     } else {
       const float4 go = grad_out[gp];
       gr = go.x; gg = go.y; gb = go.z; gA = go.w;

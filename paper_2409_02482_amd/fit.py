@@ -7,6 +7,11 @@ visibility is rasterised once and every iteration is
     fused Adam step + projection to [0, 1] + gradient reset
     on-device bookkeeping (SSE history for the PSNR curve, step counter)
 
+With quantize=True the parameters are logits and the rendered texture is
+q(sigmoid(logit)) rounded to 8 bits (Sec. 4.3 "Squeezing and
+Quantization"), the quantiser passed straight through in the gradient; with
+loss="l1" the fused loss is the paper's L1 instead of L2.
+
 Two launch strategies with identical arithmetic:
   "graph":    all views in one batched launch per kernel, the iteration
               captured once in a HIP graph and replayed;
@@ -37,14 +42,27 @@ class TextureFit:
 
     def __init__(self, meshes, cameras: Sequence, init_textures: Sequence[np.ndarray], targets: torch.Tensor,
                  mode: str = "graph", lr: float = 1e-2, betas=(0.9, 0.999), eps: float = 1e-8, bin: int = 0,
-                 max_iters: int = 1024, device: str = "cuda"):
+                 max_iters: int = 1024, device: str = "cuda", loss: str = "l2", quantize: bool = False,
+                 levels: int = 255):
         if mode not in ("graph", "per_view"):
             raise ValueError(mode)
+        if loss not in ("l2", "l1"):
+            raise ValueError(loss)
         self.mode, self.lr, self.betas, self.eps = mode, lr, betas, eps
+        self.loss, self.quantize, self.levels = loss, quantize, levels
         self.layers = R.Layers(meshes, device)
         self.views = R.Views(cameras, device)
         self.k = self.layers.k
-        self.params = [torch.from_numpy(np.ascontiguousarray(t, np.float32)).to(device) for t in init_textures]
+        init = [torch.from_numpy(np.ascontiguousarray(t, np.float32)).to(device) for t in init_textures]
+        if quantize:
+            # logits of the initial texture (kept off 0 and 1 so they stay finite)
+            lim = 0.5 / max(levels, 255)
+            self.params = [torch.logit(t.clamp(lim, 1.0 - lim)) for t in init]
+            self.tex = [torch.empty_like(t) for t in init]
+            R.squeeze(self.params, self.tex, levels)
+        else:
+            self.params = init
+            self.tex = self.params
         self.grads = [torch.zeros_like(p) for p in self.params]
         self.m = [torch.zeros_like(p) for p in self.params]
         self.v = [torch.zeros_like(p) for p in self.params]
@@ -71,14 +89,19 @@ class TextureFit:
     def _iteration(self):
         s = self.stream
         if self.mode == "graph":
-            R.render_backward(self.layers, self.params, self.views, self.vis, self.ws, grad_tex=self.grads,
-                              target=self.targets, loss_scale=self.loss_scale, sse=self.sse, stream=s)
+            R.render_backward(self.layers, self.tex, self.views, self.vis, self.ws, grad_tex=self.grads,
+                              target=self.targets, loss_scale=self.loss_scale, sse=self.sse, loss=self.loss, stream=s)
         else:
             for vv, vis, ws, tgt in self.per_view:
-                R.render_backward(self.layers, self.params, vv, vis, ws, grad_tex=self.grads, target=tgt,
-                                  loss_scale=self.loss_scale, sse=self.sse, stream=s)
-        R.adam_step(self.params, self.grads, self.m, self.v, self.step, lr=self.lr, betas=self.betas, eps=self.eps,
-                    sse=self.sse, history=self.history, stream=s)
+                R.render_backward(self.layers, self.tex, vv, vis, ws, grad_tex=self.grads, target=tgt,
+                                  loss_scale=self.loss_scale, sse=self.sse, loss=self.loss, stream=s)
+        if self.quantize:
+            R.adam_step_squeezed(self.params, self.grads, self.m, self.v, self.tex, self.step, levels=self.levels,
+                                 lr=self.lr, betas=self.betas, eps=self.eps, sse=self.sse, history=self.history,
+                                 stream=s)
+        else:
+            R.adam_step(self.params, self.grads, self.m, self.v, self.step, lr=self.lr, betas=self.betas,
+                        eps=self.eps, sse=self.sse, history=self.history, stream=s)
 
     def capture(self):
         if self.mode != "graph":
@@ -100,10 +123,16 @@ class TextureFit:
         e1.synchronize()
         return e0.elapsed_time(e1) / max(iters, 1)
 
-    def psnr(self) -> np.ndarray:
+    def loss_history(self) -> np.ndarray:
+        """Per iteration, the unscaled loss sum over all RGB scalars (squared or absolute errors)."""
         self.stream.synchronize()
         n = int(self.step.item())
-        return psnr_from_sse(self.history[:min(n, self.history.numel())].cpu().numpy(), self.n_scalars)
+        return self.history[:min(n, self.history.numel())].cpu().numpy()
+
+    def psnr(self) -> np.ndarray:
+        if self.loss != "l2":
+            raise ValueError("the per-iteration history holds absolute errors under the L1 loss")
+        return psnr_from_sse(self.loss_history(), self.n_scalars)
 
 
 def render_targets(meshes, cameras, textures: Sequence[np.ndarray], device="cuda") -> torch.Tensor:
@@ -124,25 +153,32 @@ def main(argv=None):
     ap.add_argument("--res", type=int, default=800)
     ap.add_argument("--iters", type=int, default=200)
     ap.add_argument("--modes", default="graph,per_view")
+    ap.add_argument("--loss", default="l2", choices=["l2", "l1"])
+    ap.add_argument("--quantize", action="store_true", help="fit logits of 8-bit quantised textures")
     args = ap.parse_args(argv)
     import scenes as S  # seeded synthetic inputs
     sc = S.make_config(5, n_views=args.views, resolution=(args.res, args.res))
     targets = render_targets(sc.layers, sc.cameras, sc.textures_gt)
-    res = {"config": f"k={sc.k} shells, {args.views} views at {args.res}x{args.res}, {args.iters} Adam iterations"}
+    res = {"config": f"k={sc.k} shells, {args.views} views at {args.res}x{args.res}, {args.iters} Adam iterations, "
+                     f"{args.loss} loss" + (", 8-bit quantised logits" if args.quantize else "")}
     for mode in args.modes.split(","):
-        fit = TextureFit(sc.layers, sc.cameras, sc.textures, targets, mode=mode, max_iters=args.iters + 8)
+        fit = TextureFit(sc.layers, sc.cameras, sc.textures, targets, mode=mode, max_iters=args.iters + 8,
+                         loss=args.loss, quantize=args.quantize)
         if mode == "graph":
             fit.capture()
         ms = fit.run(args.iters)
-        p = fit.psnr()
-        res[mode] = {"ms_per_iter": ms, "psnr_first": float(p[0]), "psnr_last": float(p[-1]),
-                     "psnr": [round(float(x), 4) for x in p]}
-        print(f"[fit] {mode}: {ms:.3f} ms/iter, PSNR {p[0]:.2f} -> {p[-1]:.2f} dB", file=sys.stderr, flush=True)
+        # L2: PSNR per iteration; L1: mean absolute error per RGB scalar per iteration
+        name, unit = ("psnr", "dB") if args.loss == "l2" else ("mae", "")
+        p = fit.psnr() if args.loss == "l2" else fit.loss_history() / fit.n_scalars
+        res[mode] = {"ms_per_iter": ms, f"{name}_first": float(p[0]), f"{name}_last": float(p[-1]),
+                     name: [round(float(x), 6) for x in p]}
+        print(f"[fit] {mode}: {ms:.3f} ms/iter, {name.upper()} {p[0]:.4f} -> {p[-1]:.4f} {unit}", file=sys.stderr,
+              flush=True)
         del fit
         torch.cuda.empty_cache()
     if "graph" in res and "per_view" in res:
         res["speedup_graph_vs_per_view"] = res["per_view"]["ms_per_iter"] / res["graph"]["ms_per_iter"]
-        res["max_psnr_gap_db"] = float(np.max(np.abs(np.array(res["graph"]["psnr"]) - np.array(res["per_view"]["psnr"]))))
+        res[f"max_{name}_gap"] = float(np.max(np.abs(np.array(res["graph"][name]) - np.array(res["per_view"][name]))))
     print(json.dumps(res))
 
 

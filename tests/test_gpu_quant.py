@@ -1,0 +1,132 @@
+"""GPU parity of quantisation-aware fitting with the L1 loss (Sec. 4.3).
+
+  - the fused L1 adjoint against the oracle's analytic L1 adjoint (normwise
+    1e-4) and its loss sum against the oracle image;
+  - vs_squeeze bit-exact against the oracle's q(sigmoid(theta)) (both decide
+    the 8-bit code in FP64);
+  - vs_adam_step_squeezed against the textbook update written in plain PyTorch
+    (fp32), with the texture it writes bit-exact against the oracle's squeeze
+    of the updated logits;
+  - an L1 fit on 8-bit quantised logits lowers the error, every texel stays on
+    the 1/255 grid, and graph replays equal eager iterations.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import scenes as S
+from vs_testlib import GRAD_RTOL, gpu_render, grad_rel_err, say, small_mixed_scene, vis_numpy
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2409_02482_amd as P
+    P.load()
+    return torch
+
+
+def test_l1_adjoint_matches_oracle(torch_cuda):
+    torch = torch_cuda
+    sc = small_mixed_scene(config=84)
+    tg = S.uniform_targets(84, sc.cameras)
+    P, layers, views, vis, ws, rgba, tex = gpu_render(sc)
+    flat = torch.from_numpy(np.concatenate([t.reshape(-1, 4) for t in tg])).cuda()
+    sse = torch.zeros(1, dtype=torch.float64, device="cuda")
+    scale = 0.25
+    grads = P.render_backward(layers, tex, views, vis, ws, target=flat, loss_scale=scale, sse=sse, loss="l1")
+    torch.cuda.synchronize()
+    got = [g.cpu().numpy().astype(np.float64) for g in grads]
+    want = [np.zeros(t.shape) for t in sc.textures]
+    l1 = 0.0
+    for v, cam in enumerate(sc.cameras):
+        visn = vis_numpy(views, vis, sc.k, v)
+        w = O.backward(sc.layers, sc.textures, cam, visn, target=tg[v], loss="l1")
+        want = [a + scale * b for a, b in zip(want, w)]
+        img = O.shade(sc.layers, sc.textures, cam, visn)
+        l1 += np.abs(img[..., :3] - tg[v][..., :3].astype(np.float64)).sum()
+    err = grad_rel_err(got, want)
+    say(f"[gpu] L1 adjoint rel err {err:.2e}")
+    assert err <= GRAD_RTOL
+    assert abs(sse.item() - l1) <= 1e-5 * l1
+
+
+def test_squeeze_bit_exact(torch_cuda):
+    torch = torch_cuda
+    import paper_2409_02482_amd as P
+    rng = np.random.default_rng(85)
+    shapes = [(33, 17, 4), (8, 8, 4)]
+    th = [rng.normal(0.0, 3.0, s).astype(np.float32) for s in shapes]
+    th[1].reshape(-1)[:6] = [0.0, -0.0, 40.0, -40.0, 1e-8, -1e-8]
+    for levels in (255, 15, 0):
+        params = [torch.from_numpy(t).cuda() for t in th]
+        tex = [torch.empty_like(p) for p in params]
+        P.squeeze(params, tex, levels)
+        torch.cuda.synchronize()
+        for t, g in zip(th, tex):
+            assert np.array_equal(g.cpu().numpy(), O.squeeze_quantize(t, levels)), levels
+
+
+def test_adam_step_squeezed_matches_reference(torch_cuda):
+    torch = torch_cuda
+    import paper_2409_02482_amd as P
+    g = torch.Generator(device="cpu").manual_seed(3)
+    shapes = [(8, 12, 4), (16, 16, 4)]
+    params = [(torch.randn(s, generator=g) * 2).cuda() for s in shapes]
+    ref = [p.clone() for p in params]
+    m = [torch.zeros_like(p) for p in params]
+    v = [torch.zeros_like(p) for p in params]
+    rm = [torch.zeros_like(p) for p in params]
+    rv = [torch.zeros_like(p) for p in params]
+    tex = [torch.empty_like(p) for p in params]
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    lr, b1, b2, eps = 0.05, 0.9, 0.999, 1e-8
+    for t in range(1, 5):
+        grads = [(torch.rand(s, generator=g) - 0.5).cuda() for s in shapes]
+        rgrads = [x.clone() for x in grads]
+        P.adam_step_squeezed(params, grads, m, v, tex, step, levels=255, lr=lr, betas=(b1, b2), eps=eps)
+        torch.cuda.synchronize()
+        for i in range(len(shapes)):
+            s = torch.sigmoid(ref[i])
+            gq = rgrads[i] * s * (1 - s)                     # straight through the quantiser
+            rm[i] = b1 * rm[i] + (1 - b1) * gq
+            rv[i] = b2 * rv[i] + (1 - b2) * gq * gq
+            ref[i] = ref[i] - lr * (rm[i] / (1 - b1 ** t)) / ((rv[i] / (1 - b2 ** t)).sqrt() + eps)
+            assert torch.allclose(params[i], ref[i], rtol=1e-5, atol=1e-6)
+            assert torch.count_nonzero(grads[i]) == 0
+            assert np.array_equal(tex[i].cpu().numpy(), O.squeeze_quantize(params[i].cpu().numpy(), 255))
+    assert int(step.item()) == 4
+
+
+def test_quantised_l1_fit_graph_equals_eager(torch_cuda):
+    torch = torch_cuda
+    from paper_2409_02482_amd.fit import TextureFit, render_targets
+    sc = small_mixed_scene(k=3, sizes=((96, 80), (64, 64), (80, 96)), tex=32, config=86)
+    gt = [S.smooth_texture(87, l, 32, 32, opaque=(l == 2)) for l in range(3)]
+    init = []
+    for l in range(3):
+        t = np.full((32, 32, 4), 0.5, np.float32)
+        t[..., 3] = 0.9 if l == 2 else 0.5
+        init.append(t)
+    targets = render_targets(sc.layers, sc.cameras, gt)
+    say("[gpu] quantised L1 fit: eager")
+    eager = TextureFit(sc.layers, sc.cameras, init, targets, mode="graph", max_iters=64, loss="l1", quantize=True,
+                       lr=0.05)
+    eager.run(30)
+    say("[gpu] quantised L1 fit: graph")
+    graph = TextureFit(sc.layers, sc.cameras, init, targets, mode="graph", max_iters=64, loss="l1", quantize=True,
+                       lr=0.05)
+    graph.capture()
+    for _ in range(3):
+        graph.run(10)
+        torch.cuda.synchronize()
+    he, hg = eager.loss_history(), graph.loss_history()
+    assert len(he) == len(hg) == 30
+    assert he[-1] < 0.7 * he[0], f"L1 did not drop: {he[0]:.4f} -> {he[-1]:.4f}"
+    np.testing.assert_allclose(he, hg, rtol=1e-4)
+    for t in eager.tex:
+        codes = t.cpu().numpy().astype(np.float64) * 255.0
+        assert np.abs(codes - np.rint(codes)).max() < 1e-4
