@@ -492,19 +492,35 @@ __global__ void __launch_bounds__(256, KMAX <= 8 ? 6 : 3) k_shade_bwd(const vs_v
         pend = pend && !mine;
       }
       wave_lds_sync();
-      // flush: consecutive lanes take consecutive floats of the window (row-major), so each
-      // atomic instruction covers whole texture row segments
-      const int32_t row = ww * 4, total = row * wh;
-      const float inv_row = 1.0f / (float)row;
-      for (int e = lane; e < total; e += 64) {
-        const float val = win[e];
-        if (val != 0.0f) {
-          int32_t y = (int32_t)((float)e * inv_row);
-          int32_t xe = e - y * row;
-          if (xe < 0) { --y; xe += row; } else if (xe >= row) { ++y; xe -= row; }
-          const int32_t tj = abs_index(rj, dmin_j + y, Ht, wrap);
-          const int32_t ti = abs_index(ri, dmin_i + (xe >> 2), Wt, wrap);
-          unsafeAtomicAdd(G + ((int64_t)tj * Wt + ti) * 4 + (xe & 3), val);
+      // flush: consecutive lanes take consecutive floats of a window row (so each atomic
+      // instruction covers whole texture row segments), several rows per instruction when
+      // rows are short.  Lane -> (row offset rr, float cc0); the quotients are of small
+      // integers, exact in correctly rounded FP32 division.
+      const int32_t row = ww * 4;
+      const int32_t R = row >= 64 ? 1 : (int32_t)(64.0f / (float)row);
+      const int32_t rr = row >= 64 ? 0 : (int32_t)((float)lane / (float)row);
+      const int32_t cc0 = row >= 64 ? lane : lane - rr * row;
+      const bool flat = ri + dmin_i >= 0 && ri + dmax_i < Wt && rj + dmin_j >= 0 && rj + dmax_j < Ht;
+      if (rr < R) {
+        if (flat) {   // the window does not wrap: plain strided addresses
+          float* gbase = G + ((int64_t)(rj + dmin_j) * Wt + (ri + dmin_i)) * 4;
+          const int64_t gstride = (int64_t)Wt * 4;
+          for (int32_t y = rr; y < wh; y += R)
+            for (int32_t c = cc0; c < row; c += 64) {
+              const float val = win[y * row + c];
+              if (val != 0.0f) unsafeAtomicAdd(gbase + y * gstride + c, val);
+            }
+        } else {
+          for (int32_t y = rr; y < wh; y += R) {
+            const int32_t tj = abs_index(rj, dmin_j + y, Ht, wrap);
+            for (int32_t c = cc0; c < row; c += 64) {
+              const float val = win[y * row + c];
+              if (val != 0.0f) {
+                const int32_t ti = abs_index(ri, dmin_i + (c >> 2), Wt, wrap);
+                unsafeAtomicAdd(G + ((int64_t)tj * Wt + ti) * 4 + (c & 3), val);
+              }
+            }
+          }
         }
       }
       wave_lds_sync();   // the window is reused by the next layer
