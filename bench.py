@@ -120,6 +120,18 @@ def sh_cpu_baseline(scene, sh, n_threads, per_thread=2):
                       f"shading, {per_thread} view(s) per thread on {n_threads} threads, {dt:.1f} s wall"}
 
 
+def calibration_copy(mib):
+    """One plain device-to-device copy of mib MiB (reads and writes mib MiB): the HBM counter reference."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"[bench] calibration copy of {mib} MiB done")
+    del a, b
+
+
 def run_sh(args):
     """Forward rendering of the baked representation: raster + vs_render_sh per step."""
     import torch
@@ -215,6 +227,8 @@ def main():
               "with one all-reduce of the texture gradients per step)", file=sys.stderr)
         sys.exit(2)
 
+    if args.calibrate_copy:
+        calibration_copy(args.calibrate_copy)
     if args.workload == "sh":
         return run_sh(args)
 
@@ -231,14 +245,6 @@ def main():
     k = scene.k
     nv = len(scene.cameras)
     dev = "cuda"
-    if args.calibrate_copy:
-        n = args.calibrate_copy * (1 << 20) // 4
-        a = torch.ones(n, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy of {args.calibrate_copy} MiB done")
-        del a, b
     layers = P.Layers(scene.layers, dev)
     views = P.Views(scene.cameras, dev)
     tex = [torch.from_numpy(t).to(dev) for t in scene.textures]
