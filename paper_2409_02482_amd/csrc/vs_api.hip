@@ -436,8 +436,11 @@ vs_status vs_render_backward(const vs_mesh* layers, const vs_texture* tex, int32
                        L.vert_off[k], vis, (const float4*)grad_rgba, (const float4*)target, scale, loss,
                        (float4*)out_rgba, target ? sse : nullptr, wrap, status);
   };
+  // per-layer state lives in registers, so the common layer counts get their own instantiation
   if (k <= 4) launch(vs::k_shade_bwd<4>);
+  else if (k <= 7) launch(vs::k_shade_bwd<7>);
   else if (k <= 8) launch(vs::k_shade_bwd<8>);
+  else if (k <= 9) launch(vs::k_shade_bwd<9>);
   else launch(vs::k_shade_bwd<16>);
   if ((st = check_launch("vs_render_backward"))) return st;
   return ok();

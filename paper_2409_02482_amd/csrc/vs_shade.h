@@ -318,10 +318,10 @@ __device__ inline void merge_by_key(int32_t& key, float (&v)[16], int lane) {
 // round (an owner word per cell elects it), and the window is flushed with
 // global float atomics whose lanes cover consecutive floats.  A footprint larger than the window
 // uses direct global atomics.
-// The scatter is latency bound, so up to 8 layers the register budget is held
+// The scatter is latency bound, so up to 9 layers the register budget is held
 // to 6 wavefronts per SIMD (a few bytes of spill cost less than the lost waves).
 template <int KMAX>
-__global__ void __launch_bounds__(256, KMAX <= 8 ? 6 : 3) k_shade_bwd(const vs_view* __restrict__ views, int n_views,
+__global__ void __launch_bounds__(256, KMAX <= 9 ? 6 : 3) k_shade_bwd(const vs_view* __restrict__ views, int n_views,
                                                    const int32_t* __restrict__ tile_view, int64_t n_tiles,
                                                    LayerTable L, TexTable X, const ProjVert* __restrict__ proj,
                                                    int64_t vpv, const uint64_t* __restrict__ vis,
