@@ -69,21 +69,13 @@ __device__ inline float abs_cos_face(const float* __restrict__ xyz, const int32_
   return fabsf(nx * dx + ny * dy + nz * dz) * rsqrtf(len2);
 }
 
-// Bilinear weight-sum of one byte lane of four corner words.
-__device__ inline float bil_byte(uint32_t q00, uint32_t q01, uint32_t q10, uint32_t q11, int ch, float w00,
-                                 float w01, float w10, float w11) {
-  const int sh = 8 * ch;
-  return w00 * (float)((q00 >> sh) & 0xffu) + w01 * (float)((q01 >> sh) & 0xffu) +
-         w10 * (float)((q10 >> sh) & 0xffu) + w11 * (float)((q11 >> sh) & 0xffu);
-}
-
 // One thread per pixel, same tiling and XCD order as k_shade_fwd.  Per hit
 // layer: UV in FP64, then per degree l the footprint in that level (FP64
-// coordinates, as for RGBA textures), the 2l+1 coefficient words of the four
-// corners, bilinear weights in FP32 on the raw bytes, and the decode folded
-// into the harmonic sum:
-//   raw_c = mid * sum_i Y_i + scale * sum_i Y_i (b_i,c - 127.5),
-// b the interpolated byte.  The bytes of a texel's coefficients of one degree
+// coordinates, as for RGBA textures) and the 2l+1 coefficient words of the
+// four corners; the decode and the bilinear weights are folded into the
+// harmonic sum (all linear):
+//   raw_c = mid * sum_i Y_i + scale * sum_l [ sum_corner w_corner sum_m Y_lm q_lm,c - 127.5 sum_m Y_lm ],
+// q the raw bytes (FP32 sums of exact byte values).  The bytes of a texel's coefficients of one degree
 // are adjacent, so a corner costs 2l+1 consecutive words.
 // At degree 3 the register budget is held to 4 wavefronts per SIMD (a few
 // bytes of spill cost less than the lost latency hiding).
@@ -142,14 +134,28 @@ __global__ void __launch_bounds__(256, DEG == 3 ? 4 : 1) k_shade_sh(const vs_vie
         const uint32_t* p01 = base + ((int64_t)j0 * Wl + i1) * n;
         const uint32_t* p10 = base + ((int64_t)j1 * Wl + i0) * n;
         const uint32_t* p11 = base + ((int64_t)j1 * Wl + i1) * n;
+        // per corner, the harmonic sum of this degree's raw bytes; then the corners' weights
+        float s00[4] = {0.f, 0.f, 0.f, 0.f}, s01[4] = {0.f, 0.f, 0.f, 0.f};
+        float s10[4] = {0.f, 0.f, 0.f, 0.f}, s11[4] = {0.f, 0.f, 0.f, 0.f};
+        float ysum = 0.f;
 #pragma unroll
         for (int m = 0; m < n; ++m) {
           const uint32_t q00 = p00[m], q01 = p01[m], q10 = p10[m], q11 = p11[m];
           const float y = Y[d * d + m];
+          ysum += y;
 #pragma unroll
-          for (int ch = 0; ch < 4; ++ch)
-            acc[ch] += y * (bil_byte(q00, q01, q10, q11, ch, w00, w01, w10, w11) - 127.5f);
+          for (int ch = 0; ch < 4; ++ch) {
+            const int sh = 8 * ch;
+            s00[ch] += y * (float)((q00 >> sh) & 0xffu);
+            s01[ch] += y * (float)((q01 >> sh) & 0xffu);
+            s10[ch] += y * (float)((q10 >> sh) & 0xffu);
+            s11[ch] += y * (float)((q11 >> sh) & 0xffu);
+          }
         }
+        // the weights sum to 1, so the byte offset 127.5 comes off once per degree
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch)
+          acc[ch] += (w00 * s00[ch] + w01 * s01[ch] + w10 * s10[ch] + w11 * s11[ch]) - 127.5f * ysum;
       }
       float a = sigmoidf(prm.mid * sumY + prm.scale * acc[3]);
       if (prm.view_alpha) {
