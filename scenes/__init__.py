@@ -41,6 +41,7 @@ P_GT_TEXTURE = 5
 P_UPSTREAM = 6
 P_PICK = 7
 P_SH = 8
+P_NGP = 9
 
 Z_NEAR = 0.01
 
@@ -416,6 +417,29 @@ def sh_texture(config: int, layer: int, width: int, height: int, degree: int = 3
             a = rng.integers(115, 141, (h, w, 2 * l + 1, 4), dtype=np.uint8)
         levels.append(a)
     return sh_pack(levels, width, height)
+
+
+def ngp_resolutions(levels: int, base: int, finest: int) -> List[int]:
+    """Geometric level resolutions floor(base * b^l), b = (finest / base)^(1 / (levels - 1))."""
+    if levels == 1:
+        return [base]
+    b = np.exp((np.log(finest) - np.log(base)) / (levels - 1))
+    return [int(np.floor(base * b ** l + 1e-9)) for l in range(levels)]
+
+
+def ngp_params(config: int, layer: int, levels: int, log2_table: int, hidden: int = 64, out: int = 4,
+               features: int = 2, table_scale: float = 1.0) -> np.ndarray:
+    """Seeded flat f32 parameters of one neural texture: tables U(-s, s), weights N(0, 1/fan_in), biases 0.1 N(0, 1).
+
+    Layout: tables [L][T][F] | W1 [hidden][L F] | b1 | W2 [hidden][hidden] | b2 | W3 [out][hidden] | b3."""
+    rng = np.random.default_rng([config, P_NGP, layer])
+    T = 1 << log2_table
+    parts = [rng.uniform(-table_scale, table_scale, levels * T * features),
+             rng.normal(0.0, 1.0 / np.sqrt(levels * features), hidden * levels * features),
+             0.1 * rng.normal(size=hidden),
+             rng.normal(0.0, 1.0 / np.sqrt(hidden), hidden * hidden), 0.1 * rng.normal(size=hidden),
+             rng.normal(0.0, 1.0 / np.sqrt(hidden), out * hidden), 0.1 * rng.normal(size=out)]
+    return np.concatenate(parts).astype(np.float32)
 
 
 def uniform_targets(config: int, cams: Sequence[Camera]) -> List[np.ndarray]:
