@@ -326,6 +326,47 @@ vs_status vs_adam_step_squeezed(float* const* params, float* const* grads, float
                                 const vs_adam_opts* opts, int32_t* step, double* sse, double* history,
                                 int32_t hist_len, void* stream);
 
+/* ---- neural textures (Sec. 4.3 "Texturing Meshes") ----
+ * A neural texture is a 2-D multiresolution hash grid followed by an MLP,
+ * grounded to the texture resolution by evaluating it at the texel centres
+ * ((i + 1/2)/W, (j + 1/2)/H) only (Sec. 4.3, Fig. 5): baking gives an ordinary
+ * RGBA texture for vs_render / vs_render_backward, and the texture gradient
+ * those return is carried back to the network by vs_ngp_backward.
+ * Level l of L has resolution N_l: its vertices are the integer points
+ * 0..N_l of (u N_l, v N_l) (FP64), each holding 2 features, read bilinearly;
+ * a level with (N_l + 1)^2 <= T is stored densely (index y (N_l + 1) + x),
+ * otherwise at (x XOR y * 2654435761) mod 2^32 masked to T - 1, T = 2^log2_table.
+ * MLP (hidden width 64, FP32): z1 = W1 e + b1, h1 = relu(z1); z2 = W2 h1 + b2,
+ * h2 = relu(z2); o = W3 h2 + b3; texel RGBA = sigmoid(o), e the 2L features.
+ * Parameters of one layer: one f32 array of vs_ngp_param_count floats,
+ *   tables [L][T][2] | W1 [64][2L] | b1 [64] | W2 [64][64] | b2 [64] | W3 [4][64] | b3 [4]. */
+#define VS_NGP_MAX_LEVELS 16
+typedef struct vs_ngp_config {
+  int32_t levels;                          /* 1..16 */
+  int32_t log2_table;                      /* 4..24 */
+  int32_t resolution[VS_NGP_MAX_LEVELS];   /* N_l, 1..65535 */
+} vs_ngp_config;
+
+/* Floats of one layer's parameters, or -1 for an invalid configuration. */
+int64_t vs_ngp_param_count(const vs_ngp_config* cfg);
+
+/* Workspace bytes of vs_ngp_backward for k layers of textures width[l] x height[l]. */
+size_t vs_ngp_workspace_bytes(const vs_ngp_config* cfg, int32_t k, const int32_t* width, const int32_t* height);
+
+/* Bake: tex[l] (device f32 [height[l]][width[l]][4]) = the neural texture of
+ * params[l] at every texel centre.  params, tex: host arrays [k] of device
+ * pointers (16-byte aligned); width, height: host arrays [k], 1..VS_MAX_TEX_DIM. */
+vs_status vs_ngp_bake(const float* const* params, const vs_ngp_config* cfg, int32_t k, const int32_t* width,
+                      const int32_t* height, float* const* tex, void* stream);
+
+/* Backward: given grad_tex[l] = dL/dtex[l] (device f32 [height][width][4]),
+ * ACCUMULATES dL/dparams into grad_params[l] (device f32, vs_ngp_param_count
+ * floats each; summation order not fixed: atomics).  ws: device workspace of
+ * vs_ngp_workspace_bytes, 256-byte aligned. */
+vs_status vs_ngp_backward(const float* const* params, const vs_ngp_config* cfg, int32_t k, const int32_t* width,
+                          const int32_t* height, const float* const* grad_tex, float* const* grad_params,
+                          void* ws, size_t ws_bytes, void* stream);
+
 /* ---- HIP graphs: capture a sequence of the calls above on one stream ---- */
 typedef struct vs_graph_s* vs_graph;
 

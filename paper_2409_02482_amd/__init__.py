@@ -6,8 +6,10 @@ hand-written HIP kernels behind a C ABI (include/vs.h).
 """
 from ._lib import LIB_PATH, VsError, load  # noqa: F401
 from .binding import (Graph, Layers, Renderer, Views, adam_step, adam_step_squeezed, alloc_workspace,  # noqa: F401
-                     autotune, raster, read_status, render, render_backward, render_sh, squeeze, workspace_bytes)
+                     autotune, ngp_backward, ngp_bake, ngp_workspace, NgpConfig, raster, read_status, render,
+                     render_backward, render_sh, squeeze, workspace_bytes)
 
 __all__ = ["Layers", "Views", "Renderer", "raster", "render", "render_backward", "render_sh", "read_status",
-           "workspace_bytes", "alloc_workspace", "autotune", "adam_step", "adam_step_squeezed", "squeeze", "Graph",
+           "workspace_bytes", "alloc_workspace", "autotune", "adam_step", "adam_step_squeezed", "squeeze",
+           "NgpConfig", "ngp_bake", "ngp_backward", "ngp_workspace", "Graph",
            "load", "VsError", "LIB_PATH"]

@@ -69,6 +69,10 @@ class VsShOpts(ctypes.Structure):
                 ("view_alpha", c_i32)]
 
 
+class VsNgpConfig(ctypes.Structure):
+    _fields_ = [("levels", c_i32), ("log2_table", c_i32), ("resolution", c_i32 * 16)]
+
+
 # name -> (restype, argtypes); every symbol declared in include/vs.h
 SIGNATURES = {
     "vs_version": (ctypes.c_char_p, []),
@@ -86,6 +90,10 @@ SIGNATURES = {
     "vs_squeeze": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_vp]),
     "vs_adam_step_squeezed": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_i32,
                                       c_vp]),
+    "vs_ngp_param_count": (ctypes.c_int64, [c_vp]),
+    "vs_ngp_workspace_bytes": (c_sz, [c_vp, c_i32, c_vp, c_vp]),
+    "vs_ngp_bake": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),
+    "vs_ngp_backward": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "vs_graph_begin": (c_i32, [c_vp]),
     "vs_graph_end": (c_i32, [c_vp, c_vp]),
     "vs_graph_launch": (c_i32, [c_vp, c_vp]),

@@ -285,6 +285,68 @@ def adam_step_squeezed(params, grads, m, v, tex, step: torch.Tensor, levels: int
                                            _stream(stream)), "vs_adam_step_squeezed")
 
 
+class NgpConfig:
+    """Neural texture shape: per-level grid resolutions and the hash-table size 2^log2_table."""
+
+    def __init__(self, resolutions: Sequence[int], log2_table: int):
+        if not 1 <= len(resolutions) <= 16:
+            raise ValueError("1..16 levels")
+        self.resolutions = [int(r) for r in resolutions]
+        self.log2_table = int(log2_table)
+        self.c = C.VsNgpConfig(len(self.resolutions), self.log2_table,
+                               (ctypes.c_int32 * 16)(*(self.resolutions + [0] * (16 - len(self.resolutions)))))
+        self.param_count = int(C.load().vs_ngp_param_count(ctypes.byref(self.c)))
+        if self.param_count < 0:
+            raise ValueError("invalid neural texture configuration: " + C.load().vs_last_error().decode())
+
+
+def _sizes(textures_hw):
+    k = len(textures_hw)
+    return (ctypes.c_int32 * k)(*[int(w) for w, h in textures_hw]), (ctypes.c_int32 * k)(*[int(h) for w, h in textures_hw])
+
+
+def ngp_bake(params, cfg: NgpConfig, sizes, tex=None, stream=None):
+    """vs_ngp_bake: RGBA textures [H, W, 4] of the neural textures params[l] at sizes[l] = (W, H)."""
+    k = len(params)
+    for l, p in enumerate(params):
+        _dev(p, torch.float32, f"params[{l}]")
+    if tex is None:
+        tex = [torch.empty(h, w, 4, dtype=torch.float32, device=params[0].device) for w, h in sizes]
+    for l, t in enumerate(tex):
+        _dev(t, torch.float32, f"tex[{l}]")
+    ws_, hs_ = _sizes(sizes)
+    keep = [(ctypes.c_void_p * k)(*[t.data_ptr() for t in a]) for a in (params, tex)]
+    C.check(C.load().vs_ngp_bake(ctypes.addressof(keep[0]), ctypes.byref(cfg.c), k, ctypes.addressof(ws_),
+                                 ctypes.addressof(hs_), ctypes.addressof(keep[1]), _stream(stream)), "vs_ngp_bake")
+    return tex
+
+
+def ngp_workspace(cfg: NgpConfig, sizes, device="cuda") -> torch.Tensor:
+    ws_, hs_ = _sizes(sizes)
+    n = int(C.load().vs_ngp_workspace_bytes(ctypes.byref(cfg.c), len(sizes), ctypes.addressof(ws_),
+                                            ctypes.addressof(hs_)))
+    return torch.empty(max(n, 256), dtype=torch.uint8, device=device)
+
+
+def ngp_backward(params, cfg: NgpConfig, sizes, grad_tex, grad_params=None, ws: Optional[torch.Tensor] = None,
+                 stream=None):
+    """vs_ngp_backward: accumulates dL/dparams (zeros if None) from dL/dtexture and returns it."""
+    k = len(params)
+    if grad_params is None:
+        grad_params = [torch.zeros_like(p) for p in params]
+    for name, arr in (("params", params), ("grad_tex", grad_tex), ("grad_params", grad_params)):
+        for l, t in enumerate(arr):
+            _dev(t, torch.float32, f"{name}[{l}]")
+    if ws is None:
+        ws = ngp_workspace(cfg, sizes, params[0].device)
+    ws_, hs_ = _sizes(sizes)
+    keep = [(ctypes.c_void_p * k)(*[t.data_ptr() for t in a]) for a in (params, grad_tex, grad_params)]
+    C.check(C.load().vs_ngp_backward(ctypes.addressof(keep[0]), ctypes.byref(cfg.c), k, ctypes.addressof(ws_),
+                                     ctypes.addressof(hs_), ctypes.addressof(keep[1]), ctypes.addressof(keep[2]),
+                                     ws.data_ptr(), ws.numel(), _stream(stream)), "vs_ngp_backward")
+    return grad_params
+
+
 class Graph:
     """A HIP graph captured from calls into the library on one (non-default) stream."""
 

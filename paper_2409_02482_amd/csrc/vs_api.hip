@@ -18,6 +18,7 @@
 #include "vs_shade.h"
 #include "vs_sh.h"
 #include "vs_fit.h"
+#include "vs_ngp.h"
 
 namespace {
 
@@ -665,6 +666,176 @@ extern "C" vs_status vs_adam_step_squeezed(float* const* params, float* const* g
                      opts->beta2, opts->eps, (int)levels, (const int32_t*)step);
   hipLaunchKernelGGL(vs::k_fit_bookkeep, dim3(1), dim3(64), 0, s, sse, history, hist_len, step);
   if ((st = check_launch("vs_adam_step_squeezed"))) return st;
+  return ok();
+}
+
+// ------------------------------------------------------------------ neural textures
+
+namespace {
+
+vs_status ngp_shape(const vs_ngp_config* cfg, vs::NgpShape& S) {
+  if (!cfg) return fail(VS_ERR_ARG, "vs_ngp: null config");
+  if (cfg->levels < 1 || cfg->levels > VS_NGP_MAX_LEVELS) return fail(VS_ERR_SIZE, "vs_ngp: levels = %d", cfg->levels);
+  if (cfg->log2_table < 4 || cfg->log2_table > 24) return fail(VS_ERR_SIZE, "vs_ngp: log2_table = %d", cfg->log2_table);
+  std::memset(&S, 0, sizeof(S));
+  S.levels = cfg->levels;
+  S.log2_table = cfg->log2_table;
+  const int64_t T = (int64_t)1 << cfg->log2_table;
+  for (int l = 0; l < cfg->levels; ++l) {
+    const int32_t n = cfg->resolution[l];
+    if (n < 1 || n > 65535) return fail(VS_ERR_SIZE, "vs_ngp: resolution[%d] = %d outside 1..65535", l, n);
+    S.res[l] = n;
+    S.dense[l] = (int64_t)(n + 1) * (n + 1) <= T;
+  }
+  const int64_t H = vs::kNgpHidden, O = vs::kNgpOut, in = 2 * (int64_t)cfg->levels;
+  S.o_w1 = (int64_t)cfg->levels * T * 2;
+  S.o_b1 = S.o_w1 + H * in;
+  S.o_w2 = S.o_b1 + H;
+  S.o_b2 = S.o_w2 + H * H;
+  S.o_w3 = S.o_b2 + H;
+  S.o_b3 = S.o_w3 + O * H;
+  S.total = S.o_b3 + O;
+  return VS_OK;
+}
+
+vs_status ngp_table(const char* who, const float* const* params, int32_t k, const int32_t* width,
+                    const int32_t* height, vs::NgpTable& T) {
+  if (!params || !width || !height) return fail(VS_ERR_ARG, "%s: null pointer", who);
+  if (k < 1 || k > VS_MAX_LAYERS) return fail(VS_ERR_SIZE, "%s: k = %d", who, k);
+  std::memset(&T, 0, sizeof(T));
+  T.k = k;
+  for (int l = 0; l < k; ++l) {
+    if (!params[l]) return fail(VS_ERR_ARG, "%s: params[%d] null", who, l);
+    if ((uintptr_t)params[l] % 16) return fail(VS_ERR_ARG, "%s: params[%d] not 16-byte aligned", who, l);
+    if (width[l] < 1 || height[l] < 1 || width[l] > VS_MAX_TEX_DIM || height[l] > VS_MAX_TEX_DIM)
+      return fail(VS_ERR_SIZE, "%s: texture %d size %dx%d", who, l, width[l], height[l]);
+    T.params[l] = params[l];
+    T.w[l] = width[l];
+    T.h[l] = height[l];
+    const int64_t tiles = (int64_t)((width[l] + vs::kNgpTile - 1) / vs::kNgpTile) *
+                          ((height[l] + vs::kNgpTile - 1) / vs::kNgpTile);
+    T.block_off[l + 1] = T.block_off[l] + tiles;
+    T.texel_off[l + 1] = T.texel_off[l] + (int64_t)width[l] * height[l];
+  }
+  for (int l = k + 1; l <= VS_MAX_LAYERS; ++l) {
+    T.block_off[l] = T.block_off[k];
+    T.texel_off[l] = T.texel_off[k];
+  }
+  return VS_OK;
+}
+
+struct NgpWs {
+  size_t a1, a2, a3, d1, d2, d0, total;
+};
+
+NgpWs ngp_ws(const vs::NgpShape& S, int64_t texels) {
+  NgpWs w;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off += (bytes + 255) / 256 * 256; return o; };
+  w.a1 = take((size_t)texels * (2 * S.levels + 1) * 4);
+  w.a2 = take((size_t)texels * (vs::kNgpHidden + 1) * 4);
+  w.a3 = take((size_t)texels * (vs::kNgpHidden + 1) * 4);
+  w.d1 = take((size_t)texels * vs::kNgpHidden * 4);
+  w.d2 = take((size_t)texels * vs::kNgpHidden * 4);
+  w.d0 = take((size_t)texels * vs::kNgpOut * 4);
+  w.total = off;
+  return w;
+}
+
+}  // namespace
+
+extern "C" int64_t vs_ngp_param_count(const vs_ngp_config* cfg) {
+  vs::NgpShape S;
+  if (ngp_shape(cfg, S)) return -1;
+  return S.total;
+}
+
+extern "C" size_t vs_ngp_workspace_bytes(const vs_ngp_config* cfg, int32_t k, const int32_t* width,
+                                         const int32_t* height) {
+  vs::NgpShape S;
+  if (ngp_shape(cfg, S) || !width || !height || k < 1 || k > VS_MAX_LAYERS) return 0;
+  int64_t texels = 0;
+  for (int l = 0; l < k; ++l) texels += (int64_t)std::max(width[l], 0) * std::max(height[l], 0);
+  return ngp_ws(S, texels).total;
+}
+
+extern "C" vs_status vs_ngp_bake(const float* const* params, const vs_ngp_config* cfg, int32_t k, const int32_t* width,
+                                 const int32_t* height, float* const* tex, void* stream) {
+  vs::NgpShape S;
+  vs::NgpTable T;
+  vs_status st = ngp_shape(cfg, S);
+  if (st) return st;
+  if ((st = ngp_table("vs_ngp_bake", params, k, width, height, T))) return st;
+  if (!tex) return fail(VS_ERR_ARG, "vs_ngp_bake: null tex");
+  for (int l = 0; l < k; ++l) {
+    if (!tex[l] || (uintptr_t)tex[l] % 16) return fail(VS_ERR_ARG, "vs_ngp_bake: tex[%d] null or misaligned", l);
+    T.tex[l] = tex[l];
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const unsigned grid = (unsigned)T.block_off[k];
+  if (S.levels <= 8) hipLaunchKernelGGL(vs::k_ngp_bake<8>, dim3(grid), dim3(256), 0, s, T, S);
+  else hipLaunchKernelGGL(vs::k_ngp_bake<16>, dim3(grid), dim3(256), 0, s, T, S);
+  if ((st = check_launch("vs_ngp_bake"))) return st;
+  return ok();
+}
+
+extern "C" vs_status vs_ngp_backward(const float* const* params, const vs_ngp_config* cfg, int32_t k,
+                                     const int32_t* width, const int32_t* height, const float* const* grad_tex,
+                                     float* const* grad_params, void* ws, size_t ws_bytes, void* stream) {
+  vs::NgpShape S;
+  vs::NgpTable T;
+  vs_status st = ngp_shape(cfg, S);
+  if (st) return st;
+  if ((st = ngp_table("vs_ngp_backward", params, k, width, height, T))) return st;
+  if (!grad_tex || !grad_params) return fail(VS_ERR_ARG, "vs_ngp_backward: null pointer");
+  for (int l = 0; l < k; ++l) {
+    if (!grad_tex[l] || (uintptr_t)grad_tex[l] % 16)
+      return fail(VS_ERR_ARG, "vs_ngp_backward: grad_tex[%d] null or misaligned", l);
+    if (!grad_params[l] || (uintptr_t)grad_params[l] % 16)
+      return fail(VS_ERR_ARG, "vs_ngp_backward: grad_params[%d] null or misaligned", l);
+    T.gtex[l] = grad_tex[l];
+    T.gparams[l] = grad_params[l];
+  }
+  const NgpWs w = ngp_ws(S, T.texel_off[k]);
+  if ((st = check_ws(ws, ws_bytes, w.total))) return st;
+  char* base = (char*)ws;
+  vs::NgpStage G;
+  G.a1 = (float*)(base + w.a1);
+  G.a2 = (float*)(base + w.a2);
+  G.a3 = (float*)(base + w.a3);
+  G.d1 = (float*)(base + w.d1);
+  G.d2 = (float*)(base + w.d2);
+  G.d0 = (float*)(base + w.d0);
+  hipStream_t s = (hipStream_t)stream;
+  const unsigned grid = (unsigned)T.block_off[k];
+  if (S.levels <= 8) hipLaunchKernelGGL(vs::k_ngp_texel_bwd<8>, dim3(grid), dim3(256), 0, s, T, S, G);
+  else hipLaunchKernelGGL(vs::k_ngp_texel_bwd<16>, dim3(grid), dim3(256), 0, s, T, S, G);
+  if ((st = check_launch("vs_ngp_backward"))) return st;
+  // weight products: per layer dW1 | db1 from (D1, [e|1]), dW2 | db2 from (D2, [h1|1]), dW3 | db3 from (D0, [h2|1])
+  vs::NgpGemm Q;
+  std::memset(&Q, 0, sizeof(Q));
+  const int nin = 2 * S.levels;
+  for (int l = 0; l < k; ++l) {
+    const int64_t r0 = T.texel_off[l], rows = T.texel_off[l + 1] - r0;
+    float* gp = grad_params[l];
+    const int g0 = 3 * l;
+    Q.D[g0] = G.d1 + r0 * vs::kNgpHidden; Q.A[g0] = G.a1 + r0 * (nin + 1);
+    Q.gw[g0] = gp + S.o_w1; Q.gb[g0] = gp + S.o_b1; Q.M[g0] = vs::kNgpHidden; Q.N[g0] = nin + 1;
+    Q.D[g0 + 1] = G.d2 + r0 * vs::kNgpHidden; Q.A[g0 + 1] = G.a2 + r0 * (vs::kNgpHidden + 1);
+    Q.gw[g0 + 1] = gp + S.o_w2; Q.gb[g0 + 1] = gp + S.o_b2; Q.M[g0 + 1] = vs::kNgpHidden;
+    Q.N[g0 + 1] = vs::kNgpHidden + 1;
+    Q.D[g0 + 2] = G.d0 + r0 * vs::kNgpOut; Q.A[g0 + 2] = G.a3 + r0 * (vs::kNgpHidden + 1);
+    Q.gw[g0 + 2] = gp + S.o_w3; Q.gb[g0 + 2] = gp + S.o_b3; Q.M[g0 + 2] = vs::kNgpOut;
+    Q.N[g0 + 2] = vs::kNgpHidden + 1;
+    for (int q = 0; q < 3; ++q) Q.rows[g0 + q] = rows;
+  }
+  Q.n_gemm = 3 * k;
+  int64_t max_rows = 0;
+  for (int l = 0; l < k; ++l) max_rows = std::max(max_rows, T.texel_off[l + 1] - T.texel_off[l]);
+  // enough blocks to fill the chip, each with at least a few 64-row tiles
+  Q.blocks_per_gemm = (int32_t)std::max<int64_t>(1, std::min<int64_t>(256, max_rows / 512));
+  hipLaunchKernelGGL(vs::k_ngp_wgrad, dim3((unsigned)(Q.n_gemm * Q.blocks_per_gemm)), dim3(256), 0, s, Q);
+  if ((st = check_launch("vs_ngp_backward (weights)"))) return st;
   return ok();
 }
 

@@ -1,0 +1,368 @@
+// Neural textures (Sec. 4.3 "Texturing Meshes"): a 2-D multiresolution hash
+// grid and a small MLP, grounded to the texture resolution by evaluating them
+// at the texel centres only (Fig. 5), so that the renderer samples an ordinary
+// RGBA texture.  Per texel (i, j) at u = (i + 1/2)/W, v = (j + 1/2)/H:
+//   level l: x = u N_l, y = v N_l (FP64, as the texel coordinates elsewhere),
+//            bilinear over the 4 surrounding vertices of 2 features each;
+//            vertex index y (N_l + 1) + x when (N_l + 1)^2 <= T, else
+//            (x XOR y * 2654435761) mod 2^32 masked to T - 1;
+//   e = concat_l features (2L), z1 = W1 e + b1, h1 = relu(z1) (64),
+//   z2 = W2 h1 + b2, h2 = relu(z2) (64), o = W3 h2 + b3 (4), texel = sigmoid(o).
+// Parameters per layer, flat f32:
+//   tables [L][T][2] | W1 [64][2L] | b1 [64] | W2 [64][64] | b2 [64] | W3 [4][64] | b3 [4].
+// Weights are uniform across a block's texels and are read through scalar
+// loads (no LDS).  The backward pass writes, per texel, the layer inputs
+// (with a trailing 1) and the deltas to a workspace; the weight gradients are
+// then tall-skinny products over texels (k_ngp_wgrad), the biases coming out
+// of the trailing-1 column.
+#pragma once
+
+#include "vs_common.h"
+
+namespace vs {
+
+constexpr int kNgpHidden = 64;
+constexpr int kNgpOut = 4;
+constexpr int kNgpMaxLevels = 16;
+constexpr uint32_t kNgpPrimeY = 2654435761u;
+constexpr int kNgpTile = 16;   // texels per tile side; a block of 256 threads covers one tile
+
+struct NgpShape {
+  int32_t levels, log2_table;
+  int32_t res[kNgpMaxLevels];
+  int32_t dense[kNgpMaxLevels];
+  int64_t o_w1, o_b1, o_w2, o_b2, o_w3, o_b3, total;   // o_tab = 0
+};
+
+// Per layer buffers and sizes; block_off / texel_off are prefix sums over layers.
+struct NgpTable {
+  const float* params[kMaxLayers];
+  float* tex[kMaxLayers];
+  const float* gtex[kMaxLayers];
+  float* gparams[kMaxLayers];
+  int32_t w[kMaxLayers], h[kMaxLayers];
+  int64_t block_off[kMaxLayers + 1];
+  int64_t texel_off[kMaxLayers + 1];
+  int32_t k;
+};
+
+// Staging rows per texel (backward): A1 = [e | 1], A2 = [h1 | 1], A3 = [h2 | 1], D1, D2, DO.
+struct NgpStage {
+  float* a1;   // [texels][2L + 1]
+  float* a2;   // [texels][65]
+  float* a3;   // [texels][65]
+  float* d1;   // [texels][64]
+  float* d2;   // [texels][64]
+  float* d0;   // [texels][4]
+};
+
+__device__ inline uint32_t ngp_index(uint32_t x, uint32_t y, int32_t N, int32_t dense, uint32_t mask) {
+  return dense ? y * (uint32_t)(N + 1) + x : ((x ^ (y * kNgpPrimeY)) & mask);
+}
+
+struct NgpTexel {
+  int l;
+  int32_t i, j;
+  bool valid;
+  int64_t t;   // texel index within the layer, j W + i
+};
+
+__device__ inline NgpTexel ngp_texel(const NgpTable& T) {
+  NgpTexel r;
+  const int64_t b = blockIdx.x;
+  int l = 0;
+  while (l + 1 < T.k && T.block_off[l + 1] <= b) ++l;
+  r.l = l;
+  const int W = T.w[l], H = T.h[l];
+  const int tiles_x = (W + kNgpTile - 1) / kNgpTile;
+  const int64_t tb = b - T.block_off[l];
+  const int ty = (int)(tb / tiles_x), tx = (int)(tb - (int64_t)ty * tiles_x);
+  r.i = tx * kNgpTile + (threadIdx.x & 15);
+  r.j = ty * kNgpTile + (threadIdx.x >> 4);
+  r.valid = r.i < W && r.j < H;
+  r.t = (int64_t)r.j * W + r.i;
+  return r;
+}
+
+// Encoding of one texel centre; also the per-level corner indices and weights.
+template <int LMAX>
+__device__ inline void ngp_encode(const float* __restrict__ tables, const NgpShape& S, double u, double v, float (&e)[2 * LMAX],
+                                  uint32_t (&idx)[LMAX][4], float (&wt)[LMAX][4]) {
+  const uint32_t T = 1u << S.log2_table, mask = T - 1u;
+#pragma unroll
+  for (int lv = 0; lv < LMAX; ++lv) {
+    e[2 * lv] = 0.f;
+    e[2 * lv + 1] = 0.f;
+    if (lv >= S.levels) continue;
+    const int32_t N = S.res[lv];
+    const double x = u * (double)N, y = v * (double)N;
+    const double x0 = floor(x), y0 = floor(y);
+    const float fx = (float)(x - x0), fy = (float)(y - y0);
+    const uint32_t xi = (uint32_t)x0, yi = (uint32_t)y0;
+    const float2* tab = reinterpret_cast<const float2*>(tables) + (int64_t)lv * T;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const uint32_t dx = c & 1, dy = c >> 1;
+      const uint32_t q = ngp_index(xi + dx, yi + dy, N, S.dense[lv], mask);
+      const float w = (dx ? fx : 1.0f - fx) * (dy ? fy : 1.0f - fy);
+      const float2 f = tab[q];
+      e[2 * lv] += w * f.x;
+      e[2 * lv + 1] += w * f.y;
+      idx[lv][c] = q;
+      wt[lv][c] = w;
+    }
+  }
+}
+
+__device__ inline float ngp_sigmoid(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+// Forward MLP of one texel: z1 kept as h1 (relu), z2 kept (pre-activation), o.
+template <int LMAX>
+__device__ inline void ngp_mlp(const float* __restrict__ P, const NgpShape& S, const float (&e)[2 * LMAX],
+                               float (&h1)[kNgpHidden], float (&z2)[kNgpHidden], float (&o)[kNgpOut]) {
+#pragma clang fp contract(fast)
+  const int nin = 2 * S.levels;
+  const float* W1 = P + S.o_w1;
+  const float* b1 = P + S.o_b1;
+#pragma unroll
+  for (int j = 0; j < kNgpHidden; ++j) {
+    float acc = b1[j];
+#pragma unroll
+    for (int q = 0; q < 2 * LMAX; ++q)
+      if (q < nin) acc += W1[j * nin + q] * e[q];
+    h1[j] = fmaxf(acc, 0.0f);
+  }
+  const float* W2 = P + S.o_w2;
+  const float* b2 = P + S.o_b2;
+#pragma unroll
+  for (int j = 0; j < kNgpHidden; ++j) {
+    float acc = b2[j];
+#pragma unroll
+    for (int q = 0; q < kNgpHidden; ++q) acc += W2[j * kNgpHidden + q] * h1[q];
+    z2[j] = acc;
+  }
+  const float* W3 = P + S.o_w3;
+  const float* b3 = P + S.o_b3;
+#pragma unroll
+  for (int c = 0; c < kNgpOut; ++c) {
+    float acc = b3[c];
+#pragma unroll
+    for (int q = 0; q < kNgpHidden; ++q) acc += W3[c * kNgpHidden + q] * fmaxf(z2[q], 0.0f);
+    o[c] = acc;
+  }
+}
+
+// texture = sigmoid(MLP(encoding)) at every texel centre of every layer.
+template <int LMAX>
+__global__ void __launch_bounds__(256) k_ngp_bake(NgpTable T, NgpShape S) {
+  const NgpTexel x = ngp_texel(T);
+  if (!x.valid) return;
+  const float* P = T.params[x.l];
+  const double u = ((double)x.i + 0.5) / (double)T.w[x.l], v = ((double)x.j + 0.5) / (double)T.h[x.l];
+  float e[2 * LMAX];
+  uint32_t idx[LMAX][4];
+  float wt[LMAX][4];
+  ngp_encode<LMAX>(P, S, u, v, e, idx, wt);
+  float h1[kNgpHidden], z2[kNgpHidden], o[kNgpOut];
+  ngp_mlp<LMAX>(P, S, e, h1, z2, o);
+  reinterpret_cast<float4*>(T.tex[x.l])[x.t] =
+      make_float4(ngp_sigmoid(o[0]), ngp_sigmoid(o[1]), ngp_sigmoid(o[2]), ngp_sigmoid(o[3]));
+}
+
+// Adds v into grad[q] for every lane, summing lanes that share q first when the
+// level is coarse (many texels per cell): one leader per distinct index and
+// round, the others' values reduced across the wavefront.
+__device__ inline void ngp_table_add(float* __restrict__ g, uint32_t q, float v0, float v1, bool active, bool merge) {
+  if (!merge) {
+    if (active) {
+      unsafeAtomicAdd(g + 2 * (int64_t)q, v0);
+      unsafeAtomicAdd(g + 2 * (int64_t)q + 1, v1);
+    }
+    return;
+  }
+  uint64_t pend = __ballot(active);
+  while (pend) {
+    const int leader = __builtin_ctzll(pend);
+    const uint32_t k0 = __builtin_amdgcn_readlane(q, leader);
+    const bool same = active && q == k0;
+    float s0 = same ? v0 : 0.0f, s1 = same ? v1 : 0.0f;
+    for (int off = 32; off > 0; off >>= 1) {
+      s0 += __shfl_xor(s0, off);
+      s1 += __shfl_xor(s1, off);
+    }
+    if ((int)__lane_id() == leader) {
+      unsafeAtomicAdd(g + 2 * (int64_t)k0, s0);
+      unsafeAtomicAdd(g + 2 * (int64_t)k0 + 1, s1);
+    }
+    pend &= ~__ballot(same);
+  }
+}
+
+// Backward, per texel: recompute the forward, form the deltas
+//   do = dL/dtex * s (1 - s), d2 = (W3^T do) [z2 > 0], d1 = (W2^T d2) [z1 > 0], de = W1^T d1,
+// scatter de into the hash tables (bilinear weights), and stage [e|1], [h1|1],
+// [h2|1], d1, d2, do for the weight products.
+template <int LMAX>
+__global__ void __launch_bounds__(256) k_ngp_texel_bwd(NgpTable T, NgpShape S, NgpStage G) {
+#pragma clang fp contract(fast)
+  const NgpTexel x = ngp_texel(T);
+  const int l = x.l;
+  const float* P = T.params[l];
+  const double u = ((double)x.i + 0.5) / (double)T.w[l], v = ((double)x.j + 0.5) / (double)T.h[l];
+  float e[2 * LMAX];
+  uint32_t idx[LMAX][4];
+  float wt[LMAX][4];
+  float h1[kNgpHidden], z2[kNgpHidden], o[kNgpOut];
+  float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (x.valid) {
+    ngp_encode<LMAX>(P, S, u, v, e, idx, wt);
+    ngp_mlp<LMAX>(P, S, e, h1, z2, o);
+    g = reinterpret_cast<const float4*>(T.gtex[l])[x.t];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 2 * LMAX; ++q) e[q] = 0.f;
+#pragma unroll
+    for (int q = 0; q < kNgpHidden; ++q) { h1[q] = 0.f; z2[q] = 0.f; }
+#pragma unroll
+    for (int c = 0; c < kNgpOut; ++c) o[c] = 0.f;
+#pragma unroll
+    for (int lv = 0; lv < LMAX; ++lv)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) { idx[lv][c] = 0; wt[lv][c] = 0.f; }
+  }
+  float d0[kNgpOut];
+  const float gv[4] = {g.x, g.y, g.z, g.w};
+#pragma unroll
+  for (int c = 0; c < kNgpOut; ++c) {
+    const float s = ngp_sigmoid(o[c]);
+    d0[c] = gv[c] * s * (1.0f - s);
+  }
+  const float* W3 = P + S.o_w3;
+  float d2[kNgpHidden];
+#pragma unroll
+  for (int j = 0; j < kNgpHidden; ++j) {
+    float acc = 0.f;
+#pragma unroll
+    for (int c = 0; c < kNgpOut; ++c) acc += W3[c * kNgpHidden + j] * d0[c];
+    d2[j] = z2[j] > 0.0f ? acc : 0.0f;
+  }
+  const float* W2 = P + S.o_w2;
+  float d1[kNgpHidden];
+#pragma unroll
+  for (int q = 0; q < kNgpHidden; ++q) d1[q] = 0.f;
+#pragma unroll
+  for (int j = 0; j < kNgpHidden; ++j) {
+#pragma unroll
+    for (int q = 0; q < kNgpHidden; ++q) d1[q] += W2[j * kNgpHidden + q] * d2[j];
+  }
+#pragma unroll
+  for (int q = 0; q < kNgpHidden; ++q) d1[q] = h1[q] > 0.0f ? d1[q] : 0.0f;
+  const int nin = 2 * S.levels;
+  const float* W1 = P + S.o_w1;
+  float de[2 * LMAX];
+#pragma unroll
+  for (int q = 0; q < 2 * LMAX; ++q) {
+    float acc = 0.f;
+    if (q < nin) {
+#pragma unroll
+      for (int j = 0; j < kNgpHidden; ++j) acc += W1[j * nin + q] * d1[j];
+    }
+    de[q] = acc;
+  }
+  // hash-table gradients
+  const uint32_t TT = 1u << S.log2_table;
+  float* gtab = T.gparams[l];
+#pragma unroll
+  for (int lv = 0; lv < LMAX; ++lv) {
+    if (lv >= S.levels) continue;
+    // several texels per cell: merge equal vertices across the wavefront first
+    const bool merge = (int64_t)4 * S.res[lv] <= (int64_t)min(T.w[l], T.h[l]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      ngp_table_add(gtab + (int64_t)lv * TT * 2, idx[lv][c], wt[lv][c] * de[2 * lv], wt[lv][c] * de[2 * lv + 1],
+                    x.valid, merge);
+  }
+  if (!x.valid) return;
+  // staging rows
+  const int64_t r = T.texel_off[l] + x.t;
+  float* a1 = G.a1 + r * (nin + 1);
+#pragma unroll
+  for (int q = 0; q < 2 * LMAX; ++q)
+    if (q < nin) a1[q] = e[q];
+  a1[nin] = 1.0f;
+  float* a2 = G.a2 + r * (kNgpHidden + 1);
+  float* a3 = G.a3 + r * (kNgpHidden + 1);
+  float* dd1 = G.d1 + r * kNgpHidden;
+  float* dd2 = G.d2 + r * kNgpHidden;
+#pragma unroll
+  for (int q = 0; q < kNgpHidden; ++q) {
+    a2[q] = h1[q];
+    a3[q] = fmaxf(z2[q], 0.0f);
+    dd1[q] = d1[q];
+    dd2[q] = d2[q];
+  }
+  a2[kNgpHidden] = 1.0f;
+  a3[kNgpHidden] = 1.0f;
+  *reinterpret_cast<float4*>(G.d0 + r * kNgpOut) = make_float4(d0[0], d0[1], d0[2], d0[3]);
+}
+
+// One weight-gradient product of one layer: C[m][n] = sum_r D[r][m] A[r][n]
+// over the layer's texel rows, m < M (<= 64), n < N (<= 65, last column the
+// bias).  Blocks split the rows; each thread owns outputs m = tid / 4,
+// n = tid % 4 + 4 q; partial sums are added to the gradient (weights
+// row-major [M][N - 1], then the bias [M]).
+struct NgpGemm {
+  const float* D[3 * kMaxLayers];
+  const float* A[3 * kMaxLayers];
+  float* gw[3 * kMaxLayers];
+  float* gb[3 * kMaxLayers];
+  int64_t rows[3 * kMaxLayers];
+  int32_t M[3 * kMaxLayers], N[3 * kMaxLayers];
+  int32_t n_gemm, blocks_per_gemm;
+};
+
+__global__ void __launch_bounds__(256) k_ngp_wgrad(NgpGemm Q) {
+  __shared__ float sD[64][64];
+  __shared__ float sA[64][66];
+  const int gi = blockIdx.x / Q.blocks_per_gemm, part = blockIdx.x - gi * Q.blocks_per_gemm;
+  if (gi >= Q.n_gemm) return;
+  const int M = Q.M[gi], N = Q.N[gi];
+  const int64_t rows = Q.rows[gi];
+  const int64_t per = (rows + Q.blocks_per_gemm - 1) / Q.blocks_per_gemm;
+  const int64_t r0 = (int64_t)part * per, r1 = min(rows, r0 + per);
+  const int tid = threadIdx.x, m = tid >> 2, n0 = tid & 3;
+  float acc[17];
+#pragma unroll
+  for (int q = 0; q < 17; ++q) acc[q] = 0.f;
+  for (int64_t rb = r0; rb < r1; rb += 64) {
+    const int nr = (int)min((int64_t)64, r1 - rb);
+    __syncthreads();
+    for (int p = tid; p < 64 * 64; p += 256) {
+      const int rr = p >> 6, cc = p & 63;
+      sD[rr][cc] = (rr < nr && cc < M) ? Q.D[gi][(rb + rr) * M + cc] : 0.f;
+    }
+    for (int p = tid; p < 64 * 66; p += 256) {
+      const int rr = p / 66, cc = p - rr * 66;
+      sA[rr][cc] = (rr < nr && cc < N) ? Q.A[gi][(rb + rr) * N + cc] : 0.f;
+    }
+    __syncthreads();
+    for (int rr = 0; rr < nr; ++rr) {
+      const float d = sD[rr][m];
+#pragma unroll
+      for (int q = 0; q < 17; ++q) {
+        const int n = n0 + 4 * q;
+        if (n < 66) acc[q] += d * sA[rr][n];
+      }
+    }
+  }
+  if (m >= M) return;
+#pragma unroll
+  for (int q = 0; q < 17; ++q) {
+    const int n = n0 + 4 * q;
+    if (n >= N || acc[q] == 0.0f) continue;
+    if (n < N - 1) unsafeAtomicAdd(Q.gw[gi] + (int64_t)m * (N - 1) + n, acc[q]);
+    else unsafeAtomicAdd(Q.gb[gi] + m, acc[q]);
+  }
+}
+
+}  // namespace vs
