@@ -135,6 +135,77 @@ class TextureFit:
         return psnr_from_sse(self.loss_history(), self.n_scalars)
 
 
+class NeuralTextureFit:
+    """Neural textures (hash grid + MLP, Sec. 4.3) fit through the renderer.
+
+    Per iteration: bake the textures at their texel centres, the fused shade +
+    adjoint (L2 or L1) gives dL/dtexture, the network backward carries it to the
+    parameters, and Adam (unbounded) updates them; the same launches can be
+    captured in a HIP graph."""
+
+    def __init__(self, meshes, cameras: Sequence, targets: torch.Tensor, tex_size: int, levels: int = 8,
+                 log2_table: int = 16, base_res: int = 16, lr: float = 1e-2, loss: str = "l2", config: int = 5,
+                 max_iters: int = 1024, device: str = "cuda"):
+        import scenes as S  # seeded initial parameters
+        self.layers = R.Layers(meshes, device)
+        self.views = R.Views(cameras, device)
+        self.k = self.layers.k
+        self.cfg = R.NgpConfig(S.ngp_resolutions(levels, base_res, tex_size), log2_table)
+        self.sizes = [(tex_size, tex_size)] * self.k
+        self.params = [torch.from_numpy(S.ngp_params(config, l, levels, log2_table, table_scale=1e-2)).to(device)
+                       for l in range(self.k)]
+        self.m = [torch.zeros_like(p) for p in self.params]
+        self.v = [torch.zeros_like(p) for p in self.params]
+        self.gp = [torch.zeros_like(p) for p in self.params]
+        self.tex = [torch.empty(tex_size, tex_size, 4, device=device) for _ in range(self.k)]
+        self.gtex = [torch.zeros_like(t) for t in self.tex]
+        self.nws = R.ngp_workspace(self.cfg, self.sizes, device)
+        self.step = torch.zeros(1, dtype=torch.int32, device=device)
+        self.sse = torch.zeros(1, dtype=torch.float64, device=device)
+        self.history = torch.zeros(max_iters, dtype=torch.float64, device=device)
+        self.targets, self.lr, self.loss = targets, lr, loss
+        self.n_scalars = 3 * self.views.total_pixels
+        self.stream = torch.cuda.Stream(device=device)
+        self.graph: Optional[R.Graph] = None
+        with torch.cuda.stream(self.stream):
+            self.vis, self.ws = R.raster(self.layers, self.views, stream=self.stream)
+        self.stream.synchronize()
+
+    def _iteration(self):
+        s = self.stream
+        R.ngp_bake(self.params, self.cfg, self.sizes, tex=self.tex, stream=s)
+        with torch.cuda.stream(s):
+            for g in self.gtex:
+                g.zero_()
+        R.render_backward(self.layers, self.tex, self.views, self.vis, self.ws, grad_tex=self.gtex,
+                          target=self.targets, loss_scale=1.0 / self.n_scalars, sse=self.sse, loss=self.loss, stream=s)
+        R.ngp_backward(self.params, self.cfg, self.sizes, self.gtex, grad_params=self.gp, ws=self.nws, stream=s)
+        R.adam_step(self.params, self.gp, self.m, self.v, self.step, lr=self.lr, lo=-1e30, hi=1e30, sse=self.sse,
+                    history=self.history, stream=s)
+
+    def capture(self):
+        self.graph = R.Graph(self.stream)
+        with self.graph:
+            self._iteration()
+
+    def run(self, iters: int) -> float:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(self.stream)
+        for _ in range(iters):
+            if self.graph is not None:
+                self.graph.replay()
+            else:
+                self._iteration()
+        e1.record(self.stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / max(iters, 1)
+
+    def loss_history(self) -> np.ndarray:
+        self.stream.synchronize()
+        n = int(self.step.item())
+        return self.history[:min(n, self.history.numel())].cpu().numpy()
+
+
 def render_targets(meshes, cameras, textures: Sequence[np.ndarray], device="cuda") -> torch.Tensor:
     """Target images [sum_v H_v W_v, 4] rendered by the GPU path from ground-truth textures."""
     layers = R.Layers(meshes, device)
@@ -155,10 +226,33 @@ def main(argv=None):
     ap.add_argument("--modes", default="graph,per_view")
     ap.add_argument("--loss", default="l2", choices=["l2", "l1"])
     ap.add_argument("--quantize", action="store_true", help="fit logits of 8-bit quantised textures")
+    ap.add_argument("--neural", action="store_true",
+                    help="fit neural textures (hash grid + MLP baked at 1024^2 texel centres) instead of texels")
     args = ap.parse_args(argv)
     import scenes as S  # seeded synthetic inputs
     sc = S.make_config(5, n_views=args.views, resolution=(args.res, args.res))
     targets = render_targets(sc.layers, sc.cameras, sc.textures_gt)
+    if args.neural:
+        res = {"config": f"k={sc.k} shells, {args.views} views at {args.res}x{args.res}, {args.iters} Adam iterations, "
+                         f"{args.loss} loss, neural textures (8 levels 16..1024, 2^16 entries, MLP 64x64) baked at 1024^2"}
+        for mode in args.modes.split(","):
+            if mode not in ("graph", "eager"):
+                continue
+            fit = NeuralTextureFit(sc.layers, sc.cameras, targets, tex_size=sc.textures[0].shape[1],
+                                   loss=args.loss, max_iters=args.iters + 8)
+            if mode == "graph":
+                fit.capture()
+            ms = fit.run(args.iters)
+            h = fit.loss_history() / fit.n_scalars
+            curve = psnr_from_sse(fit.loss_history(), fit.n_scalars) if args.loss == "l2" else h
+            res[mode] = {"ms_per_iter": ms, "first": float(curve[0]), "last": float(curve[-1]),
+                         "curve": [round(float(x), 6) for x in curve]}
+            print(f"[fit] neural {mode}: {ms:.3f} ms/iter, {'PSNR' if args.loss == 'l2' else 'MAE'} "
+                  f"{curve[0]:.4f} -> {curve[-1]:.4f}", file=sys.stderr, flush=True)
+            del fit
+            torch.cuda.empty_cache()
+        print(json.dumps(res))
+        return
     res = {"config": f"k={sc.k} shells, {args.views} views at {args.res}x{args.res}, {args.iters} Adam iterations, "
                      f"{args.loss} loss" + (", 8-bit quantised logits" if args.quantize else "")}
     for mode in args.modes.split(","):
