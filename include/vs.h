@@ -355,17 +355,20 @@ size_t vs_ngp_workspace_bytes(const vs_ngp_config* cfg, int32_t k, const int32_t
 
 /* Bake: tex[l] (device f32 [height[l]][width[l]][4]) = the neural texture of
  * params[l] at every texel centre.  params, tex: host arrays [k] of device
- * pointers (16-byte aligned); width, height: host arrays [k], 1..VS_MAX_TEX_DIM. */
+ * pointers (16-byte aligned); width, height: host arrays [k], 1..VS_MAX_TEX_DIM.
+ * ws (device, vs_ngp_workspace_bytes, 256-byte aligned) may be NULL; when
+ * given, the network's per-texel activations are kept there for
+ * vs_ngp_backward. */
 vs_status vs_ngp_bake(const float* const* params, const vs_ngp_config* cfg, int32_t k, const int32_t* width,
-                      const int32_t* height, float* const* tex, void* stream);
+                      const int32_t* height, float* const* tex, void* ws, size_t ws_bytes, void* stream);
 
-/* Backward: given grad_tex[l] = dL/dtex[l] (device f32 [height][width][4]),
- * ACCUMULATES dL/dparams into grad_params[l] (device f32, vs_ngp_param_count
- * floats each; summation order not fixed: atomics).  ws: device workspace of
- * vs_ngp_workspace_bytes, 256-byte aligned. */
+/* Backward of the last vs_ngp_bake that was given this workspace (same
+ * params, sizes and textures tex): with grad_tex[l] = dL/dtex[l] (device f32
+ * [height][width][4]) it ACCUMULATES dL/dparams into grad_params[l] (device
+ * f32, vs_ngp_param_count floats each; summation order not fixed: atomics). */
 vs_status vs_ngp_backward(const float* const* params, const vs_ngp_config* cfg, int32_t k, const int32_t* width,
-                          const int32_t* height, const float* const* grad_tex, float* const* grad_params,
-                          void* ws, size_t ws_bytes, void* stream);
+                          const int32_t* height, const float* const* tex, const float* const* grad_tex,
+                          float* const* grad_params, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- HIP graphs: capture a sequence of the calls above on one stream ---- */
 typedef struct vs_graph_s* vs_graph;

@@ -92,8 +92,8 @@ SIGNATURES = {
                                       c_vp]),
     "vs_ngp_param_count": (ctypes.c_int64, [c_vp]),
     "vs_ngp_workspace_bytes": (c_sz, [c_vp, c_i32, c_vp, c_vp]),
-    "vs_ngp_bake": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp]),
-    "vs_ngp_backward": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "vs_ngp_bake": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "vs_ngp_backward": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "vs_graph_begin": (c_i32, [c_vp]),
     "vs_graph_end": (c_i32, [c_vp, c_vp]),
     "vs_graph_launch": (c_i32, [c_vp, c_vp]),

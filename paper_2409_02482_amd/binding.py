@@ -305,8 +305,9 @@ def _sizes(textures_hw):
     return (ctypes.c_int32 * k)(*[int(w) for w, h in textures_hw]), (ctypes.c_int32 * k)(*[int(h) for w, h in textures_hw])
 
 
-def ngp_bake(params, cfg: NgpConfig, sizes, tex=None, stream=None):
-    """vs_ngp_bake: RGBA textures [H, W, 4] of the neural textures params[l] at sizes[l] = (W, H)."""
+def ngp_bake(params, cfg: NgpConfig, sizes, tex=None, ws: Optional[torch.Tensor] = None, stream=None):
+    """vs_ngp_bake: RGBA textures [H, W, 4] of the neural textures params[l] at sizes[l] = (W, H);
+    with ws (ngp_workspace) the activations are kept for ngp_backward."""
     k = len(params)
     for l, p in enumerate(params):
         _dev(p, torch.float32, f"params[{l}]")
@@ -317,7 +318,9 @@ def ngp_bake(params, cfg: NgpConfig, sizes, tex=None, stream=None):
     ws_, hs_ = _sizes(sizes)
     keep = [(ctypes.c_void_p * k)(*[t.data_ptr() for t in a]) for a in (params, tex)]
     C.check(C.load().vs_ngp_bake(ctypes.addressof(keep[0]), ctypes.byref(cfg.c), k, ctypes.addressof(ws_),
-                                 ctypes.addressof(hs_), ctypes.addressof(keep[1]), _stream(stream)), "vs_ngp_bake")
+                                 ctypes.addressof(hs_), ctypes.addressof(keep[1]),
+                                 None if ws is None else ws.data_ptr(), 0 if ws is None else ws.numel(),
+                                 _stream(stream)), "vs_ngp_bake")
     return tex
 
 
@@ -328,22 +331,21 @@ def ngp_workspace(cfg: NgpConfig, sizes, device="cuda") -> torch.Tensor:
     return torch.empty(max(n, 256), dtype=torch.uint8, device=device)
 
 
-def ngp_backward(params, cfg: NgpConfig, sizes, grad_tex, grad_params=None, ws: Optional[torch.Tensor] = None,
-                 stream=None):
-    """vs_ngp_backward: accumulates dL/dparams (zeros if None) from dL/dtexture and returns it."""
+def ngp_backward(params, cfg: NgpConfig, sizes, tex, grad_tex, ws: torch.Tensor, grad_params=None, stream=None):
+    """vs_ngp_backward of the last ngp_bake given ws (with the same params and textures tex):
+    accumulates dL/dparams (zeros if None) from dL/dtexture and returns it."""
     k = len(params)
     if grad_params is None:
         grad_params = [torch.zeros_like(p) for p in params]
-    for name, arr in (("params", params), ("grad_tex", grad_tex), ("grad_params", grad_params)):
+    for name, arr in (("params", params), ("tex", tex), ("grad_tex", grad_tex), ("grad_params", grad_params)):
         for l, t in enumerate(arr):
             _dev(t, torch.float32, f"{name}[{l}]")
-    if ws is None:
-        ws = ngp_workspace(cfg, sizes, params[0].device)
     ws_, hs_ = _sizes(sizes)
-    keep = [(ctypes.c_void_p * k)(*[t.data_ptr() for t in a]) for a in (params, grad_tex, grad_params)]
+    keep = [(ctypes.c_void_p * k)(*[t.data_ptr() for t in a]) for a in (params, tex, grad_tex, grad_params)]
     C.check(C.load().vs_ngp_backward(ctypes.addressof(keep[0]), ctypes.byref(cfg.c), k, ctypes.addressof(ws_),
                                      ctypes.addressof(hs_), ctypes.addressof(keep[1]), ctypes.addressof(keep[2]),
-                                     ws.data_ptr(), ws.numel(), _stream(stream)), "vs_ngp_backward")
+                                     ctypes.addressof(keep[3]), ws.data_ptr(), ws.numel(), _stream(stream)),
+            "vs_ngp_backward")
     return grad_params
 
 

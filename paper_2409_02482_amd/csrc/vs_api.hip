@@ -715,12 +715,8 @@ vs_status ngp_table(const char* who, const float* const* params, int32_t k, cons
     const int64_t tiles = (int64_t)((width[l] + vs::kNgpTile - 1) / vs::kNgpTile) *
                           ((height[l] + vs::kNgpTile - 1) / vs::kNgpTile);
     T.block_off[l + 1] = T.block_off[l] + tiles;
-    T.texel_off[l + 1] = T.texel_off[l] + (int64_t)width[l] * height[l];
   }
-  for (int l = k + 1; l <= VS_MAX_LAYERS; ++l) {
-    T.block_off[l] = T.block_off[k];
-    T.texel_off[l] = T.texel_off[k];
-  }
+  for (int l = k + 1; l <= VS_MAX_LAYERS; ++l) T.block_off[l] = T.block_off[k];
   return VS_OK;
 }
 
@@ -728,18 +724,27 @@ struct NgpWs {
   size_t a1, a2, a3, d1, d2, d0, total;
 };
 
-NgpWs ngp_ws(const vs::NgpShape& S, int64_t texels) {
+// rows: 256 per texel tile of every layer
+NgpWs ngp_ws(const vs::NgpShape& S, int64_t rows) {
   NgpWs w;
   size_t off = 0;
   auto take = [&](size_t bytes) { const size_t o = off; off += (bytes + 255) / 256 * 256; return o; };
-  w.a1 = take((size_t)texels * (2 * S.levels + 1) * 4);
-  w.a2 = take((size_t)texels * (vs::kNgpHidden + 1) * 4);
-  w.a3 = take((size_t)texels * (vs::kNgpHidden + 1) * 4);
-  w.d1 = take((size_t)texels * vs::kNgpHidden * 4);
-  w.d2 = take((size_t)texels * vs::kNgpHidden * 4);
-  w.d0 = take((size_t)texels * vs::kNgpOut * 4);
+  w.a1 = take((size_t)rows * 2 * S.levels * 4);
+  w.a2 = take((size_t)rows * vs::kNgpHidden * 4);
+  w.a3 = take((size_t)rows * vs::kNgpHidden * 4);
+  w.d1 = take((size_t)rows * vs::kNgpHidden * 4);
+  w.d2 = take((size_t)rows * vs::kNgpHidden * 4);
+  w.d0 = take((size_t)rows * vs::kNgpOut * 4);
   w.total = off;
   return w;
+}
+
+int64_t ngp_rows(const int32_t* width, const int32_t* height, int32_t k) {
+  int64_t rows = 0;
+  for (int l = 0; l < k; ++l)
+    rows += (int64_t)((std::max(width[l], 0) + vs::kNgpTile - 1) / vs::kNgpTile) *
+            ((std::max(height[l], 0) + vs::kNgpTile - 1) / vs::kNgpTile) * 256;
+  return rows;
 }
 
 }  // namespace
@@ -754,13 +759,24 @@ extern "C" size_t vs_ngp_workspace_bytes(const vs_ngp_config* cfg, int32_t k, co
                                          const int32_t* height) {
   vs::NgpShape S;
   if (ngp_shape(cfg, S) || !width || !height || k < 1 || k > VS_MAX_LAYERS) return 0;
-  int64_t texels = 0;
-  for (int l = 0; l < k; ++l) texels += (int64_t)std::max(width[l], 0) * std::max(height[l], 0);
-  return ngp_ws(S, texels).total;
+  return ngp_ws(S, ngp_rows(width, height, k)).total;
+}
+
+vs::NgpStage ngp_stage(void* ws, const NgpWs& w, int64_t rows) {
+  char* base = (char*)ws;
+  vs::NgpStage G;
+  G.R = rows;
+  G.a1 = (float*)(base + w.a1);
+  G.a2 = (float*)(base + w.a2);
+  G.a3 = (float*)(base + w.a3);
+  G.d1 = (float*)(base + w.d1);
+  G.d2 = (float*)(base + w.d2);
+  G.d0 = (float*)(base + w.d0);
+  return G;
 }
 
 extern "C" vs_status vs_ngp_bake(const float* const* params, const vs_ngp_config* cfg, int32_t k, const int32_t* width,
-                                 const int32_t* height, float* const* tex, void* stream) {
+                                 const int32_t* height, float* const* tex, void* ws, size_t ws_bytes, void* stream) {
   vs::NgpShape S;
   vs::NgpTable T;
   vs_status st = ngp_shape(cfg, S);
@@ -771,24 +787,40 @@ extern "C" vs_status vs_ngp_bake(const float* const* params, const vs_ngp_config
     if (!tex[l] || (uintptr_t)tex[l] % 16) return fail(VS_ERR_ARG, "vs_ngp_bake: tex[%d] null or misaligned", l);
     T.tex[l] = tex[l];
   }
+  vs::NgpStage G;
+  std::memset(&G, 0, sizeof(G));
+  if (ws) {
+    const int64_t rows = T.block_off[k] * 256;
+    if (rows * vs::kNgpHidden >= ((int64_t)1 << 31)) return fail(VS_ERR_SIZE, "vs_ngp_bake: too many texels to stage");
+    const NgpWs w = ngp_ws(S, rows);
+    if ((st = check_ws(ws, ws_bytes, w.total))) return st;
+    G = ngp_stage(ws, w, rows);
+  }
   hipStream_t s = (hipStream_t)stream;
   const unsigned grid = (unsigned)T.block_off[k];
-  if (S.levels <= 8) hipLaunchKernelGGL(vs::k_ngp_bake<8>, dim3(grid), dim3(256), 0, s, T, S);
-  else hipLaunchKernelGGL(vs::k_ngp_bake<16>, dim3(grid), dim3(256), 0, s, T, S);
+  auto launch = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, T, S, G); };
+  if (S.levels <= 8) {
+    if (ws) launch(vs::k_ngp_bake<8, true>); else launch(vs::k_ngp_bake<8, false>);
+  } else {
+    if (ws) launch(vs::k_ngp_bake<16, true>); else launch(vs::k_ngp_bake<16, false>);
+  }
   if ((st = check_launch("vs_ngp_bake"))) return st;
   return ok();
 }
 
 extern "C" vs_status vs_ngp_backward(const float* const* params, const vs_ngp_config* cfg, int32_t k,
-                                     const int32_t* width, const int32_t* height, const float* const* grad_tex,
-                                     float* const* grad_params, void* ws, size_t ws_bytes, void* stream) {
+                                     const int32_t* width, const int32_t* height, const float* const* tex,
+                                     const float* const* grad_tex, float* const* grad_params, void* ws,
+                                     size_t ws_bytes, void* stream) {
   vs::NgpShape S;
   vs::NgpTable T;
   vs_status st = ngp_shape(cfg, S);
   if (st) return st;
   if ((st = ngp_table("vs_ngp_backward", params, k, width, height, T))) return st;
-  if (!grad_tex || !grad_params) return fail(VS_ERR_ARG, "vs_ngp_backward: null pointer");
+  if (!grad_tex || !grad_params || !tex) return fail(VS_ERR_ARG, "vs_ngp_backward: null pointer");
   for (int l = 0; l < k; ++l) {
+    if (!tex[l] || (uintptr_t)tex[l] % 16) return fail(VS_ERR_ARG, "vs_ngp_backward: tex[%d] null or misaligned", l);
+    T.tex[l] = const_cast<float*>(tex[l]);
     if (!grad_tex[l] || (uintptr_t)grad_tex[l] % 16)
       return fail(VS_ERR_ARG, "vs_ngp_backward: grad_tex[%d] null or misaligned", l);
     if (!grad_params[l] || (uintptr_t)grad_params[l] % 16)
@@ -796,42 +828,37 @@ extern "C" vs_status vs_ngp_backward(const float* const* params, const vs_ngp_co
     T.gtex[l] = grad_tex[l];
     T.gparams[l] = grad_params[l];
   }
-  const NgpWs w = ngp_ws(S, T.texel_off[k]);
+  const int64_t R = T.block_off[k] * 256;
+  if (R * vs::kNgpHidden >= ((int64_t)1 << 31)) return fail(VS_ERR_SIZE, "vs_ngp_backward: too many texels");
+  const NgpWs w = ngp_ws(S, R);
   if ((st = check_ws(ws, ws_bytes, w.total))) return st;
-  char* base = (char*)ws;
-  vs::NgpStage G;
-  G.a1 = (float*)(base + w.a1);
-  G.a2 = (float*)(base + w.a2);
-  G.a3 = (float*)(base + w.a3);
-  G.d1 = (float*)(base + w.d1);
-  G.d2 = (float*)(base + w.d2);
-  G.d0 = (float*)(base + w.d0);
+  const vs::NgpStage G = ngp_stage(ws, w, R);
   hipStream_t s = (hipStream_t)stream;
   const unsigned grid = (unsigned)T.block_off[k];
-  if (S.levels <= 8) hipLaunchKernelGGL(vs::k_ngp_texel_bwd<8>, dim3(grid), dim3(256), 0, s, T, S, G);
-  else hipLaunchKernelGGL(vs::k_ngp_texel_bwd<16>, dim3(grid), dim3(256), 0, s, T, S, G);
+  hipLaunchKernelGGL(vs::k_ngp_texel_bwd1, dim3(grid), dim3(256), 0, s, T, S, G);
+  if (S.levels <= 8) hipLaunchKernelGGL(vs::k_ngp_texel_bwd2<8>, dim3(grid), dim3(256), 0, s, T, S, G);
+  else hipLaunchKernelGGL(vs::k_ngp_texel_bwd2<16>, dim3(grid), dim3(256), 0, s, T, S, G);
   if ((st = check_launch("vs_ngp_backward"))) return st;
-  // weight products: per layer dW1 | db1 from (D1, [e|1]), dW2 | db2 from (D2, [h1|1]), dW3 | db3 from (D0, [h2|1])
+  // weight products: per layer dW1, db1 from (D1, e), dW2, db2 from (D2, h1), dW3, db3 from (D0, h2)
   vs::NgpGemm Q;
   std::memset(&Q, 0, sizeof(Q));
   const int nin = 2 * S.levels;
+  int64_t max_rows = 0;
   for (int l = 0; l < k; ++l) {
-    const int64_t r0 = T.texel_off[l], rows = T.texel_off[l + 1] - r0;
+    const int64_t r0 = T.block_off[l] * 256, rows = (T.block_off[l + 1] - T.block_off[l]) * 256;
+    max_rows = std::max(max_rows, rows);
     float* gp = grad_params[l];
     const int g0 = 3 * l;
-    Q.D[g0] = G.d1 + r0 * vs::kNgpHidden; Q.A[g0] = G.a1 + r0 * (nin + 1);
-    Q.gw[g0] = gp + S.o_w1; Q.gb[g0] = gp + S.o_b1; Q.M[g0] = vs::kNgpHidden; Q.N[g0] = nin + 1;
-    Q.D[g0 + 1] = G.d2 + r0 * vs::kNgpHidden; Q.A[g0 + 1] = G.a2 + r0 * (vs::kNgpHidden + 1);
-    Q.gw[g0 + 1] = gp + S.o_w2; Q.gb[g0 + 1] = gp + S.o_b2; Q.M[g0 + 1] = vs::kNgpHidden;
-    Q.N[g0 + 1] = vs::kNgpHidden + 1;
-    Q.D[g0 + 2] = G.d0 + r0 * vs::kNgpOut; Q.A[g0 + 2] = G.a3 + r0 * (vs::kNgpHidden + 1);
-    Q.gw[g0 + 2] = gp + S.o_w3; Q.gb[g0 + 2] = gp + S.o_b3; Q.M[g0 + 2] = vs::kNgpOut;
-    Q.N[g0 + 2] = vs::kNgpHidden + 1;
+    Q.D[g0] = G.d1 + r0; Q.A[g0] = G.a1 + r0; Q.gw[g0] = gp + S.o_w1; Q.gb[g0] = gp + S.o_b1;
+    Q.M[g0] = vs::kNgpHidden; Q.K[g0] = nin;
+    Q.D[g0 + 1] = G.d2 + r0; Q.A[g0 + 1] = G.a2 + r0; Q.gw[g0 + 1] = gp + S.o_w2; Q.gb[g0 + 1] = gp + S.o_b2;
+    Q.M[g0 + 1] = vs::kNgpHidden; Q.K[g0 + 1] = vs::kNgpHidden;
+    Q.D[g0 + 2] = G.d0 + r0; Q.A[g0 + 2] = G.a3 + r0; Q.gw[g0 + 2] = gp + S.o_w3; Q.gb[g0 + 2] = gp + S.o_b3;
+    Q.M[g0 + 2] = vs::kNgpOut; Q.K[g0 + 2] = vs::kNgpHidden;
     for (int q = 0; q < 3; ++q) Q.rows[g0 + q] = rows;
   }
+  Q.R = R;
   Q.n_gemm = 3 * k;
-  int64_t max_rows = 0;
-  for (int l = 0; l < k; ++l) max_rows = std::max(max_rows, T.texel_off[l + 1] - T.texel_off[l]);
   // enough blocks to fill the chip, each with at least a few 64-row tiles
   Q.blocks_per_gemm = (int32_t)std::max<int64_t>(1, std::min<int64_t>(256, max_rows / 512));
   hipLaunchKernelGGL(vs::k_ngp_wgrad, dim3((unsigned)(Q.n_gemm * Q.blocks_per_gemm)), dim3(256), 0, s, Q);

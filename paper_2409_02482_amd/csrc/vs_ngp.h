@@ -11,10 +11,10 @@
 // Parameters per layer, flat f32:
 //   tables [L][T][2] | W1 [64][2L] | b1 [64] | W2 [64][64] | b2 [64] | W3 [4][64] | b3 [4].
 // Weights are uniform across a block's texels and are read through scalar
-// loads (no LDS).  The backward pass writes, per texel, the layer inputs
-// (with a trailing 1) and the deltas to a workspace; the weight gradients are
-// then tall-skinny products over texels (k_ngp_wgrad), the biases coming out
-// of the trailing-1 column.
+// loads (no LDS).  The backward pass (two per-texel kernels, to keep each
+// one's registers, and so its occupancy, moderate) writes the layer inputs
+// and the deltas of every texel to a workspace; the weight gradients are then
+// tall-skinny products over texels (k_ngp_wgrad).
 #pragma once
 
 #include "vs_common.h"
@@ -34,7 +34,8 @@ struct NgpShape {
   int64_t o_w1, o_b1, o_w2, o_b2, o_w3, o_b3, total;   // o_tab = 0
 };
 
-// Per layer buffers and sizes; block_off / texel_off are prefix sums over layers.
+// Per layer buffers and sizes; block_off is the prefix sum of 256-texel tiles
+// over layers, and row block_off * 256 + thread is a texel's staging row.
 struct NgpTable {
   const float* params[kMaxLayers];
   float* tex[kMaxLayers];
@@ -42,18 +43,21 @@ struct NgpTable {
   float* gparams[kMaxLayers];
   int32_t w[kMaxLayers], h[kMaxLayers];
   int64_t block_off[kMaxLayers + 1];
-  int64_t texel_off[kMaxLayers + 1];
   int32_t k;
 };
 
-// Staging rows per texel (backward): A1 = [e | 1], A2 = [h1 | 1], A3 = [h2 | 1], D1, D2, DO.
+// Staging for the backward, feature-major [feature][R] over R = 256 * tiles
+// rows (every access of a wavefront, and every GEMM tile load, is then
+// consecutive): A1 = e, A2 = h1, A3 = h2, D1, D2, DO.  Rows of texels outside
+// the texture hold zeros.
 struct NgpStage {
-  float* a1;   // [texels][2L + 1]
-  float* a2;   // [texels][65]
-  float* a3;   // [texels][65]
-  float* d1;   // [texels][64]
-  float* d2;   // [texels][64]
-  float* d0;   // [texels][4]
+  float* a1;   // [2L][R]
+  float* a2;   // [64][R]
+  float* a3;   // [64][R]
+  float* d1;   // [64][R]
+  float* d2;   // [64][R]
+  float* d0;   // [4][R]
+  int64_t R;
 };
 
 __device__ inline uint32_t ngp_index(uint32_t x, uint32_t y, int32_t N, int32_t dense, uint32_t mask) {
@@ -64,7 +68,8 @@ struct NgpTexel {
   int l;
   int32_t i, j;
   bool valid;
-  int64_t t;   // texel index within the layer, j W + i
+  int64_t t;     // texel index within the layer, j W + i
+  int64_t row;   // staging row
 };
 
 __device__ inline NgpTexel ngp_texel(const NgpTable& T) {
@@ -81,6 +86,7 @@ __device__ inline NgpTexel ngp_texel(const NgpTable& T) {
   r.j = ty * kNgpTile + (threadIdx.x >> 4);
   r.valid = r.i < W && r.j < H;
   r.t = (int64_t)r.j * W + r.i;
+  r.row = b * 256 + threadIdx.x;
   return r;
 }
 
@@ -152,26 +158,49 @@ __device__ inline void ngp_mlp(const float* __restrict__ P, const NgpShape& S, c
   }
 }
 
-// texture = sigmoid(MLP(encoding)) at every texel centre of every layer.
-template <int LMAX>
-__global__ void __launch_bounds__(256) k_ngp_bake(NgpTable T, NgpShape S) {
+// texture = sigmoid(MLP(encoding)) at every texel centre of every layer; with
+// STAGE the layer inputs [e | 1], [h1 | 1], [h2 | 1] are kept for the backward.
+template <int LMAX, bool STAGE>
+__global__ void __launch_bounds__(256) k_ngp_bake(NgpTable T, NgpShape S, NgpStage G) {
   const NgpTexel x = ngp_texel(T);
-  if (!x.valid) return;
-  const float* P = T.params[x.l];
-  const double u = ((double)x.i + 0.5) / (double)T.w[x.l], v = ((double)x.j + 0.5) / (double)T.h[x.l];
+  if (!x.valid) {
+    if (STAGE) {
+      const uint32_t r = (uint32_t)x.row, R = (uint32_t)G.R;
+      for (int q = 0; q < 2 * S.levels; ++q) G.a1[q * R + r] = 0.f;
+      for (int j = 0; j < kNgpHidden; ++j) G.a2[j * R + r] = 0.f, G.a3[j * R + r] = 0.f;
+    }
+    return;
+  }
+  const int l = x.l;
+  const float* P = T.params[l];
+  const double u = ((double)x.i + 0.5) / (double)T.w[l], v = ((double)x.j + 0.5) / (double)T.h[l];
   float e[2 * LMAX];
   uint32_t idx[LMAX][4];
   float wt[LMAX][4];
   ngp_encode<LMAX>(P, S, u, v, e, idx, wt);
   float h1[kNgpHidden], z2[kNgpHidden], o[kNgpOut];
   ngp_mlp<LMAX>(P, S, e, h1, z2, o);
-  reinterpret_cast<float4*>(T.tex[x.l])[x.t] =
+  reinterpret_cast<float4*>(T.tex[l])[x.t] =
       make_float4(ngp_sigmoid(o[0]), ngp_sigmoid(o[1]), ngp_sigmoid(o[2]), ngp_sigmoid(o[3]));
+  if (STAGE) {
+    // 32-bit element offsets (the workspace holds < 2^31 floats per array): one base + offset each
+    const int nin = 2 * S.levels;
+    const uint32_t r = (uint32_t)x.row, R = (uint32_t)G.R;
+#pragma unroll
+    for (int q = 0; q < 2 * LMAX; ++q)
+      if (q < nin) G.a1[q * R + r] = e[q];
+#pragma unroll
+    for (int j = 0; j < kNgpHidden; ++j) {
+      G.a2[j * R + r] = h1[j];
+      G.a3[j * R + r] = fmaxf(z2[j], 0.0f);
+    }
+  }
 }
 
-// Adds v into grad[q] for every lane, summing lanes that share q first when the
-// level is coarse (many texels per cell): one leader per distinct index and
-// round, the others' values reduced across the wavefront.
+// Adds (v0, v1) into the feature pair q of a table for every active lane,
+// summing lanes that share q first when the level is coarse (many texels per
+// cell): one leader per distinct index and round, the others' values reduced
+// across the wavefront.
 __device__ inline void ngp_table_add(float* __restrict__ g, uint32_t q, float v0, float v1, bool active, bool merge) {
   if (!merge) {
     if (active) {
@@ -198,66 +227,59 @@ __device__ inline void ngp_table_add(float* __restrict__ g, uint32_t q, float v0
   }
 }
 
-// Backward, per texel: recompute the forward, form the deltas
-//   do = dL/dtex * s (1 - s), d2 = (W3^T do) [z2 > 0], d1 = (W2^T d2) [z1 > 0], de = W1^T d1,
-// scatter de into the hash tables (bilinear weights), and stage [e|1], [h1|1],
-// [h2|1], d1, d2, do for the weight products.
-template <int LMAX>
-__global__ void __launch_bounds__(256) k_ngp_texel_bwd(NgpTable T, NgpShape S, NgpStage G) {
+// Backward, first half, per texel (after a staging bake of the same
+// parameters): do = dL/dtex * t (1 - t) from the baked texel t, and
+// d2 = (W3^T do) [h2 > 0] (h2 > 0 exactly where z2 > 0); both staged.
+__global__ void __launch_bounds__(256) k_ngp_texel_bwd1(NgpTable T, NgpShape S, NgpStage G) {
 #pragma clang fp contract(fast)
   const NgpTexel x = ngp_texel(T);
   const int l = x.l;
   const float* P = T.params[l];
-  const double u = ((double)x.i + 0.5) / (double)T.w[l], v = ((double)x.j + 0.5) / (double)T.h[l];
-  float e[2 * LMAX];
-  uint32_t idx[LMAX][4];
-  float wt[LMAX][4];
-  float h1[kNgpHidden], z2[kNgpHidden], o[kNgpOut];
-  float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+  const uint32_t r = (uint32_t)x.row, R = (uint32_t)G.R;
+  float d0[4] = {0.f, 0.f, 0.f, 0.f};
   if (x.valid) {
-    ngp_encode<LMAX>(P, S, u, v, e, idx, wt);
-    ngp_mlp<LMAX>(P, S, e, h1, z2, o);
-    g = reinterpret_cast<const float4*>(T.gtex[l])[x.t];
-  } else {
-#pragma unroll
-    for (int q = 0; q < 2 * LMAX; ++q) e[q] = 0.f;
-#pragma unroll
-    for (int q = 0; q < kNgpHidden; ++q) { h1[q] = 0.f; z2[q] = 0.f; }
-#pragma unroll
-    for (int c = 0; c < kNgpOut; ++c) o[c] = 0.f;
-#pragma unroll
-    for (int lv = 0; lv < LMAX; ++lv)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) { idx[lv][c] = 0; wt[lv][c] = 0.f; }
-  }
-  float d0[kNgpOut];
-  const float gv[4] = {g.x, g.y, g.z, g.w};
-#pragma unroll
-  for (int c = 0; c < kNgpOut; ++c) {
-    const float s = ngp_sigmoid(o[c]);
-    d0[c] = gv[c] * s * (1.0f - s);
+    const float4 g = reinterpret_cast<const float4*>(T.gtex[l])[x.t];
+    const float4 t = reinterpret_cast<const float4*>(T.tex[l])[x.t];
+    d0[0] = g.x * t.x * (1.0f - t.x); d0[1] = g.y * t.y * (1.0f - t.y);
+    d0[2] = g.z * t.z * (1.0f - t.z); d0[3] = g.w * t.w * (1.0f - t.w);
   }
   const float* W3 = P + S.o_w3;
-  float d2[kNgpHidden];
 #pragma unroll
   for (int j = 0; j < kNgpHidden; ++j) {
     float acc = 0.f;
 #pragma unroll
     for (int c = 0; c < kNgpOut; ++c) acc += W3[c * kNgpHidden + j] * d0[c];
-    d2[j] = z2[j] > 0.0f ? acc : 0.0f;
+    G.d2[j * R + r] = G.a3[j * R + r] > 0.0f ? acc : 0.0f;
   }
-  const float* W2 = P + S.o_w2;
+#pragma unroll
+  for (int c = 0; c < kNgpOut; ++c) G.d0[c * R + r] = d0[c];
+}
+
+// Backward, second half, per texel: d1 = (W2^T d2) [h1 > 0] (staged), de = W1^T d1,
+// and de scattered into the hash tables through the encoding's corners and weights.
+template <int LMAX>
+__global__ void __launch_bounds__(256) k_ngp_texel_bwd2(NgpTable T, NgpShape S, NgpStage G) {
+#pragma clang fp contract(fast)
+  const NgpTexel x = ngp_texel(T);
+  const int l = x.l;
+  const float* P = T.params[l];
+  const int nin = 2 * S.levels;
+  const uint32_t r = (uint32_t)x.row, R = (uint32_t)G.R;
   float d1[kNgpHidden];
 #pragma unroll
   for (int q = 0; q < kNgpHidden; ++q) d1[q] = 0.f;
+  const float* W2 = P + S.o_w2;
 #pragma unroll
   for (int j = 0; j < kNgpHidden; ++j) {
+    const float d = G.d2[j * R + r];   // zero outside the texture
 #pragma unroll
-    for (int q = 0; q < kNgpHidden; ++q) d1[q] += W2[j * kNgpHidden + q] * d2[j];
+    for (int q = 0; q < kNgpHidden; ++q) d1[q] += W2[j * kNgpHidden + q] * d;
   }
 #pragma unroll
-  for (int q = 0; q < kNgpHidden; ++q) d1[q] = h1[q] > 0.0f ? d1[q] : 0.0f;
-  const int nin = 2 * S.levels;
+  for (int q = 0; q < kNgpHidden; ++q) {
+    d1[q] = G.a2[q * R + r] > 0.0f ? d1[q] : 0.0f;
+    G.d1[q * R + r] = d1[q];
+  }
   const float* W1 = P + S.o_w1;
   float de[2 * LMAX];
 #pragma unroll
@@ -269,99 +291,97 @@ __global__ void __launch_bounds__(256) k_ngp_texel_bwd(NgpTable T, NgpShape S, N
     }
     de[q] = acc;
   }
-  // hash-table gradients
-  const uint32_t TT = 1u << S.log2_table;
+  // the encoding's corners and weights (no table reads needed)
+  const double u = ((double)x.i + 0.5) / (double)T.w[l], v = ((double)x.j + 0.5) / (double)T.h[l];
+  const uint32_t TT = 1u << S.log2_table, mask = TT - 1u;
   float* gtab = T.gparams[l];
 #pragma unroll
   for (int lv = 0; lv < LMAX; ++lv) {
     if (lv >= S.levels) continue;
+    const int32_t N = S.res[lv];
+    const double xx = u * (double)N, yy = v * (double)N;
+    const double x0 = floor(xx), y0 = floor(yy);
+    const float fx = (float)(xx - x0), fy = (float)(yy - y0);
+    const uint32_t xi = (uint32_t)x0, yi = (uint32_t)y0;
     // several texels per cell: merge equal vertices across the wavefront first
-    const bool merge = (int64_t)4 * S.res[lv] <= (int64_t)min(T.w[l], T.h[l]);
+    const bool merge = (int64_t)4 * N <= (int64_t)min(T.w[l], T.h[l]);
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-      ngp_table_add(gtab + (int64_t)lv * TT * 2, idx[lv][c], wt[lv][c] * de[2 * lv], wt[lv][c] * de[2 * lv + 1],
-                    x.valid, merge);
+    for (int c = 0; c < 4; ++c) {
+      const uint32_t dx = c & 1, dy = c >> 1;
+      const uint32_t q = x.valid ? ngp_index(xi + dx, yi + dy, N, S.dense[lv], mask) : 0u;
+      const float w = (dx ? fx : 1.0f - fx) * (dy ? fy : 1.0f - fy);
+      ngp_table_add(gtab + (int64_t)lv * TT * 2, q, w * de[2 * lv], w * de[2 * lv + 1], x.valid, merge);
+    }
   }
-  if (!x.valid) return;
-  // staging rows
-  const int64_t r = T.texel_off[l] + x.t;
-  float* a1 = G.a1 + r * (nin + 1);
-#pragma unroll
-  for (int q = 0; q < 2 * LMAX; ++q)
-    if (q < nin) a1[q] = e[q];
-  a1[nin] = 1.0f;
-  float* a2 = G.a2 + r * (kNgpHidden + 1);
-  float* a3 = G.a3 + r * (kNgpHidden + 1);
-  float* dd1 = G.d1 + r * kNgpHidden;
-  float* dd2 = G.d2 + r * kNgpHidden;
-#pragma unroll
-  for (int q = 0; q < kNgpHidden; ++q) {
-    a2[q] = h1[q];
-    a3[q] = fmaxf(z2[q], 0.0f);
-    dd1[q] = d1[q];
-    dd2[q] = d2[q];
-  }
-  a2[kNgpHidden] = 1.0f;
-  a3[kNgpHidden] = 1.0f;
-  *reinterpret_cast<float4*>(G.d0 + r * kNgpOut) = make_float4(d0[0], d0[1], d0[2], d0[3]);
 }
 
-// One weight-gradient product of one layer: C[m][n] = sum_r D[r][m] A[r][n]
-// over the layer's texel rows, m < M (<= 64), n < N (<= 65, last column the
-// bias).  Blocks split the rows; each thread owns outputs m = tid / 4,
-// n = tid % 4 + 4 q; partial sums are added to the gradient (weights
-// row-major [M][N - 1], then the bias [M]).
+// One weight-gradient product of one layer: C[m][n] = sum_r D[m][r] A[n][r]
+// over the layer's staging rows (feature-major, row stride R), m < M (<= 64),
+// n < K (<= 64); the bias gradient is sum_r D[m][r].  Blocks split the rows;
+// each thread owns a 4 x 4 tile of outputs (m = 4 (tid / 16) ..,
+// n = 4 (tid % 16) ..) and the threads of the first column tile also the 4
+// bias sums; partial sums are added to the gradient (weights row-major
+// [M][K], then the bias [M]).
 struct NgpGemm {
   const float* D[3 * kMaxLayers];
   const float* A[3 * kMaxLayers];
   float* gw[3 * kMaxLayers];
   float* gb[3 * kMaxLayers];
   int64_t rows[3 * kMaxLayers];
-  int32_t M[3 * kMaxLayers], N[3 * kMaxLayers];
+  int32_t M[3 * kMaxLayers], K[3 * kMaxLayers];
+  int64_t R;
   int32_t n_gemm, blocks_per_gemm;
 };
 
 __global__ void __launch_bounds__(256) k_ngp_wgrad(NgpGemm Q) {
-  __shared__ float sD[64][64];
-  __shared__ float sA[64][66];
+#pragma clang fp contract(fast)
+  __shared__ __align__(16) float sD[64][64];
+  __shared__ __align__(16) float sA[64][64];
   const int gi = blockIdx.x / Q.blocks_per_gemm, part = blockIdx.x - gi * Q.blocks_per_gemm;
   if (gi >= Q.n_gemm) return;
-  const int M = Q.M[gi], N = Q.N[gi];
-  const int64_t rows = Q.rows[gi];
-  const int64_t per = (rows + Q.blocks_per_gemm - 1) / Q.blocks_per_gemm;
+  const int M = Q.M[gi], K = Q.K[gi];
+  const int64_t rows = Q.rows[gi], R = Q.R;
+  const int64_t per = ((rows + Q.blocks_per_gemm - 1) / Q.blocks_per_gemm + 63) / 64 * 64;
   const int64_t r0 = (int64_t)part * per, r1 = min(rows, r0 + per);
-  const int tid = threadIdx.x, m = tid >> 2, n0 = tid & 3;
-  float acc[17];
+  const int tid = threadIdx.x, mb = (tid >> 4) * 4, nb = (tid & 15) * 4;
+  float acc[4][4], bacc[4];
 #pragma unroll
-  for (int q = 0; q < 17; ++q) acc[q] = 0.f;
+  for (int a = 0; a < 4; ++a) {
+    bacc[a] = 0.f;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.f;
+  }
   for (int64_t rb = r0; rb < r1; rb += 64) {
     const int nr = (int)min((int64_t)64, r1 - rb);
     __syncthreads();
     for (int p = tid; p < 64 * 64; p += 256) {
-      const int rr = p >> 6, cc = p & 63;
-      sD[rr][cc] = (rr < nr && cc < M) ? Q.D[gi][(rb + rr) * M + cc] : 0.f;
-    }
-    for (int p = tid; p < 64 * 66; p += 256) {
-      const int rr = p / 66, cc = p - rr * 66;
-      sA[rr][cc] = (rr < nr && cc < N) ? Q.A[gi][(rb + rr) * N + cc] : 0.f;
+      const int rr = p & 63, cc = p >> 6;   // consecutive threads read consecutive rows of one feature
+      sD[rr][cc] = (rr < nr && cc < M) ? Q.D[gi][cc * R + rb + rr] : 0.f;
+      sA[rr][cc] = (rr < nr && cc < K) ? Q.A[gi][cc * R + rb + rr] : 0.f;
     }
     __syncthreads();
     for (int rr = 0; rr < nr; ++rr) {
-      const float d = sD[rr][m];
+      const float4 d = *reinterpret_cast<const float4*>(&sD[rr][mb]);
+      const float4 av = *reinterpret_cast<const float4*>(&sA[rr][nb]);
+      const float dv[4] = {d.x, d.y, d.z, d.w}, aw[4] = {av.x, av.y, av.z, av.w};
 #pragma unroll
-      for (int q = 0; q < 17; ++q) {
-        const int n = n0 + 4 * q;
-        if (n < 66) acc[q] += d * sA[rr][n];
+      for (int a = 0; a < 4; ++a) {
+        bacc[a] += dv[a];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] += dv[a] * aw[b];
       }
     }
   }
-  if (m >= M) return;
 #pragma unroll
-  for (int q = 0; q < 17; ++q) {
-    const int n = n0 + 4 * q;
-    if (n >= N || acc[q] == 0.0f) continue;
-    if (n < N - 1) unsafeAtomicAdd(Q.gw[gi] + (int64_t)m * (N - 1) + n, acc[q]);
-    else unsafeAtomicAdd(Q.gb[gi] + m, acc[q]);
+  for (int a = 0; a < 4; ++a) {
+    const int m = mb + a;
+    if (m >= M) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int n = nb + b;
+      if (n < K && acc[a][b] != 0.0f) unsafeAtomicAdd(Q.gw[gi] + (int64_t)m * K + n, acc[a][b]);
+    }
+    if (nb == 0 && bacc[a] != 0.0f) unsafeAtomicAdd(Q.gb[gi] + m, bacc[a]);
   }
 }
 

@@ -173,13 +173,13 @@ class NeuralTextureFit:
 
     def _iteration(self):
         s = self.stream
-        R.ngp_bake(self.params, self.cfg, self.sizes, tex=self.tex, stream=s)
+        R.ngp_bake(self.params, self.cfg, self.sizes, tex=self.tex, ws=self.nws, stream=s)
         with torch.cuda.stream(s):
             for g in self.gtex:
                 g.zero_()
         R.render_backward(self.layers, self.tex, self.views, self.vis, self.ws, grad_tex=self.gtex,
                           target=self.targets, loss_scale=1.0 / self.n_scalars, sse=self.sse, loss=self.loss, stream=s)
-        R.ngp_backward(self.params, self.cfg, self.sizes, self.gtex, grad_params=self.gp, ws=self.nws, stream=s)
+        R.ngp_backward(self.params, self.cfg, self.sizes, self.tex, self.gtex, self.nws, grad_params=self.gp, stream=s)
         R.adam_step(self.params, self.gp, self.m, self.v, self.step, lr=self.lr, lo=-1e30, hi=1e30, sse=self.sse,
                     history=self.history, stream=s)
 

@@ -48,6 +48,9 @@ def test_ngp_bake_matches_oracle(torch_cuda, case):
     torch = torch_cuda
     P, cfg, ocfg, params, dev, sizes = _setup(torch, case)
     tex = P.ngp_bake(dev, cfg, sizes)
+    staged = P.ngp_bake(dev, cfg, sizes, ws=P.ngp_workspace(cfg, sizes))
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(tex, staged))
     torch.cuda.synchronize()
     for l, (w, h) in enumerate(sizes):
         want = N.bake(params[l].astype(np.float64), ocfg, w, h)
@@ -62,7 +65,9 @@ def test_ngp_backward_matches_oracle(torch_cuda, case):
     P, cfg, ocfg, params, dev, sizes = _setup(torch, case)
     rng = np.random.default_rng(40)
     gt = [rng.uniform(-1, 1, (h, w, 4)).astype(np.float32) for w, h in sizes]
-    grads = P.ngp_backward(dev, cfg, sizes, [torch.from_numpy(g).cuda() for g in gt])
+    ws = P.ngp_workspace(cfg, sizes)
+    tex = P.ngp_bake(dev, cfg, sizes, ws=ws)
+    grads = P.ngp_backward(dev, cfg, sizes, tex, [torch.from_numpy(g).cuda() for g in gt], ws)
     torch.cuda.synchronize()
     lay = N.param_layout(ocfg)
     for l, (w, h) in enumerate(sizes):
@@ -99,11 +104,11 @@ def test_ngp_texture_fit_through_renderer(torch_cuda):
     hist = torch.zeros(64, dtype=torch.float64, device="cuda")
     scale = 1.0 / (3 * views.total_pixels)
     for it in range(40):
-        tex = P.ngp_bake(params, cfg, sizes)
+        tex = P.ngp_bake(params, cfg, sizes, ws=nws)
         for g in gt_tex:
             g.zero_()
         P.render_backward(layers, tex, views, vis, ws, grad_tex=gt_tex, target=target, loss_scale=scale, sse=sse)
-        P.ngp_backward(params, cfg, sizes, gt_tex, grad_params=gp, ws=nws)
+        P.ngp_backward(params, cfg, sizes, tex, gt_tex, nws, grad_params=gp)
         P.adam_step(params, gp, m, v, step, lr=1e-2, lo=-1e30, hi=1e30, sse=sse, history=hist)
     torch.cuda.synchronize()
     h = hist[:40].cpu().numpy()
