@@ -46,7 +46,7 @@ def test_struct_layouts_match_c(C, tmp_path):
                     'sizeof(vs_texture), sizeof(vs_camera), sizeof(vs_view), sizeof(vs_views), sizeof(vs_raster_opts),'
                     'sizeof(vs_shade_opts), offsetof(vs_view, pix_offset), offsetof(vs_shade_opts, target),'
                     'offsetof(vs_raster_opts, list_capacity), sizeof(vs_sh_texture), sizeof(vs_sh_opts),'
-                    'offsetof(vs_sh_opts, view_alpha));'
+                    'offsetof(vs_sh_opts, view_alpha)); printf("%zu\\n", sizeof(vs_ngp_config));'
                     'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
@@ -55,7 +55,7 @@ def test_struct_layouts_match_c(C, tmp_path):
             ctypes.sizeof(C.VsView), ctypes.sizeof(C.VsViews), ctypes.sizeof(C.VsRasterOpts),
             ctypes.sizeof(C.VsShadeOpts), C.VsView.pix_offset.offset, C.VsShadeOpts.target.offset,
             C.VsRasterOpts.list_capacity.offset, ctypes.sizeof(C.VsShTexture), ctypes.sizeof(C.VsShOpts),
-            C.VsShOpts.view_alpha.offset]
+            C.VsShOpts.view_alpha.offset, ctypes.sizeof(C.VsNgpConfig)]
     assert got == want
 
 
@@ -185,6 +185,32 @@ def test_render_sh_validation_without_gpu(C):
     tex[0].height = 0
     assert call(C.VsShOpts(-15.0, 15.0, 0.0, 0, 3, 1)) == C.VS_ERR_SIZE
     assert b"SH texture 0" in L.vs_last_error()
+
+
+def test_ngp_host_calls(C):
+    """Parameter count and workspace size are host-only; bad configurations are refused without a GPU."""
+    from oracle import ngp as N
+    L = C.load()
+    res = [4, 8, 18, 40]
+    cfg = C.VsNgpConfig(4, 8, (ctypes.c_int32 * 16)(*(res + [0] * 12)))
+    assert L.vs_ngp_param_count(ctypes.byref(cfg)) == N.param_count(N.NgpConfig(res, 8))
+    w = (ctypes.c_int32 * 2)(40, 33)
+    h = (ctypes.c_int32 * 2)(24, 47)
+    # 256 staging rows per 16 x 16 tile: (3*2 + 3*3) tiles; 2L + 64*4 + 4 floats per row, 256-byte rounded
+    nbytes = L.vs_ngp_workspace_bytes(ctypes.byref(cfg), 2, ctypes.addressof(w), ctypes.addressof(h))
+    rows = (3 * 2 + 3 * 3) * 256
+    assert nbytes >= rows * (8 + 4 * 64 + 4) * 4
+    bad = C.VsNgpConfig(0, 8, (ctypes.c_int32 * 16)())
+    assert L.vs_ngp_param_count(ctypes.byref(bad)) == -1
+    bad = C.VsNgpConfig(2, 30, (ctypes.c_int32 * 16)(4, 8))
+    assert L.vs_ngp_param_count(ctypes.byref(bad)) == -1
+    p = (ctypes.c_void_p * 2)(0x10000, 0x20000)
+    t = (ctypes.c_void_p * 2)(0x30000, None)
+    assert L.vs_ngp_bake(ctypes.addressof(p), ctypes.byref(cfg), 2, ctypes.addressof(w), ctypes.addressof(h),
+                         ctypes.addressof(t), None, 0, None) == C.VS_ERR_ARG
+    w[0] = 0
+    assert L.vs_ngp_bake(ctypes.addressof(p), ctypes.byref(cfg), 2, ctypes.addressof(w), ctypes.addressof(h),
+                         ctypes.addressof(t), None, 0, None) == C.VS_ERR_SIZE
 
 
 def test_status_strings(C):
