@@ -42,6 +42,7 @@ P_UPSTREAM = 6
 P_PICK = 7
 P_SH = 8
 P_NGP = 9
+P_KSDF = 10
 
 Z_NEAR = 0.01
 
@@ -440,6 +441,62 @@ def ngp_params(config: int, layer: int, levels: int, log2_table: int, hidden: in
              rng.normal(0.0, 1.0 / np.sqrt(hidden), hidden * hidden), 0.1 * rng.normal(size=hidden),
              rng.normal(0.0, 1.0 / np.sqrt(hidden), out * hidden), 0.1 * rng.normal(size=out)]
     return np.concatenate(parts).astype(np.float32)
+
+
+@dataclasses.dataclass
+class KsdfGrids:
+    """Fields of a k-SDF on the cube [lo, hi]^3 given at grid vertices ([z][y][x] order).
+
+    ``sdf`` f32 [(R+1)^3] is the main signed distance (positive outside);
+    ``rgba`` f32 [(Ra+1)^3, 4] is straight RGB plus the transparency field.
+    """
+    sdf: np.ndarray
+    sdf_res: int
+    rgba: np.ndarray
+    rgba_res: int
+    lo: float
+    hi: float
+
+
+def _grid_points(res: int, lo: float, hi: float) -> np.ndarray:
+    ax = lo + (hi - lo) * np.arange(res + 1) / res
+    z, y, x = np.meshgrid(ax, ax, ax, indexing="ij")
+    return np.stack([x.reshape(-1), y.reshape(-1), z.reshape(-1)], -1)
+
+
+def ksdf_grids(config: int, sdf_res: int, rgba_res: int, lo: float = -1.25, hi: float = 1.25,
+               amp: float = 0.05) -> KsdfGrids:
+    """The displaced sphere |x| - (1 + amp s(x/|x|)) of the shell scenes as a vertex grid, and a smooth RGBA field.
+
+    Appearance per channel: 0.5 + 0.5 (1/6) sum_m sin(<f_m, x> + phi_m) with
+    |f_m| in [2, 8]; the transparency channel is mapped to [0.1, 0.9].
+    """
+    p = _grid_points(sdf_res, lo, hi)
+    r = np.linalg.norm(p, axis=1)
+    dirs = np.where(r[:, None] > 0, p / np.maximum(r, 1e-300)[:, None], np.array([0.0, 1.0, 0.0]))
+    sdf = (r - (1.0 + amp * sine_field(config)(dirs))).astype(np.float32)
+    q = _grid_points(rgba_res, lo, hi)
+    rng = np.random.default_rng([config, P_KSDF, 0])
+    rgba = np.empty((q.shape[0], 4), np.float32)
+    for ch in range(4):
+        f = rng.normal(size=(6, 3))
+        f *= (rng.uniform(2.0, 8.0, 6) / np.linalg.norm(f, axis=1))[:, None]
+        ph = rng.uniform(0.0, 2 * np.pi, 6)
+        val = 0.5 + 0.5 * np.sin(q @ f.T + ph).mean(axis=1)
+        rgba[:, ch] = 0.1 + 0.8 * val if ch == 3 else val
+    return KsdfGrids(sdf, sdf_res, rgba, rgba_res, lo, hi)
+
+
+def affine_grid(res: int, lo: float, hi: float, coef: Sequence[float]) -> np.ndarray:
+    """f32 [(res+1)^3] vertex values of a + b x + c y + d z (grid values of an affine field)."""
+    p = _grid_points(res, lo, hi)
+    return (coef[0] + p @ np.asarray(coef[1:4], np.float64)).astype(np.float32)
+
+
+def ksdf_offsets(k: int, beta: float) -> List[float]:
+    """Support shells inside the main surface at multiples of the logistic standard deviation pi / (sqrt(3) beta)."""
+    step = math.pi / (math.sqrt(3.0) * beta)
+    return [j * step for j in range(k)]
 
 
 def uniform_targets(config: int, cams: Sequence[Camera]) -> List[np.ndarray]:
