@@ -370,6 +370,82 @@ vs_status vs_ngp_backward(const float* const* params, const vs_ngp_config* cfg, 
                           const int32_t* height, const float* const* tex, const float* const* grad_tex,
                           float* const* grad_params, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- k-SDF volume rendering (Sec. 4.1 "k-SDF", Sec. 4.2 "Surfaces
+ *      Blending", Sec. 4.4 "Occupancy Grid" and "Importance Sampling";
+ *      supplement "Points sampling") ----
+ * The implicit stage renders k nested surfaces d_j = d + o_j of a main signed
+ * distance d (positive outside) by NeuS quadrature along each pixel ray and
+ * blends them in fixed order, surface 0 (the outermost) first.  The fields are
+ * given on vertex grids over the cube [lo, hi]^3 and read trilinearly: a grid
+ * of resolution R has (R+1)^3 vertices in [z][y][x] order, spacing
+ * h = (hi - lo)/R; a point p reads cell coordinate c = (p - lo)/h clamped to
+ * [0, R], base vertex min(floor(c), R - 1), weights c - base. */
+#define VS_KSDF_MAX_SURFACES 16
+#define VS_KSDF_MAX_SAMPLES 128
+typedef struct vs_ksdf_field {
+  const float* sdf;     /* device, [(sdf_res+1)^3]: main signed distance d */
+  const float* rgba;    /* device, 16-byte aligned, [(rgba_res+1)^3][4]: straight RGB and transparency */
+  int32_t sdf_res;      /* 1..1024 */
+  int32_t rgba_res;     /* 1..1024 */
+  double lo, hi;        /* lo < hi */
+} vs_ksdf_field;
+
+/* Options of the k-SDF calls.
+ * k, offsets:   surfaces d + offsets[j], offsets non-decreasing (positive offsets lie inside).
+ * beta:         logistic kernel size; density phi(x) = beta e^{-beta x} / (1 + e^{-beta x})^2 (Eq. 2),
+ *               CDF Phi(x) = 1 / (1 + e^{-beta x}).
+ * occ_threshold, occ_res: a voxel of the occ_res^3 grid over the cube is occupied iff for some j,
+ *               phi(max(|d_j(centre)| - sqrt(3) h_o / 2, 0)) > occ_threshold (decided in FP64).
+ * n_uniform:    samples placed uniformly in the occupied part of each ray.
+ * n_importance: samples added by two importance rounds of n_importance/2 each (kernel size beta/2,
+ *               then beta); n_uniform + n_importance <= VS_KSDF_MAX_SAMPLES.
+ * march_steps:  equal steps over the ray's interval in the cube that resolve its occupied part
+ *               (a step is occupied iff the voxel holding its midpoint is); multiple of 64, <= 2048.
+ * pdf_floor:    added to every interval weight before the importance pdf is normalised.
+ * normal_eps:   central-difference step of the SDF normals. */
+typedef struct vs_ksdf_opts {
+  int32_t k;                                 /* 1..VS_KSDF_MAX_SURFACES */
+  double offsets[VS_KSDF_MAX_SURFACES];
+  double beta;                               /* > 0 */
+  double occ_threshold;                      /* > 0 */
+  int32_t occ_res;                           /* 1..1024 */
+  int32_t n_uniform;                         /* >= 2 */
+  int32_t n_importance;                      /* even, >= 0 */
+  int32_t march_steps;
+  double pdf_floor;                          /* > 0 */
+  double normal_eps;                         /* > 0 */
+} vs_ksdf_opts;
+
+/* 32-bit words of an occupancy bit grid of resolution occ_res (0 if invalid):
+ * voxel (x, y, z) is bit i & 31 of word i >> 5, i = (z occ_res + y) occ_res + x. */
+int64_t vs_ksdf_occupancy_words(int32_t occ_res);
+
+/* Build the occupancy grid (Sec. 4.4) of field and opts into occ (device,
+ * vs_ksdf_occupancy_words words; every word is written). */
+vs_status vs_ksdf_occupancy(const vs_ksdf_field* field, const vs_ksdf_opts* opts, uint32_t* occ, void* stream);
+
+/* Render every pixel of views (vs_views_prepare output) by k-SDF volume rendering.
+ * Per pixel ray (origin -R^T t, direction R^T ((i+.5-cx)/fx, (j+.5-cy)/fy, 1) normalised) over its
+ * interval [t_in, t_out] in the cube (t >= 0):
+ *   1. march_steps equal steps mark the occupied part; with M occupied steps, uniform sample i sits in
+ *      occupied step floor(rho) at fraction rho - floor(rho), rho = (i + 1/2) M / n_uniform;
+ *   2. two importance rounds: over the sorted samples, NeuS interval weights of every surface
+ *      (a_i = max((Phi(d_j(x_i)) - Phi(d_j(x_{i+1}))) / Phi(d_j(x_i)), 0), w_i = a_i prod_{l<i} (1 - a_l))
+ *      are summed over surfaces, floored, normalised and inverted at u_q = (q + 1/2)/(n_importance/2)
+ *      (linear within an interval); new samples are merged in order;
+ *   3. per surface C_j = sum_i w_ij xi(x_i), A_j = sum_i w_ij alpha_w(x_i) a(x_i), (xi, a) the RGBA
+ *      field, alpha_w = 2 sigmoid(10 |v.n|) - 1, n the normalised central difference of d;
+ *   4. out = (sum_j C_j A_j prod_{l<j} (1 - A_l), 1 - prod_j (1 - A_j)).
+ * Rays that miss the cube or meet no occupied step give zeros.
+ * occ: from vs_ksdf_occupancy with the same field and opts.
+ * out_rgba: device f32 [total pixels][4], 16-byte aligned.
+ * layers (may be NULL): device f32 [k][total pixels][4], (C_j, A_j) per surface.
+ * samples (may be NULL): device f64 [total pixels][n_uniform + n_importance], the final sorted sample
+ *   parameters t, -1 for rays without samples.
+ * Weights, appearance and blending are FP32; ray set-up, marching and sample positions FP64. */
+vs_status vs_ksdf_render(const vs_ksdf_field* field, const vs_ksdf_opts* opts, const uint32_t* occ,
+                         const vs_views* views, float* out_rgba, float* layers, double* samples, void* stream);
+
 /* ---- HIP graphs: capture a sequence of the calls above on one stream ---- */
 typedef struct vs_graph_s* vs_graph;
 

@@ -122,13 +122,13 @@ def logistic_cdf(x: np.ndarray, beta: float) -> np.ndarray:
 # --------------------------------------------------------------------------
 # occupancy grid (Sec. 4.4)
 # --------------------------------------------------------------------------
-def occupancy(field: KsdfField, opts: KsdfOpts) -> np.ndarray:
-    """uint8 [Ro, Ro, Ro] ([z][y][x]); 1 where some surface may have density above the threshold."""
+def occupancy_at(field: KsdfField, opts: KsdfOpts, vox: np.ndarray) -> np.ndarray:
+    """Occupancy (bool) of the voxels with linear indices ``vox`` ((z Ro + y) Ro + x)."""
     Ro = opts.occ_res
     ho = (field.hi - field.lo) / Ro
-    ax = field.lo + (np.arange(Ro) + 0.5) * ho
-    z, y, x = np.meshgrid(ax, ax, ax, indexing="ij")
-    centres = np.stack([x.reshape(-1), y.reshape(-1), z.reshape(-1)], -1)
+    vox = np.asarray(vox, np.int64)
+    x, y, z = vox % Ro, (vox // Ro) % Ro, vox // (Ro * Ro)
+    centres = np.stack([field.lo + (x + 0.5) * ho, field.lo + (y + 0.5) * ho, field.lo + (z + 0.5) * ho], -1)
     dc = sdf_at(field, centres)
     half_diag = math.sqrt(3.0) * ho / 2.0
     occ = np.zeros(dc.shape, bool)
@@ -136,7 +136,17 @@ def occupancy(field: KsdfField, opts: KsdfOpts) -> np.ndarray:
         for o in opts.offsets:
             delta = np.maximum(np.abs(dc + o) - half_diag, 0.0)
             occ |= logistic_density(delta, opts.beta) > opts.occ_threshold
-    return occ.reshape(Ro, Ro, Ro).astype(np.uint8)
+    return occ
+
+
+def occupancy(field: KsdfField, opts: KsdfOpts, chunk: int = 1 << 21) -> np.ndarray:
+    """uint8 [Ro, Ro, Ro] ([z][y][x]); 1 where some surface may have density above the threshold."""
+    Ro = opts.occ_res
+    n = Ro ** 3
+    out = np.empty(n, np.uint8)
+    for a in range(0, n, chunk):
+        out[a:a + chunk] = occupancy_at(field, opts, np.arange(a, min(a + chunk, n)))
+    return out.reshape(Ro, Ro, Ro)
 
 
 # --------------------------------------------------------------------------

@@ -73,6 +73,16 @@ class VsNgpConfig(ctypes.Structure):
     _fields_ = [("levels", c_i32), ("log2_table", c_i32), ("resolution", c_i32 * 16)]
 
 
+class VsKsdfField(ctypes.Structure):
+    _fields_ = [("sdf", c_vp), ("rgba", c_vp), ("sdf_res", c_i32), ("rgba_res", c_i32), ("lo", c_f64), ("hi", c_f64)]
+
+
+class VsKsdfOpts(ctypes.Structure):
+    _fields_ = [("k", c_i32), ("offsets", c_f64 * 16), ("beta", c_f64), ("occ_threshold", c_f64),
+                ("occ_res", c_i32), ("n_uniform", c_i32), ("n_importance", c_i32), ("march_steps", c_i32),
+                ("pdf_floor", c_f64), ("normal_eps", c_f64)]
+
+
 # name -> (restype, argtypes); every symbol declared in include/vs.h
 SIGNATURES = {
     "vs_version": (ctypes.c_char_p, []),
@@ -94,6 +104,9 @@ SIGNATURES = {
     "vs_ngp_workspace_bytes": (c_sz, [c_vp, c_i32, c_vp, c_vp]),
     "vs_ngp_bake": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "vs_ngp_backward": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "vs_ksdf_occupancy_words": (ctypes.c_int64, [c_i32]),
+    "vs_ksdf_occupancy": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
+    "vs_ksdf_render": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "vs_graph_begin": (c_i32, [c_vp]),
     "vs_graph_end": (c_i32, [c_vp, c_vp]),
     "vs_graph_launch": (c_i32, [c_vp, c_vp]),

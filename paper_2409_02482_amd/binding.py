@@ -349,6 +349,62 @@ def ngp_backward(params, cfg: NgpConfig, sizes, tex, grad_tex, ws: torch.Tensor,
     return grad_params
 
 
+class KsdfField:
+    """k-SDF fields on device: SDF grid f32 [(R+1)^3] and RGBA grid f32 [(Ra+1)^3, 4] over the cube [lo, hi]^3."""
+
+    def __init__(self, sdf: torch.Tensor, sdf_res: int, rgba: torch.Tensor, rgba_res: int, lo: float, hi: float):
+        self.sdf = _dev(sdf, torch.float32, "sdf")
+        self.rgba = _dev(rgba, torch.float32, "rgba")
+        if self.sdf.numel() != (sdf_res + 1) ** 3 or self.rgba.numel() != 4 * (rgba_res + 1) ** 3:
+            raise ValueError("grid sizes do not match the resolutions")
+        self.c = C.VsKsdfField(self.sdf.data_ptr(), self.rgba.data_ptr(), int(sdf_res), int(rgba_res), float(lo),
+                               float(hi))
+
+
+def ksdf_opts(offsets, beta: float, occ_threshold: float = 1e-4, occ_res: int = 256, n_uniform: int = 64,
+              n_importance: int = 32, march_steps: int = 1024, pdf_floor: float = 1e-5,
+              normal_eps: float = 1e-4) -> C.VsKsdfOpts:
+    offs = [float(o) for o in offsets]
+    if not 1 <= len(offs) <= 16:
+        raise ValueError("1..16 surfaces")
+    return C.VsKsdfOpts(len(offs), (ctypes.c_double * 16)(*(offs + [0.0] * (16 - len(offs)))), float(beta),
+                        float(occ_threshold), int(occ_res), int(n_uniform), int(n_importance), int(march_steps),
+                        float(pdf_floor), float(normal_eps))
+
+
+def ksdf_occupancy(field: KsdfField, opts: C.VsKsdfOpts, occ: Optional[torch.Tensor] = None, stream=None):
+    """vs_ksdf_occupancy: the occupancy bit grid (int32 words; bit i & 31 of word i >> 5)."""
+    words = int(C.load().vs_ksdf_occupancy_words(opts.occ_res))
+    if occ is None:
+        occ = torch.empty(max(words, 1), dtype=torch.int32, device=field.sdf.device)
+    _dev(occ, torch.int32, "occ")
+    if occ.numel() < words:
+        raise ValueError("occ too small")
+    C.check(C.load().vs_ksdf_occupancy(ctypes.byref(field.c), ctypes.byref(opts), occ.data_ptr(), _stream(stream)),
+            "vs_ksdf_occupancy")
+    return occ
+
+
+def ksdf_render(field: KsdfField, opts: C.VsKsdfOpts, occ: torch.Tensor, views: Views, out=None,
+                layers: bool = False, samples: bool = False, stream=None):
+    """vs_ksdf_render: RGBA [total pixels, 4]; optionally per-surface (C_j, A_j) [k, total, 4] and the final
+    sample parameters [total, n_uniform + n_importance] (f64)."""
+    total = views.total_pixels
+    dev = field.sdf.device
+    if out is None:
+        out = torch.empty(total, 4, dtype=torch.float32, device=dev)
+    _dev(out, torch.float32, "out")
+    lay = torch.empty(opts.k, total, 4, dtype=torch.float32, device=dev) if layers else None
+    smp = torch.empty(total, opts.n_uniform + opts.n_importance, dtype=torch.float64, device=dev) if samples else None
+    _dev(occ, torch.int32, "occ")
+    C.check(C.load().vs_ksdf_render(ctypes.byref(field.c), ctypes.byref(opts), occ.data_ptr(), ctypes.byref(views.c),
+                                    out.data_ptr(), None if lay is None else lay.data_ptr(),
+                                    None if smp is None else smp.data_ptr(), _stream(stream)), "vs_ksdf_render")
+    if layers or samples:
+        return out, lay, smp
+    return out
+
+
 class Graph:
     """A HIP graph captured from calls into the library on one (non-default) stream."""
 

@@ -19,6 +19,7 @@
 #include "vs_sh.h"
 #include "vs_fit.h"
 #include "vs_ngp.h"
+#include "vs_ksdf.h"
 
 namespace {
 
@@ -872,6 +873,101 @@ struct vs_graph_s {
   hipGraph_t graph;
   hipGraphExec_t exec;
 };
+
+// ---------------------------------------------------------------------------
+// k-SDF volume rendering
+// ---------------------------------------------------------------------------
+namespace {
+
+vs_status ksdf_params(const char* who, const vs_ksdf_field* f, const vs_ksdf_opts* o, vs::KsdfParams& P) {
+  if (!f || !o) return fail(VS_ERR_ARG, "%s: null field or opts", who);
+  if (!f->sdf || !f->rgba) return fail(VS_ERR_ARG, "%s: null field grid", who);
+  if ((uintptr_t)f->rgba % 16) return fail(VS_ERR_ARG, "%s: rgba grid not 16-byte aligned", who);
+  if (f->sdf_res < 1 || f->sdf_res > 1024 || f->rgba_res < 1 || f->rgba_res > 1024)
+    return fail(VS_ERR_SIZE, "%s: grid resolutions %d, %d outside 1..1024", who, f->sdf_res, f->rgba_res);
+  if (!(std::isfinite(f->lo) && std::isfinite(f->hi) && f->lo < f->hi))
+    return fail(VS_ERR_ARG, "%s: need finite lo < hi", who);
+  if (o->k < 1 || o->k > VS_KSDF_MAX_SURFACES) return fail(VS_ERR_ARG, "%s: k = %d outside 1..%d", who, o->k,
+                                                            VS_KSDF_MAX_SURFACES);
+  for (int j = 0; j < o->k; ++j) {
+    if (!std::isfinite(o->offsets[j])) return fail(VS_ERR_ARG, "%s: offset %d not finite", who, j);
+    if (j && o->offsets[j] < o->offsets[j - 1]) return fail(VS_ERR_ARG, "%s: offsets must not decrease", who);
+  }
+  if (!(std::isfinite(o->beta) && o->beta > 0.0)) return fail(VS_ERR_ARG, "%s: beta must be > 0", who);
+  if (!(std::isfinite(o->occ_threshold) && o->occ_threshold > 0.0))
+    return fail(VS_ERR_ARG, "%s: occ_threshold must be > 0", who);
+  if (o->occ_res < 1 || o->occ_res > 1024) return fail(VS_ERR_SIZE, "%s: occ_res %d outside 1..1024", who, o->occ_res);
+  if (o->n_uniform < 2 || o->n_importance < 0 || o->n_importance % 2 ||
+      o->n_uniform + o->n_importance > VS_KSDF_MAX_SAMPLES)
+    return fail(VS_ERR_ARG, "%s: need n_uniform >= 2, even n_importance >= 0, total <= %d", who, VS_KSDF_MAX_SAMPLES);
+  if (o->march_steps < 64 || o->march_steps > 2048 || o->march_steps % 64)
+    return fail(VS_ERR_ARG, "%s: march_steps must be a multiple of 64 in 64..2048", who);
+  if (!(std::isfinite(o->pdf_floor) && o->pdf_floor > 0.0)) return fail(VS_ERR_ARG, "%s: pdf_floor must be > 0", who);
+  if (!(std::isfinite(o->normal_eps) && o->normal_eps > 0.0))
+    return fail(VS_ERR_ARG, "%s: normal_eps must be > 0", who);
+  std::memset(&P, 0, sizeof(P));
+  P.sdf = f->sdf;
+  P.rgba = (const float4*)f->rgba;
+  P.sdf_res = f->sdf_res;
+  P.rgba_res = f->rgba_res;
+  P.occ_res = o->occ_res;
+  P.lo = f->lo;
+  P.hi = f->hi;
+  P.h_sdf = (f->hi - f->lo) / f->sdf_res;
+  P.h_rgba = (f->hi - f->lo) / f->rgba_res;
+  P.h_occ = (f->hi - f->lo) / o->occ_res;
+  P.k = o->k;
+  for (int j = 0; j < o->k; ++j) P.off[j] = o->offsets[j];
+  P.beta = o->beta;
+  P.occ_threshold = o->occ_threshold;
+  P.half_diag = std::sqrt(3.0) * P.h_occ / 2.0;
+  P.n = o->n_uniform;
+  P.m = o->n_importance;
+  P.steps = o->march_steps;
+  P.pdf_floor = (float)o->pdf_floor;
+  P.normal_eps = o->normal_eps;
+  return VS_OK;
+}
+
+}  // namespace
+
+extern "C" int64_t vs_ksdf_occupancy_words(int32_t occ_res) {
+  if (occ_res < 1 || occ_res > 1024) return 0;
+  return ((int64_t)occ_res * occ_res * occ_res + 31) / 32;
+}
+
+extern "C" vs_status vs_ksdf_occupancy(const vs_ksdf_field* field, const vs_ksdf_opts* opts, uint32_t* occ,
+                                       void* stream) {
+  vs::KsdfParams P;
+  vs_status st = ksdf_params("vs_ksdf_occupancy", field, opts, P);
+  if (st) return st;
+  if (!occ) return fail(VS_ERR_ARG, "vs_ksdf_occupancy: null occ");
+  const int64_t n_vox = (int64_t)P.occ_res * P.occ_res * P.occ_res;
+  const int64_t words = vs_ksdf_occupancy_words(P.occ_res);
+  hipLaunchKernelGGL(vs::k_ksdf_occupancy, dim3((unsigned)((n_vox + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     P, occ, n_vox, words);
+  if ((st = check_launch("vs_ksdf_occupancy"))) return st;
+  return ok();
+}
+
+extern "C" vs_status vs_ksdf_render(const vs_ksdf_field* field, const vs_ksdf_opts* opts, const uint32_t* occ,
+                                    const vs_views* views, float* out_rgba, float* layers, double* samples,
+                                    void* stream) {
+  vs::KsdfParams P;
+  vs_status st = ksdf_params("vs_ksdf_render", field, opts, P);
+  if (st) return st;
+  if ((st = check_views(views))) return st;
+  if (!occ || !out_rgba) return fail(VS_ERR_ARG, "vs_ksdf_render: null occ or out_rgba");
+  if ((uintptr_t)out_rgba % 16 || (layers && (uintptr_t)layers % 16) || (samples && (uintptr_t)samples % 8))
+    return fail(VS_ERR_ARG, "vs_ksdf_render: misaligned output");
+  const int64_t total = views->host[views->n_views].pix_offset;
+  const int64_t blocks = ((total + vs::kKsdfWaves - 1) / vs::kKsdfWaves + 7) / 8 * 8;
+  if (blocks > INT32_MAX) return fail(VS_ERR_SIZE, "vs_ksdf_render: too many pixels");
+  hipLaunchKernelGGL(vs::k_ksdf_render, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, views->dev,
+                     views->n_views, total, P, occ, (float4*)out_rgba, (float4*)layers, samples);
+  if ((st = check_launch("vs_ksdf_render"))) return st;
+  return ok();
+}
 
 extern "C" vs_status vs_graph_begin(void* stream) {
   if (!stream) return fail(VS_ERR_ARG, "vs_graph_begin: the null stream cannot be captured");

@@ -46,7 +46,8 @@ def test_struct_layouts_match_c(C, tmp_path):
                     'sizeof(vs_texture), sizeof(vs_camera), sizeof(vs_view), sizeof(vs_views), sizeof(vs_raster_opts),'
                     'sizeof(vs_shade_opts), offsetof(vs_view, pix_offset), offsetof(vs_shade_opts, target),'
                     'offsetof(vs_raster_opts, list_capacity), sizeof(vs_sh_texture), sizeof(vs_sh_opts),'
-                    'offsetof(vs_sh_opts, view_alpha)); printf("%zu\\n", sizeof(vs_ngp_config));'
+                    'offsetof(vs_sh_opts, view_alpha)); printf("%zu %zu %zu %zu\\n", sizeof(vs_ngp_config),'
+                    'sizeof(vs_ksdf_field), sizeof(vs_ksdf_opts), offsetof(vs_ksdf_opts, normal_eps));'
                     'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
@@ -55,7 +56,8 @@ def test_struct_layouts_match_c(C, tmp_path):
             ctypes.sizeof(C.VsView), ctypes.sizeof(C.VsViews), ctypes.sizeof(C.VsRasterOpts),
             ctypes.sizeof(C.VsShadeOpts), C.VsView.pix_offset.offset, C.VsShadeOpts.target.offset,
             C.VsRasterOpts.list_capacity.offset, ctypes.sizeof(C.VsShTexture), ctypes.sizeof(C.VsShOpts),
-            C.VsShOpts.view_alpha.offset, ctypes.sizeof(C.VsNgpConfig)]
+            C.VsShOpts.view_alpha.offset, ctypes.sizeof(C.VsNgpConfig), ctypes.sizeof(C.VsKsdfField),
+            ctypes.sizeof(C.VsKsdfOpts), C.VsKsdfOpts.normal_eps.offset]
     assert got == want
 
 
@@ -211,6 +213,44 @@ def test_ngp_host_calls(C):
     w[0] = 0
     assert L.vs_ngp_bake(ctypes.addressof(p), ctypes.byref(cfg), 2, ctypes.addressof(w), ctypes.addressof(h),
                          ctypes.addressof(t), None, 0, None) == C.VS_ERR_SIZE
+
+
+def test_ksdf_host_validation(C):
+    """Occupancy word counts and option checks of the k-SDF calls, refused on the host without a GPU."""
+    L = C.load()
+    assert L.vs_ksdf_occupancy_words(256) == 256 ** 3 // 32
+    assert L.vs_ksdf_occupancy_words(5) == (125 + 31) // 32
+    assert L.vs_ksdf_occupancy_words(0) == 0 and L.vs_ksdf_occupancy_words(2000) == 0
+    field = C.VsKsdfField(0x10000, 0x20000, 64, 32, -1.25, 1.25)
+
+    def opts(**kw):
+        a = dict(k=3, offsets=[0.0, 0.01, 0.02], beta=1000.0, occ_threshold=1e-4, occ_res=64, n_uniform=64,
+                 n_importance=32, march_steps=1024, pdf_floor=1e-5, normal_eps=1e-4)
+        a.update(kw)
+        offs = list(a["offsets"]) + [0.0] * (16 - len(a["offsets"]))
+        return C.VsKsdfOpts(a["k"], (ctypes.c_double * 16)(*offs), a["beta"], a["occ_threshold"], a["occ_res"],
+                            a["n_uniform"], a["n_importance"], a["march_steps"], a["pdf_floor"], a["normal_eps"])
+
+    def occ(o, f=field, out=0x30000):
+        return L.vs_ksdf_occupancy(ctypes.byref(f), ctypes.byref(o), out, None)
+
+    assert occ(opts(), out=None) == C.VS_ERR_ARG
+    assert occ(opts(k=0)) == C.VS_ERR_ARG
+    assert occ(opts(offsets=[0.0, 0.02, 0.01])) == C.VS_ERR_ARG         # offsets must not decrease
+    assert occ(opts(beta=0.0)) == C.VS_ERR_ARG
+    assert occ(opts(occ_res=0)) == C.VS_ERR_SIZE
+    assert occ(opts(n_importance=31)) == C.VS_ERR_ARG
+    assert occ(opts(n_uniform=100, n_importance=32)) == C.VS_ERR_ARG    # more than 128 samples
+    assert occ(opts(march_steps=1000)) == C.VS_ERR_ARG
+    assert occ(opts(pdf_floor=0.0)) == C.VS_ERR_ARG
+    assert occ(opts(), f=C.VsKsdfField(0x10000, 0x20008, 64, 32, -1.25, 1.25)) == C.VS_ERR_ARG   # misaligned rgba
+    assert occ(opts(), f=C.VsKsdfField(0x10000, 0x20000, 64, 32, 1.0, -1.0)) == C.VS_ERR_ARG
+    assert occ(opts(), f=C.VsKsdfField(0x10000, 0x20000, 2048, 32, -1.0, 1.0)) == C.VS_ERR_SIZE
+    host, views, _, _ = _fake_call_args(C)
+    assert L.vs_ksdf_render(ctypes.byref(field), ctypes.byref(opts()), 0x30000, ctypes.byref(views), None, None,
+                            None, None) == C.VS_ERR_ARG
+    assert L.vs_ksdf_render(ctypes.byref(field), ctypes.byref(opts()), 0x30000, ctypes.byref(views), 0x40008, None,
+                            None, None) == C.VS_ERR_ARG
 
 
 def test_status_strings(C):
