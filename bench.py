@@ -203,6 +203,125 @@ def run_sh(args):
     print(json.dumps(res), flush=True)
 
 
+KSDF_METRIC = "rays/s, k-SDF volume rendering fwd (k=7, 64+32 samples/ray, 256^3 fields, 8 views at 512^2)"
+FP_PEAK_TFLOPS = 78.6    # fp64 FMA (and unpacked fp32 FMA): 256 CUs x 64 lanes x 2 flops x 2.4 GHz
+
+
+def ksdf_flops_per_ray(k, n, m, steps):
+    """Algorithmic floating-point operations of one ray with samples (counted from the method's steps).
+
+    march: per step the midpoint (2) and three voxel coordinates (4 each);
+    SDF lookup: three cell coordinates (2 each) and 8 corners (weight 2 + accumulate 2);
+    RGBA lookup: cell coordinates (6) and 8 corners (weight 2 + 4 channels x 2);
+    interval weight per sample and surface: argument (2), logistic CDF (3), a_i (3), T_i and w_i (2);
+    per interval of the final samples: position (6), normal (6 lookups, 3 differences, normalise 9,
+    dot 5), alpha_w (4), per surface accumulation of C and A (10).
+    """
+    N = n + m
+    sdf, rgba = 6 + 8 * 4, 6 + 8 * 10
+    flops = steps * 14
+    flops += N * (6 + sdf)                                   # sample positions and their SDF
+    flops += (n + (n + m // 2) + N) * k * 10                 # weights of both importance rounds and the final pass
+    flops += (N - 1) * (6 + rgba + 6 * sdf + 3 + 9 + 5 + 4 + 10 * k)
+    return flops
+
+
+def ksdf_cpu_baseline(grids, oopts, occ_np, cams, n_rays):
+    """The oracle on a bounded random sample of the workload's rays (single process, NumPy)."""
+    import threadpoolctl
+
+    from oracle import ksdf as K
+    rng = np.random.default_rng(70)
+    per = n_rays // len(cams)
+    with threadpoolctl.threadpool_limits(1):
+        t0 = time.perf_counter()
+        for cam in cams:
+            o, d = K.camera_rays(cam)
+            pick = rng.choice(o.shape[0], per, replace=False)
+            K.render_rays(grids, oopts, occ_np, o[pick], d[pick])
+        dt = time.perf_counter() - t0
+    return {"value": per * len(cams) / dt, "unit": "rays/s", "cores": 1, "kind": "oracle",
+            "sample": f"{per * len(cams)} random rays ({per} per view) of the {len(cams)} views, occupancy grid "
+                      f"given, one NumPy thread, {dt:.1f} s wall"}
+
+
+def run_ksdf(args):
+    """k-SDF volume-rendering forward: occupancy grid + vs_ksdf_render per step."""
+    import math
+
+    import torch
+
+    import paper_2409_02482_amd as P
+    import scenes as S
+    log("[bench] building k-SDF fields")
+    k, n, m, steps, res = 7, 64, 32, 1024, 512
+    beta = math.exp(7.0)
+    grids = S.ksdf_grids(5, 256, 128)
+    cams = S.ring_cameras(5, 8, [(res, res)] * 8)
+    dev = "cuda"
+    field = P.KsdfField(torch.from_numpy(grids.sdf).to(dev), grids.sdf_res,
+                        torch.from_numpy(grids.rgba.reshape(-1, 4)).to(dev), grids.rgba_res, grids.lo, grids.hi)
+    offs = S.ksdf_offsets(k, beta)
+    opts = P.ksdf_opts(offs, beta, occ_res=256, n_uniform=n, n_importance=m, march_steps=steps)
+    views = P.Views(cams, dev)
+    occ = P.ksdf_occupancy(field, opts)
+    out = torch.empty(views.total_pixels, 4, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        P.ksdf_occupancy(field, opts, occ)
+        if ev is not None:
+            ev[1].record(stream)
+        P.ksdf_render(field, opts, occ, views, out=out)
+        if ev is not None:
+            ev[2].record(stream)
+
+    log("[bench] warmup")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    _, _, smp = P.ksdf_render(field, opts, occ, views, samples=True)
+    sampled = int((smp[:, 0] >= 0).sum().item())
+    del smp
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for st in range(args.steps):
+        step(evs[st])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    phase = np.array([[evs[st][i].elapsed_time(evs[st][i + 1]) for i in range(2)] for st in range(args.steps)])
+    ms_phase = phase.mean(0)
+    ms_wall = wall / args.steps * 1e3
+    rays = views.total_pixels
+    fl = ksdf_flops_per_ray(k, n, m, steps) * sampled
+    achieved = fl / (ms_phase[1] * 1e-3) / 1e12
+    res_ = {
+        "metric": KSDF_METRIC, "value": rays / (ms_wall * 1e-3), "unit": "rays/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_wall, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": f"k-SDF (k={k} shells of the displaced sphere, offsets pi/(sqrt(3) beta), beta=e^7), "
+                               f"SDF grid 256^3, RGBA grid 128^3, occupancy 256^3, {n} uniform + {m} importance "
+                               f"samples, {steps} march steps, 8 ring views at {res}x{res}; occupancy + render",
+                   "views": len(cams), "k": k, "rays": rays, "rays_with_samples": sampled,
+                   "samples_per_ray": n + m},
+        "phases_ms": {"occupancy": float(ms_phase[0]), "render": float(ms_phase[1])},
+        "samples_per_s": sampled * (n + m) / (ms_wall * 1e-3),
+        "roofline": {"bound": "alu", "kernel": "ksdf_render", "achieved": achieved, "peak": FP_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP_PEAK_TFLOPS, "traffic": counter_traffic("ksdf_render"),
+                     "flops_per_ray": ksdf_flops_per_ray(k, n, m, steps)},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        from oracle import ksdf as K
+        oopts = K.KsdfOpts(offsets=offs, beta=beta, occ_res=256, n_uniform=n, n_importance=m, march_steps=steps)
+        occ_np = K.occupancy(grids, oopts)
+        res_["cpu_baseline"] = ksdf_cpu_baseline(grids, oopts, occ_np, cams, 4000)
+    print(json.dumps(res_), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,9 +333,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=8)
     ap.add_argument("--unfused", action="store_true", help="separate forward shading pass before the adjoint")
-    ap.add_argument("--workload", default="metric", choices=["metric", "cfg4", "sh"],
+    ap.add_argument("--workload", default="metric", choices=["metric", "cfg4", "sh", "ksdf"],
                     help="metric: k=7, 64 views at 1024^2; cfg4: k=9, 299,208 tris/layer, 64 mixed-size views; "
-                         "sh: the metric scene rendered forward with baked 8-bit SH textures (degree 3, 2048^2 base)")
+                         "sh: the metric scene rendered forward with baked 8-bit SH textures (degree 3, 2048^2 base); "
+                         "ksdf: k-SDF volume rendering of the implicit stage (8 views at 512^2)")
     ap.add_argument("--graph", action="store_true", help="replay the step from a captured HIP graph")
     ap.add_argument("--autotune", action="store_true", help="pick the raster bin size with vs_autotune")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -231,6 +351,8 @@ def main():
         calibration_copy(args.calibrate_copy)
     if args.workload == "sh":
         return run_sh(args)
+    if args.workload == "ksdf":
+        return run_ksdf(args)
 
     import torch
 
