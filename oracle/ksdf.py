@@ -11,8 +11,8 @@ Definitions (our reading where the paper gives no formula):
   * fields on the cube [lo, hi]^3: the main SDF d on (R+1)^3 vertices and a
     straight RGBA appearance field (RGB = xi, A = the transparency field) on
     (Ra+1)^3 vertices, both stored [z][y][x]; a grid of resolution R has
-    spacing h = (hi - lo) / R, cell coordinate c = (p - lo) / h clamped to
-    [0, R], base vertex min(floor(c), R - 1), weights c - base;
+    cell coordinate c = (p - lo) * (R / (hi - lo)) clamped to [0, R], base
+    vertex min(floor(c), R - 1), weights c - base;
   * surfaces d_j = d + o_j with constant offsets o_0 <= o_1 <= ..., j = 0 the
     outermost (positive offsets lie inside, Sec. 4.1);
   * logistic density phi_b(x) = b e^{-bx} / (1 + e^{-bx})^2 (Eq. 2) and its
@@ -86,8 +86,8 @@ class KsdfOpts:
 def trilinear(grid: np.ndarray, res: int, lo: float, hi: float, p: np.ndarray) -> np.ndarray:
     """Trilinear interpolation of vertex values ``grid`` [(res+1)^3, C] at points p [n, 3] -> [n, C]."""
     g = np.asarray(grid, np.float64).reshape((res + 1) ** 3, -1)
-    h = (hi - lo) / res
-    c = np.clip((np.asarray(p, np.float64) - lo) / h, 0.0, float(res))
+    inv = res / (hi - lo)
+    c = np.clip((np.asarray(p, np.float64) - lo) * inv, 0.0, float(res))
     b = np.minimum(np.floor(c), res - 1).astype(np.int64)
     f = c - b
     out = np.zeros((c.shape[0], g.shape[1]))
@@ -190,11 +190,11 @@ def box_interval(o: np.ndarray, v: np.ndarray, lo: float, hi: float):
 def march_occupied(o, v, t_in, t_out, occ: np.ndarray, lo: float, hi: float, steps: int) -> np.ndarray:
     """bool [n_rays, S]: march step s of each ray is occupied (voxel of its midpoint)."""
     Ro = occ.shape[0]
-    ho = (hi - lo) / Ro
+    inv = Ro / (hi - lo)
     D = (t_out - t_in) / steps
     tm = t_in[:, None] + (np.arange(steps)[None, :] + 0.5) * D[:, None]
     p = o[:, None, :] + tm[..., None] * v[:, None, :]
-    vox = np.clip(np.floor((p - lo) / ho), 0, Ro - 1).astype(np.int64)
+    vox = np.clip(np.floor((p - lo) * inv), 0, Ro - 1).astype(np.int64)
     return occ[vox[..., 2], vox[..., 1], vox[..., 0]].astype(bool)
 
 
