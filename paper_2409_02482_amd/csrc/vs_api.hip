@@ -913,9 +913,11 @@ vs_status ksdf_params(const char* who, const vs_ksdf_field* f, const vs_ksdf_opt
   P.occ_res = o->occ_res;
   P.lo = f->lo;
   P.hi = f->hi;
-  P.h_sdf = (f->hi - f->lo) / f->sdf_res;
-  P.h_rgba = (f->hi - f->lo) / f->rgba_res;
   P.h_occ = (f->hi - f->lo) / o->occ_res;
+  P.inv_sdf = f->sdf_res / (f->hi - f->lo);
+  P.inv_rgba = f->rgba_res / (f->hi - f->lo);
+  P.inv_occ = o->occ_res / (f->hi - f->lo);
+  P.inv_2eps = 1.0 / (2.0 * o->normal_eps);
   P.k = o->k;
   for (int j = 0; j < o->k; ++j) P.off[j] = o->offsets[j];
   P.beta = o->beta;

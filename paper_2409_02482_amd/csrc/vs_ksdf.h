@@ -30,7 +30,9 @@ struct KsdfParams {
   const float* sdf;
   const float4* rgba;
   int32_t sdf_res, rgba_res, occ_res;
-  double lo, hi, h_sdf, h_rgba, h_occ;
+  double lo, hi, h_occ;
+  double inv_sdf, inv_rgba, inv_occ;       // R / (hi - lo) of each grid
+  double inv_2eps;                         // 1 / (2 normal_eps)
   int32_t k;
   double off[VS_KSDF_MAX_SURFACES];
   double beta, occ_threshold, half_diag;
@@ -39,17 +41,24 @@ struct KsdfParams {
   double normal_eps;
 };
 
+// Cell of a point along one axis: base vertex and weight (FP64).
+__device__ inline void ksdf_cell(double p, double lo, double inv, int R, int32_t& b, double& f) {
+  const double c = fmin(fmax((p - lo) * inv, 0.0), (double)R);
+  const double bb = fmin(floor(c), (double)(R - 1));
+  b = (int32_t)bb;
+  f = c - bb;
+}
+
 // Trilinear lookup of the SDF grid in FP64 (the accumulation order of a plain
 // evaluation: corners z-major, then y, then x).
 __device__ inline double ksdf_sdf(const KsdfParams& P, double px, double py, double pz) {
   const int R = P.sdf_res;
-  const double cx = fmin(fmax((px - P.lo) / P.h_sdf, 0.0), (double)R);
-  const double cy = fmin(fmax((py - P.lo) / P.h_sdf, 0.0), (double)R);
-  const double cz = fmin(fmax((pz - P.lo) / P.h_sdf, 0.0), (double)R);
-  const double bx = fmin(floor(cx), (double)(R - 1)), by = fmin(floor(cy), (double)(R - 1)),
-               bz = fmin(floor(cz), (double)(R - 1));
-  const double fx = cx - bx, fy = cy - by, fz = cz - bz;
-  const int32_t ix = (int32_t)bx, iy = (int32_t)by, iz = (int32_t)bz, R1 = R + 1;
+  int32_t ix, iy, iz;
+  double fx, fy, fz;
+  ksdf_cell(px, P.lo, P.inv_sdf, R, ix, fx);
+  ksdf_cell(py, P.lo, P.inv_sdf, R, iy, fy);
+  ksdf_cell(pz, P.lo, P.inv_sdf, R, iz, fz);
+  const int32_t R1 = R + 1;
   double acc = 0.0;
 #pragma unroll
   for (int dz = 0; dz < 2; ++dz)
@@ -64,16 +73,81 @@ __device__ inline double ksdf_sdf(const KsdfParams& P, double px, double py, dou
   return acc;
 }
 
+// Sum over the 4 grid lines through the cell along one axis: sum_q w4[q] lerp(g[b + o4[q]], g[b + o4[q] + stride], f).
+__device__ inline double ksdf_lines(const float* __restrict__ g, int32_t b, int32_t stride, const int32_t o4[4],
+                                    const double w4[4], double f) {
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double g0 = (double)g[b + o4[q]], g1 = (double)g[b + o4[q] + stride];
+    acc += w4[q] * (g0 + f * (g1 - g0));
+  }
+  return acc;
+}
+
+// Central differences of the SDF at p along x, y and z (step normal_eps),
+// each from the two shifted points; the weights and lines of the two axes
+// that do not move are shared by both points.
+__device__ inline void ksdf_sdf_grad(const KsdfParams& P, double px, double py, double pz, double& gx, double& gy,
+                                     double& gz) {
+  const int R = P.sdf_res;
+  const int32_t R1 = R + 1, R2 = R1 * R1;
+  const double e = P.normal_eps;
+  int32_t ix, iy, iz;
+  double fx, fy, fz;
+  ksdf_cell(px, P.lo, P.inv_sdf, R, ix, fx);
+  ksdf_cell(py, P.lo, P.inv_sdf, R, iy, fy);
+  ksdf_cell(pz, P.lo, P.inv_sdf, R, iz, fz);
+  const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+  double w4[4];
+  int32_t o4[4];
+  int32_t b;
+  double f, hi_v, lo_v;
+  // x
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    w4[q] = wy[q & 1] * wz[q >> 1];
+    o4[q] = (iz + (q >> 1)) * R2 + (iy + (q & 1)) * R1;
+  }
+  ksdf_cell(px + e, P.lo, P.inv_sdf, R, b, f);
+  hi_v = ksdf_lines(P.sdf, b, 1, o4, w4, f);
+  ksdf_cell(px - e, P.lo, P.inv_sdf, R, b, f);
+  lo_v = ksdf_lines(P.sdf, b, 1, o4, w4, f);
+  gx = (hi_v - lo_v) * P.inv_2eps;
+  // y
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    w4[q] = wx[q & 1] * wz[q >> 1];
+    o4[q] = (iz + (q >> 1)) * R2 + ix + (q & 1);
+  }
+  ksdf_cell(py + e, P.lo, P.inv_sdf, R, b, f);
+  hi_v = ksdf_lines(P.sdf, b * R1, R1, o4, w4, f);
+  ksdf_cell(py - e, P.lo, P.inv_sdf, R, b, f);
+  lo_v = ksdf_lines(P.sdf, b * R1, R1, o4, w4, f);
+  gy = (hi_v - lo_v) * P.inv_2eps;
+  // z
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    w4[q] = wx[q & 1] * wy[q >> 1];
+    o4[q] = (iy + (q >> 1)) * R1 + ix + (q & 1);
+  }
+  ksdf_cell(pz + e, P.lo, P.inv_sdf, R, b, f);
+  hi_v = ksdf_lines(P.sdf, b * R2, R2, o4, w4, f);
+  ksdf_cell(pz - e, P.lo, P.inv_sdf, R, b, f);
+  lo_v = ksdf_lines(P.sdf, b * R2, R2, o4, w4, f);
+  gz = (hi_v - lo_v) * P.inv_2eps;
+}
+
 // Trilinear lookup of the RGBA grid: FP64 cell coordinates, FP32 weights and sum.
 __device__ inline float4 ksdf_rgba(const KsdfParams& P, double px, double py, double pz) {
   const int R = P.rgba_res;
-  const double cx = fmin(fmax((px - P.lo) / P.h_rgba, 0.0), (double)R);
-  const double cy = fmin(fmax((py - P.lo) / P.h_rgba, 0.0), (double)R);
-  const double cz = fmin(fmax((pz - P.lo) / P.h_rgba, 0.0), (double)R);
-  const double bx = fmin(floor(cx), (double)(R - 1)), by = fmin(floor(cy), (double)(R - 1)),
-               bz = fmin(floor(cz), (double)(R - 1));
-  const float fx = (float)(cx - bx), fy = (float)(cy - by), fz = (float)(cz - bz);
-  const int32_t ix = (int32_t)bx, iy = (int32_t)by, iz = (int32_t)bz, R1 = R + 1;
+  int32_t ix, iy, iz;
+  double dfx, dfy, dfz;
+  ksdf_cell(px, P.lo, P.inv_rgba, R, ix, dfx);
+  ksdf_cell(py, P.lo, P.inv_rgba, R, iy, dfy);
+  ksdf_cell(pz, P.lo, P.inv_rgba, R, iz, dfz);
+  const float fx = (float)dfx, fy = (float)dfy, fz = (float)dfz;
+  const int32_t R1 = R + 1;
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
   for (int dz = 0; dz < 2; ++dz)
@@ -119,40 +193,58 @@ __global__ void __launch_bounds__(256) k_ksdf_occupancy(KsdfParams P, uint32_t* 
 }
 
 // ---------------------------------------------------------------------------
-// wavefront helpers (64 lanes)
+// wavefront helpers (64 lanes, DPP: row shifts within 16-lane rows, row
+// broadcasts across rows, whole-wave shifts by one lane)
 // ---------------------------------------------------------------------------
-__device__ inline int ksdf_scan_add_i(int x, int lane) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ inline float ksdf_dpp(float old, float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(x), CTRL, ROW_MASK, 0xf, false));
+}
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ inline int ksdf_dpp_i(int old, int x) {
+  return __builtin_amdgcn_update_dpp(old, x, CTRL, ROW_MASK, 0xf, false);
+}
+
+// Inclusive prefix sum over the wave.
+__device__ inline int ksdf_scan_add_i(int x) {
+  x += ksdf_dpp_i<0x111>(0, x);
+  x += ksdf_dpp_i<0x112>(0, x);
+  x += ksdf_dpp_i<0x114>(0, x);
+  x += ksdf_dpp_i<0x118>(0, x);
+  x += ksdf_dpp_i<0x142, 0xa>(0, x);
+  x += ksdf_dpp_i<0x143, 0xc>(0, x);
   return x;
 }
 
-__device__ inline float ksdf_scan_add(float x, int lane) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const float y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
+__device__ inline float ksdf_scan_add(float x) {
+  x += ksdf_dpp<0x111>(0.f, x);
+  x += ksdf_dpp<0x112>(0.f, x);
+  x += ksdf_dpp<0x114>(0.f, x);
+  x += ksdf_dpp<0x118>(0.f, x);
+  x += ksdf_dpp<0x142, 0xa>(0.f, x);
+  x += ksdf_dpp<0x143, 0xc>(0.f, x);
   return x;
 }
 
-__device__ inline float ksdf_scan_mul(float x, int lane) {
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const float y = __shfl_up(x, o, 64);
-    if (lane >= o) x *= y;
-  }
+// Inclusive prefix product over the wave.
+__device__ inline float ksdf_scan_mul(float x) {
+  x *= ksdf_dpp<0x111>(1.f, x);
+  x *= ksdf_dpp<0x112>(1.f, x);
+  x *= ksdf_dpp<0x114>(1.f, x);
+  x *= ksdf_dpp<0x118>(1.f, x);
+  x *= ksdf_dpp<0x142, 0xa>(1.f, x);
+  x *= ksdf_dpp<0x143, 0xc>(1.f, x);
   return x;
 }
 
-__device__ inline float ksdf_sum(float x) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
-}
+__device__ inline float ksdf_lane(float x, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l)); }
+
+// Sum over the wave (the same value in every lane).
+__device__ inline float ksdf_sum(float x) { return ksdf_lane(ksdf_scan_add(x), 63); }
+
+// Value of lane - 1 (lane 0: old) and of lane + 1 (lane 63: old).
+__device__ inline float ksdf_from_below(float old, float x) { return ksdf_dpp<0x138>(old, x); }
+__device__ inline float ksdf_from_above(float old, float x) { return ksdf_dpp<0x130>(old, x); }
 
 __device__ inline void ksdf_wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -170,27 +262,28 @@ struct KsdfLds {
   uint32_t mask[64];        // march: occupied-step bits per lane
 };
 
+// NeuS opacity of the interval between two samples from E = exp(-beta d_j) at
+// both ends: 1 - Phi_{i+1}/Phi_i = (E_{i+1} - E_i) / (1 + E_{i+1}), 0 where
+// Phi_i = 0 (E_i infinite), 1 where only Phi_{i+1} = 0.
+__device__ inline float ksdf_alpha(float e, float en, bool valid) {
+  if (!valid || isinf(e)) return 0.f;
+  if (isinf(en)) return 1.f;
+  return fmaxf((en - e) / (1.f + en), 0.f);
+}
+
 // NeuS interval weights of one surface over the samples held in two slots:
-// a_i from the logistic CDF at samples i and i+1, w_i = a_i prod_{l<i} (1 - a_l).
+// w_i = a_i prod_{l<i} (1 - a_l).
 __device__ inline void ksdf_weights(double d0, double d1, double off, double beta, int N, int lane, float& w0,
                                     float& w1) {
-  const float x0 = (float)(beta * (d0 + off)), x1 = (float)(beta * (d1 + off));
-  const float p0 = 1.f / (1.f + expf(-x0)), p1 = 1.f / (1.f + expf(-x1));
-  // the next sample's CDF: lane+1 of the same slot; lane 63 of slot 0 continues with lane 0 of slot 1
-  float n0 = __shfl_down(p0, 1, 64), n1 = __shfl_down(p1, 1, 64);
-  const float first1 = __shfl(p1, 0, 64);
-  if (lane == 63) n0 = first1;
-  const int i0 = lane, i1 = lane + 64;
-  const float a0 = (i0 < N - 1 && p0 > 0.f) ? fmaxf((p0 - n0) / p0, 0.f) : 0.f;
-  const float a1 = (i1 < N - 1 && p1 > 0.f) ? fmaxf((p1 - n1) / p1, 0.f) : 0.f;
-  const float c0 = ksdf_scan_mul(1.f - a0, lane);
-  const float tot0 = __shfl(c0, 63, 64);
-  const float c1 = ksdf_scan_mul(1.f - a1, lane) * tot0;
-  const float e0 = __shfl_up(c0, 1, 64), e1 = __shfl_up(c1, 1, 64);
-  const float T0 = lane == 0 ? 1.f : e0;
-  const float T1 = lane == 0 ? tot0 : e1;
-  w0 = T0 * a0;
-  w1 = T1 * a1;
+  const float e0 = expf(-(float)(beta * (d0 + off))), e1 = expf(-(float)(beta * (d1 + off)));
+  // the next sample: lane + 1 of the same slot; lane 63 of slot 0 continues with lane 0 of slot 1
+  const float n0 = ksdf_from_above(ksdf_lane(e1, 0), e0), n1 = ksdf_from_above(e1, e1);
+  const float a0 = ksdf_alpha(e0, n0, lane < N - 1), a1 = ksdf_alpha(e1, n1, lane + 64 < N - 1);
+  const float c0 = ksdf_scan_mul(1.f - a0);
+  const float tot0 = ksdf_lane(c0, 63);
+  const float c1 = ksdf_scan_mul(1.f - a1) * tot0;
+  w0 = ksdf_from_below(1.f, c0) * a0;
+  w1 = ksdf_from_below(tot0, c1) * a1;
 }
 
 // Block b -> a contiguous run of rays per XCD (blocks are dealt round-robin to the 8 XCDs).
@@ -260,15 +353,15 @@ __global__ void __launch_bounds__(256) k_ksdf_render(const vs_view* __restrict__
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const double pa = o[a] + tm * v[a];
-        vox[a] = (int)fmin(fmax(floor((pa - P.lo) / P.h_occ), 0.0), (double)(Ro - 1));
+        vox[a] = (int)fmin(fmax(floor((pa - P.lo) * P.inv_occ), 0.0), (double)(Ro - 1));
       }
       const int64_t idx = ((int64_t)vox[2] * Ro + vox[1]) * Ro + vox[0];
       mask |= ((occ[idx >> 5] >> (idx & 31)) & 1u) << q;
     }
     const int c = __popc(mask);
-    const int incl = ksdf_scan_add_i(c, lane);
+    const int incl = ksdf_scan_add_i(c);
     pre = incl - c;
-    M = __shfl(incl, 63, 64);
+    M = __builtin_amdgcn_readlane(incl, 63);
   }
   if (M == 0) {
     if (lane == 0) out[ray] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -322,8 +415,8 @@ __global__ void __launch_bounds__(256) k_ksdf_render(const vs_view* __restrict__
     const bool v0 = lane < Ncur - 1, v1 = lane + 64 < Ncur - 1;
     const float q0 = v0 ? W0 + P.pdf_floor : 0.f, q1 = v1 ? W1 + P.pdf_floor : 0.f;
     const float S = ksdf_sum(q0 + q1);
-    const float c0 = ksdf_scan_add(q0 / S, lane);
-    const float c1 = ksdf_scan_add(q1 / S, lane) + __shfl(c0, 63, 64);
+    const float c0 = ksdf_scan_add(q0 / S);
+    const float c1 = ksdf_scan_add(q1 / S) + ksdf_lane(c0, 63);
     if (lane == 0) L.cdf[0] = 0.f;
     if (v0) L.cdf[lane + 1] = c0;
     if (v1) L.cdf[lane + 65] = c1;
@@ -391,10 +484,8 @@ __global__ void __launch_bounds__(256) k_ksdf_render(const vs_view* __restrict__
     if (i < N - 1) {
       const double px = o[0] + ts[sl] * v[0], py = o[1] + ts[sl] * v[1], pz = o[2] + ts[sl] * v[2];
       app[sl] = ksdf_rgba(P, px, py, pz);
-      const double e = P.normal_eps;
-      const double gx = (ksdf_sdf(P, px + e, py, pz) - ksdf_sdf(P, px - e, py, pz)) / (2.0 * e);
-      const double gy = (ksdf_sdf(P, px, py + e, pz) - ksdf_sdf(P, px, py - e, pz)) / (2.0 * e);
-      const double gz = (ksdf_sdf(P, px, py, pz + e) - ksdf_sdf(P, px, py, pz - e)) / (2.0 * e);
+      double gx, gy, gz;
+      ksdf_sdf_grad(P, px, py, pz, gx, gy, gz);
       const double gn = sqrt((gx * gx + gy * gy) + gz * gz);
       const double vdn = gn > 0.0 ? fabs(((gx / gn) * v[0] + (gy / gn) * v[1]) + (gz / gn) * v[2]) : 0.0;
       aw[sl] = 2.f / (1.f + expf(-10.f * (float)vdn)) - 1.f;
