@@ -385,8 +385,8 @@ vs_status vs_ngp_backward(const float* const* params, const vs_ngp_config* cfg, 
 typedef struct vs_ksdf_field {
   const float* sdf;     /* device, [(sdf_res+1)^3]: main signed distance d */
   const float* rgba;    /* device, 16-byte aligned, [(rgba_res+1)^3][4]: straight RGB and transparency */
-  int32_t sdf_res;      /* 1..1024 */
-  int32_t rgba_res;     /* 1..1024 */
+  int32_t sdf_res;      /* 1..1023 (the grid stays below 2^32 bytes) */
+  int32_t rgba_res;     /* 1..644 (the grid stays below 2^32 bytes) */
   double lo, hi;        /* lo < hi */
 } vs_ksdf_field;
 

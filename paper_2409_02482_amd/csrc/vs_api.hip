@@ -883,8 +883,8 @@ vs_status ksdf_params(const char* who, const vs_ksdf_field* f, const vs_ksdf_opt
   if (!f || !o) return fail(VS_ERR_ARG, "%s: null field or opts", who);
   if (!f->sdf || !f->rgba) return fail(VS_ERR_ARG, "%s: null field grid", who);
   if ((uintptr_t)f->rgba % 16) return fail(VS_ERR_ARG, "%s: rgba grid not 16-byte aligned", who);
-  if (f->sdf_res < 1 || f->sdf_res > 1024 || f->rgba_res < 1 || f->rgba_res > 1024)
-    return fail(VS_ERR_SIZE, "%s: grid resolutions %d, %d outside 1..1024", who, f->sdf_res, f->rgba_res);
+  if (f->sdf_res < 1 || f->sdf_res > 1023 || f->rgba_res < 1 || f->rgba_res > 644)
+    return fail(VS_ERR_SIZE, "%s: grid resolutions %d, %d outside 1..1023, 1..644", who, f->sdf_res, f->rgba_res);
   if (!(std::isfinite(f->lo) && std::isfinite(f->hi) && f->lo < f->hi))
     return fail(VS_ERR_ARG, "%s: need finite lo < hi", who);
   if (o->k < 1 || o->k > VS_KSDF_MAX_SURFACES) return fail(VS_ERR_ARG, "%s: k = %d outside 1..%d", who, o->k,
@@ -919,7 +919,13 @@ vs_status ksdf_params(const char* who, const vs_ksdf_field* f, const vs_ksdf_opt
   P.inv_occ = o->occ_res / (f->hi - f->lo);
   P.inv_2eps = 1.0 / (2.0 * o->normal_eps);
   P.k = o->k;
-  for (int j = 0; j < o->k; ++j) P.off[j] = o->offsets[j];
+  P.factor = 1;
+  for (int j = 0; j < o->k; ++j) {
+    P.off[j] = o->offsets[j];
+    if (!(std::fabs(o->beta * o->offsets[j]) <= 60.0)) P.factor = 0;
+    P.cexp[0][j] = (float)std::exp(-(o->beta / 2.0) * o->offsets[j]);
+    P.cexp[1][j] = (float)std::exp(-o->beta * o->offsets[j]);
+  }
   P.beta = o->beta;
   P.occ_threshold = o->occ_threshold;
   P.half_diag = std::sqrt(3.0) * P.h_occ / 2.0;

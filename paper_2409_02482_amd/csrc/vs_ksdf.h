@@ -33,6 +33,8 @@ struct KsdfParams {
   double lo, hi, h_occ;
   double inv_sdf, inv_rgba, inv_occ;       // R / (hi - lo) of each grid
   double inv_2eps;                         // 1 / (2 normal_eps)
+  float cexp[2][VS_KSDF_MAX_SURFACES];     // exp(-beta_r o_j) for beta_r = beta / 2 (round 0) and beta
+  int32_t factor;                          // 1: every |beta o_j| <= 60, so exp(-beta_r (d + o_j)) = E cexp
   int32_t k;
   double off[VS_KSDF_MAX_SURFACES];
   double beta, occ_threshold, half_diag;
@@ -41,11 +43,20 @@ struct KsdfParams {
   double normal_eps;
 };
 
+// Grid element at a 32-bit element index (grids are limited to 2^32 bytes, so
+// the byte offset is a 32-bit unsigned value added to a scalar base address).
+__device__ inline float ksdf_at(const float* __restrict__ g, uint32_t i) {
+  return *(const float*)((const char*)g + (i << 2));
+}
+__device__ inline float4 ksdf_at4(const float4* __restrict__ g, uint32_t i) {
+  return *(const float4*)((const char*)g + (i << 4));
+}
+
 // Cell of a point along one axis: base vertex and weight (FP64).
-__device__ inline void ksdf_cell(double p, double lo, double inv, int R, int32_t& b, double& f) {
+__device__ inline void ksdf_cell(double p, double lo, double inv, int R, uint32_t& b, double& f) {
   const double c = fmin(fmax((p - lo) * inv, 0.0), (double)R);
   const double bb = fmin(floor(c), (double)(R - 1));
-  b = (int32_t)bb;
+  b = (uint32_t)bb;
   f = c - bb;
 }
 
@@ -53,12 +64,12 @@ __device__ inline void ksdf_cell(double p, double lo, double inv, int R, int32_t
 // evaluation: corners z-major, then y, then x).
 __device__ inline double ksdf_sdf(const KsdfParams& P, double px, double py, double pz) {
   const int R = P.sdf_res;
-  int32_t ix, iy, iz;
+  uint32_t ix, iy, iz;
   double fx, fy, fz;
   ksdf_cell(px, P.lo, P.inv_sdf, R, ix, fx);
   ksdf_cell(py, P.lo, P.inv_sdf, R, iy, fy);
   ksdf_cell(pz, P.lo, P.inv_sdf, R, iz, fz);
-  const int32_t R1 = R + 1;
+  const uint32_t R1 = R + 1;
   double acc = 0.0;
 #pragma unroll
   for (int dz = 0; dz < 2; ++dz)
@@ -67,19 +78,19 @@ __device__ inline double ksdf_sdf(const KsdfParams& P, double px, double py, dou
 #pragma unroll
       for (int dx = 0; dx < 2; ++dx) {
         const double w = ((dx ? fx : 1.0 - fx) * (dy ? fy : 1.0 - fy)) * (dz ? fz : 1.0 - fz);
-        const int32_t idx = ((iz + dz) * R1 + (iy + dy)) * R1 + (ix + dx);
-        acc += w * (double)P.sdf[idx];
+        const uint32_t idx = ((iz + dz) * R1 + (iy + dy)) * R1 + (ix + dx);
+        acc += w * (double)ksdf_at(P.sdf, idx);
       }
   return acc;
 }
 
 // Sum over the 4 grid lines through the cell along one axis: sum_q w4[q] lerp(g[b + o4[q]], g[b + o4[q] + stride], f).
-__device__ inline double ksdf_lines(const float* __restrict__ g, int32_t b, int32_t stride, const int32_t o4[4],
+__device__ inline double ksdf_lines(const float* __restrict__ g, uint32_t b, uint32_t stride, const uint32_t o4[4],
                                     const double w4[4], double f) {
   double acc = 0.0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const double g0 = (double)g[b + o4[q]], g1 = (double)g[b + o4[q] + stride];
+    const double g0 = (double)ksdf_at(g, b + o4[q]), g1 = (double)ksdf_at(g, b + o4[q] + stride);
     acc += w4[q] * (g0 + f * (g1 - g0));
   }
   return acc;
@@ -91,17 +102,17 @@ __device__ inline double ksdf_lines(const float* __restrict__ g, int32_t b, int3
 __device__ inline void ksdf_sdf_grad(const KsdfParams& P, double px, double py, double pz, double& gx, double& gy,
                                      double& gz) {
   const int R = P.sdf_res;
-  const int32_t R1 = R + 1, R2 = R1 * R1;
+  const uint32_t R1 = R + 1, R2 = R1 * R1;
   const double e = P.normal_eps;
-  int32_t ix, iy, iz;
+  uint32_t ix, iy, iz;
   double fx, fy, fz;
   ksdf_cell(px, P.lo, P.inv_sdf, R, ix, fx);
   ksdf_cell(py, P.lo, P.inv_sdf, R, iy, fy);
   ksdf_cell(pz, P.lo, P.inv_sdf, R, iz, fz);
   const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
   double w4[4];
-  int32_t o4[4];
-  int32_t b;
+  uint32_t o4[4];
+  uint32_t b;
   double f, hi_v, lo_v;
   // x
 #pragma unroll
@@ -141,13 +152,13 @@ __device__ inline void ksdf_sdf_grad(const KsdfParams& P, double px, double py, 
 // Trilinear lookup of the RGBA grid: FP64 cell coordinates, FP32 weights and sum.
 __device__ inline float4 ksdf_rgba(const KsdfParams& P, double px, double py, double pz) {
   const int R = P.rgba_res;
-  int32_t ix, iy, iz;
+  uint32_t ix, iy, iz;
   double dfx, dfy, dfz;
   ksdf_cell(px, P.lo, P.inv_rgba, R, ix, dfx);
   ksdf_cell(py, P.lo, P.inv_rgba, R, iy, dfy);
   ksdf_cell(pz, P.lo, P.inv_rgba, R, iz, dfz);
   const float fx = (float)dfx, fy = (float)dfy, fz = (float)dfz;
-  const int32_t R1 = R + 1;
+  const uint32_t R1 = R + 1;
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
   for (int dz = 0; dz < 2; ++dz)
@@ -156,7 +167,7 @@ __device__ inline float4 ksdf_rgba(const KsdfParams& P, double px, double py, do
 #pragma unroll
       for (int dx = 0; dx < 2; ++dx) {
         const float w = ((dx ? fx : 1.f - fx) * (dy ? fy : 1.f - fy)) * (dz ? fz : 1.f - fz);
-        const float4 g = P.rgba[((iz + dz) * R1 + (iy + dy)) * R1 + (ix + dx)];
+        const float4 g = ksdf_at4(P.rgba, ((iz + dz) * R1 + (iy + dy)) * R1 + (ix + dx));
         acc.x += w * g.x;
         acc.y += w * g.y;
         acc.z += w * g.z;
@@ -268,14 +279,33 @@ struct KsdfLds {
 __device__ inline float ksdf_alpha(float e, float en, bool valid) {
   if (!valid || isinf(e)) return 0.f;
   if (isinf(en)) return 1.f;
-  return fmaxf((en - e) / (1.f + en), 0.f);
+  return fmaxf((en - e) * __builtin_amdgcn_rcpf(1.f + en), 0.f);
 }
 
-// NeuS interval weights of one surface over the samples held in two slots:
-// w_i = a_i prod_{l<i} (1 - a_l).
-__device__ inline void ksdf_weights(double d0, double d1, double off, double beta, int N, int lane, float& w0,
-                                    float& w1) {
-  const float e0 = expf(-(float)(beta * (d0 + off))), e1 = expf(-(float)(beta * (d1 + off)));
+// exp(-beta_r (d + o_j)) at the two slots: E cexp_j from E = exp(-beta_r d)
+// shared by all surfaces, or one exponential per surface when the offsets are
+// too large for the factor to stay a normal float.
+__device__ inline void ksdf_surface_exp(const KsdfParams& P, int round, int j, double beta_r, double d0, double d1,
+                                        float E0, float E1, float& e0, float& e1) {
+  if (P.factor) {
+    e0 = E0 * P.cexp[round][j];
+    e1 = E1 * P.cexp[round][j];
+  } else {
+    e0 = expf(-(float)(beta_r * (d0 + P.off[j])));
+    e1 = expf(-(float)(beta_r * (d1 + P.off[j])));
+  }
+}
+
+// NeuS interval weights of one surface when all N <= 64 samples sit in slot 0.
+__device__ inline float ksdf_weights1(float e0, int N, int lane) {
+  const float n0 = ksdf_from_above(e0, e0);
+  const float a0 = ksdf_alpha(e0, n0, lane < N - 1);
+  return ksdf_from_below(1.f, ksdf_scan_mul(1.f - a0)) * a0;
+}
+
+// NeuS interval weights of one surface over the samples held in two slots,
+// w_i = a_i prod_{l<i} (1 - a_l), from e = exp(-beta_r d_j) at each sample.
+__device__ inline void ksdf_weights(float e0, float e1, int N, int lane, float& w0, float& w1) {
   // the next sample: lane + 1 of the same slot; lane 63 of slot 0 continues with lane 0 of slot 1
   const float n0 = ksdf_from_above(ksdf_lane(e1, 0), e0), n1 = ksdf_from_above(e1, e1);
   const float a0 = ksdf_alpha(e0, n0, lane < N - 1), a1 = ksdf_alpha(e1, n1, lane + 64 < N - 1);
@@ -349,14 +379,14 @@ __global__ void __launch_bounds__(256) k_ksdf_render(const vs_view* __restrict__
     for (int q = 0; q < sp; ++q) {
       const int s = lane * sp + q;
       const double tm = t_in + ((double)s + 0.5) * D;
-      int vox[3];
+      uint32_t vox[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         const double pa = o[a] + tm * v[a];
-        vox[a] = (int)fmin(fmax(floor((pa - P.lo) * P.inv_occ), 0.0), (double)(Ro - 1));
+        vox[a] = (uint32_t)fmin(fmax(floor((pa - P.lo) * P.inv_occ), 0.0), (double)(Ro - 1));
       }
-      const int64_t idx = ((int64_t)vox[2] * Ro + vox[1]) * Ro + vox[0];
-      mask |= ((occ[idx >> 5] >> (idx & 31)) & 1u) << q;
+      const uint32_t idx = (vox[2] * (uint32_t)Ro + vox[1]) * (uint32_t)Ro + vox[0];
+      mask |= ((*(const uint32_t*)((const char*)occ + ((idx >> 5) << 2)) >> (idx & 31)) & 1u) << q;
     }
     const int c = __popc(mask);
     const int incl = ksdf_scan_add_i(c);
@@ -405,18 +435,29 @@ __global__ void __launch_bounds__(256) k_ksdf_render(const vs_view* __restrict__
   int Ncur = P.n;
   for (int round = 0; round < 2 && m2 > 0; ++round) {
     const double beta_r = round == 0 ? P.beta / 2.0 : P.beta;
+    const float E0 = expf(-(float)(beta_r * ds[0])), E1 = expf(-(float)(beta_r * ds[1]));
     float W0 = 0.f, W1 = 0.f;
-    for (int j = 0; j < P.k; ++j) {
-      float w0, w1;
-      ksdf_weights(ds[0], ds[1], P.off[j], beta_r, Ncur, lane, w0, w1);
-      W0 += w0;
-      W1 += w1;
+    if (Ncur > 64) {
+      for (int j = 0; j < P.k; ++j) {
+        float e0, e1, w0, w1;
+        ksdf_surface_exp(P, round, j, beta_r, ds[0], ds[1], E0, E1, e0, e1);
+        ksdf_weights(e0, e1, Ncur, lane, w0, w1);
+        W0 += w0;
+        W1 += w1;
+      }
+    } else {
+      for (int j = 0; j < P.k; ++j) {
+        float e0, e1;
+        ksdf_surface_exp(P, round, j, beta_r, ds[0], ds[1], E0, E1, e0, e1);
+        W0 += ksdf_weights1(e0, Ncur, lane);
+      }
     }
     const bool v0 = lane < Ncur - 1, v1 = lane + 64 < Ncur - 1;
     const float q0 = v0 ? W0 + P.pdf_floor : 0.f, q1 = v1 ? W1 + P.pdf_floor : 0.f;
     const float S = ksdf_sum(q0 + q1);
-    const float c0 = ksdf_scan_add(q0 / S);
-    const float c1 = ksdf_scan_add(q1 / S) + ksdf_lane(c0, 63);
+    const float rS = 1.f / S;
+    const float c0 = ksdf_scan_add(q0 * rS);
+    const float c1 = ksdf_scan_add(q1 * rS) + ksdf_lane(c0, 63);
     if (lane == 0) L.cdf[0] = 0.f;
     if (v0) L.cdf[lane + 1] = c0;
     if (v1) L.cdf[lane + 65] = c1;
@@ -494,9 +535,11 @@ __global__ void __launch_bounds__(256) k_ksdf_render(const vs_view* __restrict__
 
   // per-surface quadrature and fixed-order blend
   float R = 0.f, G = 0.f, B = 0.f, T = 1.f;
+  const float E0 = expf(-(float)(P.beta * ds[0])), E1 = expf(-(float)(P.beta * ds[1]));
   for (int j = 0; j < P.k; ++j) {
-    float w0, w1;
-    ksdf_weights(ds[0], ds[1], P.off[j], P.beta, N, lane, w0, w1);
+    float e0, e1, w0, w1;
+    ksdf_surface_exp(P, 1, j, P.beta, ds[0], ds[1], E0, E1, e0, e1);
+    ksdf_weights(e0, e1, N, lane, w0, w1);
     const float cr = ksdf_sum(w0 * app[0].x + w1 * app[1].x);
     const float cg = ksdf_sum(w0 * app[0].y + w1 * app[1].y);
     const float cb = ksdf_sum(w0 * app[0].z + w1 * app[1].z);

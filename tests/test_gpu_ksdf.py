@@ -8,7 +8,8 @@ oracle's (the GPU's interval weights are FP32, which shifts the CDF by about
 1e-6 relative: a sample drawn where the pdf is only its floor moves by up to
 one gap, and carries no weight, which the colour bar confirms).
 Cases: ragged views, a distant camera whose corner rays miss the cube,
-k = 1 / 2 / 3 / 7, no importance sampling, two-slot sample counts, 64 and
+k = 1 / 2 / 3 / 7, offsets inside and outside the main surface (up to
+77 / beta), no importance sampling, two-slot sample counts, 64 and
 2048 march steps, odd occupancy resolutions (a partial last bit word), and the
 full-size grids and views of the bench on sampled rays.
 """
@@ -36,11 +37,11 @@ def torch_cuda():
     return torch
 
 
-def _setup(torch, grids, k, occ_res, **kw):
+def _setup(torch, grids, k, occ_res, offsets=None, **kw):
     import paper_2409_02482_amd as P
     field = P.KsdfField(torch.from_numpy(grids.sdf).cuda(), grids.sdf_res,
                         torch.from_numpy(grids.rgba.reshape(-1, 4)).cuda(), grids.rgba_res, grids.lo, grids.hi)
-    offs = S.ksdf_offsets(k, BETA)
+    offs = S.ksdf_offsets(k, BETA) if offsets is None else offsets
     opts = P.ksdf_opts(offs, BETA, occ_res=occ_res, **kw)
     oopts = K.KsdfOpts(offsets=offs, beta=BETA, occ_res=occ_res,
                        **{a: b for a, b in kw.items() if a in ("n_uniform", "n_importance", "march_steps")})
@@ -72,6 +73,9 @@ CASES = {
     "k7": dict(k=7, kw=dict(n_uniform=64, n_importance=32, march_steps=1024)),
     "k1_no_importance": dict(k=1, kw=dict(n_uniform=32, n_importance=0, march_steps=64)),
     "two_slots": dict(k=2, kw=dict(n_uniform=100, n_importance=28, march_steps=2048)),
+    # offsets beyond 60 / beta: one exponential per surface instead of a shared factor
+    "wide_offsets": dict(k=3, kw=dict(n_uniform=64, n_importance=32, march_steps=512),
+                         offsets=[-0.02, 0.03, 0.07]),
 }
 
 
@@ -81,7 +85,7 @@ def test_ksdf_render_matches_oracle(torch_cuda, case):
     import paper_2409_02482_amd as P
     c = CASES[case]
     g = S.ksdf_grids(62, 48, 24)
-    P, field, opts, oopts = _setup(torch, g, c["k"], 40, **c["kw"])
+    P, field, opts, oopts = _setup(torch, g, c["k"], 40, offsets=c.get("offsets"), **c["kw"])
     cams = S.ring_cameras(63, 2, [(40, 32), (37, 29)])
     cams.append(S.make_camera(23, 19, [0.5, 0.4, 4.5]))          # corner rays miss the cube
     views = P.Views(cams)
