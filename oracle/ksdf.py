@@ -40,7 +40,10 @@ Definitions (our reading where the paper gives no formula):
     (existing samples first on ties);
   * per surface C_j = sum_i w_ij xi(x_i), A_j = sum_i w_ij alpha_w(x_i) A(x_i),
     alpha_w = 2 sigmoid(10 |v . n|) - 1 (Sec. 4.2) with n the normalised
-    central-difference gradient of d (step eps_n per axis; supplement);
+    gradient of d (supplement: normals are normalised SDF gradients; the
+    paper takes its network's gradient by finite differences, a grid field's
+    gradient is exact: the derivative of the trilinear interpolant inside
+    the cell that holds the point);
   * blend (Sec. 4.2, exclusive product as for the meshes): RGB = sum_j C_j A_j
     prod_{l<j} (1 - A_l), alpha = 1 - prod_j (1 - A_j).
 """
@@ -73,7 +76,6 @@ class KsdfOpts:
     n_importance: int = 32          # m, added in two rounds of m/2
     march_steps: int = 1024
     pdf_floor: float = 1e-5
-    normal_eps: float = 1e-4
 
     @property
     def k(self) -> int:
@@ -251,14 +253,33 @@ def merge_sorted(t: np.ndarray, d: np.ndarray, tn: np.ndarray, dn: np.ndarray):
     return np.take_along_axis(tt, order, 1), np.take_along_axis(dd, order, 1)
 
 
-def sdf_normals(field: KsdfField, p: np.ndarray, eps: float) -> np.ndarray:
-    g = np.zeros_like(p)
-    for a in range(3):
-        e = np.zeros(3)
-        e[a] = eps
-        g[:, a] = (sdf_at(field, p + e) - sdf_at(field, p - e)) / (2.0 * eps)
-    n = np.linalg.norm(g, axis=1, keepdims=True)
-    return np.divide(g, n, out=np.zeros_like(g), where=n > 0.0)
+def sdf_gradient(field: KsdfField, p: np.ndarray) -> np.ndarray:
+    """[n, 3] gradient of the trilinear SDF inside the cell holding each point (the cell of ``trilinear``)."""
+    res, lo, hi = field.sdf_res, field.lo, field.hi
+    g = np.asarray(field.sdf, np.float64).reshape(-1)
+    inv = res / (hi - lo)
+    c = np.clip((np.asarray(p, np.float64) - lo) * inv, 0.0, float(res))
+    b = np.minimum(np.floor(c), res - 1).astype(np.int64)
+    f = c - b
+    out = np.zeros((c.shape[0], 3))
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                idx = ((b[:, 2] + dz) * (res + 1) + (b[:, 1] + dy)) * (res + 1) + (b[:, 0] + dx)
+                wx = f[:, 0] if dx else 1 - f[:, 0]
+                wy = f[:, 1] if dy else 1 - f[:, 1]
+                wz = f[:, 2] if dz else 1 - f[:, 2]
+                sx, sy, sz = (1 if dx else -1), (1 if dy else -1), (1 if dz else -1)
+                out[:, 0] += sx * wy * wz * g[idx]
+                out[:, 1] += sy * wx * wz * g[idx]
+                out[:, 2] += sz * wx * wy * g[idx]
+    return out * inv
+
+
+def sdf_normals(field: KsdfField, p: np.ndarray) -> np.ndarray:
+    grad = sdf_gradient(field, p)
+    n = np.linalg.norm(grad, axis=1, keepdims=True)
+    return np.divide(grad, n, out=np.zeros_like(grad), where=n > 0.0)
 
 
 # --------------------------------------------------------------------------
@@ -292,7 +313,7 @@ def render_rays(field: KsdfField, opts: KsdfOpts, occ: np.ndarray, o: np.ndarray
             t, d = merge_sorted(t, d, tn, sdf_along(tn))
         p = (ro[:, None, :] + t[:, :-1, None] * rv[:, None, :]).reshape(-1, 3)
         app = rgba_at(field, p).reshape(rows.size, N - 1, 4)
-        nrm = sdf_normals(field, p, opts.normal_eps).reshape(rows.size, N - 1, 3)
+        nrm = sdf_normals(field, p).reshape(rows.size, N - 1, 3)
         vdotn = np.abs((nrm * rv[:, None, :]).sum(-1))
         alpha_w = 2.0 / (1.0 + np.exp(-10.0 * vdotn)) - 1.0
         Tacc = np.ones(rows.size)

@@ -17,7 +17,8 @@
   V6  importance sampling: linear inversion of the piecewise-constant pdf
       equals np.interp on the CDF; zero weights give the uniform-pdf quantiles;
       merging keeps the samples sorted and their SDF values attached
-  V7  normals of an affine SDF are its unit gradient; blending constant
+  V7  normals of an affine SDF are its unit gradient, and on a generic grid the
+      gradient equals central differences inside cells; blending constant
       appearance over planes facing the camera gives the closed-form
       composite sum_j xi a alpha_w (1 - a alpha_w)^j
   V8  rays that miss the cube or meet no occupied voxel render zero
@@ -198,7 +199,16 @@ def test_v7_normals_and_blend_closed_form():
     n = np.array([0.6, 0.0, -0.8])
     g = _grids((0.1, *n), res=8)
     p = np.random.default_rng(7).uniform(-0.8, 0.8, (40, 3))
-    np.testing.assert_allclose(K.sdf_normals(g, p, 1e-4), np.tile(n, (40, 1)), atol=1e-6)
+    np.testing.assert_allclose(K.sdf_normals(g, p), np.tile(n, (40, 1)), atol=1e-6)
+    # a generic grid: the gradient equals central differences of the lookup away from cell faces
+    gg = S.ksdf_grids(7, 12, 4)
+    rng = np.random.default_rng(8)
+    inv = 12 / (gg.hi - gg.lo)
+    q = rng.uniform(gg.lo + 0.1, gg.hi - 0.1, (400, 3))
+    frac = (q - gg.lo) * inv % 1.0
+    q = q[((frac > 0.01) & (frac < 0.99)).all(1)]
+    fd = np.stack([(K.sdf_at(gg, q + h) - K.sdf_at(gg, q - h)) / 2e-5 for h in np.eye(3) * 1e-5], 1)
+    np.testing.assert_allclose(K.sdf_gradient(gg, q), fd, rtol=1e-6, atol=1e-8)
     # planes z = 0 - o_j facing a camera on +z; constant appearance (xi, a); densities peaked enough for
     # each surface's weights to sum to 1 over the samples
     xi, a = np.array([0.2, 0.5, 0.8]), 0.6
