@@ -401,8 +401,7 @@ typedef struct vs_ksdf_field {
  *               then beta); n_uniform + n_importance <= VS_KSDF_MAX_SAMPLES.
  * march_steps:  equal steps over the ray's interval in the cube that resolve its occupied part
  *               (a step is occupied iff the voxel holding its midpoint is); multiple of 64, <= 2048.
- * pdf_floor:    added to every interval weight before the importance pdf is normalised.
- * normal_eps:   central-difference step of the SDF normals. */
+ * pdf_floor:    added to every interval weight before the importance pdf is normalised. */
 typedef struct vs_ksdf_opts {
   int32_t k;                                 /* 1..VS_KSDF_MAX_SURFACES */
   double offsets[VS_KSDF_MAX_SURFACES];
@@ -413,7 +412,6 @@ typedef struct vs_ksdf_opts {
   int32_t n_importance;                      /* even, >= 0 */
   int32_t march_steps;
   double pdf_floor;                          /* > 0 */
-  double normal_eps;                         /* > 0 */
 } vs_ksdf_opts;
 
 /* 32-bit words of an occupancy bit grid of resolution occ_res (0 if invalid):
@@ -434,7 +432,8 @@ vs_status vs_ksdf_occupancy(const vs_ksdf_field* field, const vs_ksdf_opts* opts
  *      are summed over surfaces, floored, normalised and inverted at u_q = (q + 1/2)/(n_importance/2)
  *      (linear within an interval); new samples are merged in order;
  *   3. per surface C_j = sum_i w_ij xi(x_i), A_j = sum_i w_ij alpha_w(x_i) a(x_i), (xi, a) the RGBA
- *      field, alpha_w = 2 sigmoid(10 |v.n|) - 1, n the normalised central difference of d;
+ *      field, alpha_w = 2 sigmoid(10 |v.n|) - 1, n the normalised gradient of d (the derivative of
+ *      the trilinear interpolant inside the cell holding x_i);
  *   4. out = (sum_j C_j A_j prod_{l<j} (1 - A_l), 1 - prod_j (1 - A_j)).
  * Rays that miss the cube or meet no occupied step give zeros.
  * occ: from vs_ksdf_occupancy with the same field and opts.

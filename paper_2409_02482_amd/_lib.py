@@ -80,7 +80,7 @@ class VsKsdfField(ctypes.Structure):
 class VsKsdfOpts(ctypes.Structure):
     _fields_ = [("k", c_i32), ("offsets", c_f64 * 16), ("beta", c_f64), ("occ_threshold", c_f64),
                 ("occ_res", c_i32), ("n_uniform", c_i32), ("n_importance", c_i32), ("march_steps", c_i32),
-                ("pdf_floor", c_f64), ("normal_eps", c_f64)]
+                ("pdf_floor", c_f64)]
 
 
 # name -> (restype, argtypes); every symbol declared in include/vs.h

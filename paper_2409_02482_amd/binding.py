@@ -362,14 +362,13 @@ class KsdfField:
 
 
 def ksdf_opts(offsets, beta: float, occ_threshold: float = 1e-4, occ_res: int = 256, n_uniform: int = 64,
-              n_importance: int = 32, march_steps: int = 1024, pdf_floor: float = 1e-5,
-              normal_eps: float = 1e-4) -> C.VsKsdfOpts:
+              n_importance: int = 32, march_steps: int = 1024, pdf_floor: float = 1e-5) -> C.VsKsdfOpts:
     offs = [float(o) for o in offsets]
     if not 1 <= len(offs) <= 16:
         raise ValueError("1..16 surfaces")
     return C.VsKsdfOpts(len(offs), (ctypes.c_double * 16)(*(offs + [0.0] * (16 - len(offs)))), float(beta),
                         float(occ_threshold), int(occ_res), int(n_uniform), int(n_importance), int(march_steps),
-                        float(pdf_floor), float(normal_eps))
+                        float(pdf_floor))
 
 
 def ksdf_occupancy(field: KsdfField, opts: C.VsKsdfOpts, occ: Optional[torch.Tensor] = None, stream=None):

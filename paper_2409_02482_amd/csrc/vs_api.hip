@@ -903,8 +903,6 @@ vs_status ksdf_params(const char* who, const vs_ksdf_field* f, const vs_ksdf_opt
   if (o->march_steps < 64 || o->march_steps > 2048 || o->march_steps % 64)
     return fail(VS_ERR_ARG, "%s: march_steps must be a multiple of 64 in 64..2048", who);
   if (!(std::isfinite(o->pdf_floor) && o->pdf_floor > 0.0)) return fail(VS_ERR_ARG, "%s: pdf_floor must be > 0", who);
-  if (!(std::isfinite(o->normal_eps) && o->normal_eps > 0.0))
-    return fail(VS_ERR_ARG, "%s: normal_eps must be > 0", who);
   std::memset(&P, 0, sizeof(P));
   P.sdf = f->sdf;
   P.rgba = (const float4*)f->rgba;
@@ -917,7 +915,6 @@ vs_status ksdf_params(const char* who, const vs_ksdf_field* f, const vs_ksdf_opt
   P.inv_sdf = f->sdf_res / (f->hi - f->lo);
   P.inv_rgba = f->rgba_res / (f->hi - f->lo);
   P.inv_occ = o->occ_res / (f->hi - f->lo);
-  P.inv_2eps = 1.0 / (2.0 * o->normal_eps);
   P.k = o->k;
   P.factor = 1;
   for (int j = 0; j < o->k; ++j) {
@@ -933,7 +930,6 @@ vs_status ksdf_params(const char* who, const vs_ksdf_field* f, const vs_ksdf_opt
   P.m = o->n_importance;
   P.steps = o->march_steps;
   P.pdf_floor = (float)o->pdf_floor;
-  P.normal_eps = o->normal_eps;
   return VS_OK;
 }
 

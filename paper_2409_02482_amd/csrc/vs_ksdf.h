@@ -32,7 +32,6 @@ struct KsdfParams {
   int32_t sdf_res, rgba_res, occ_res;
   double lo, hi, h_occ;
   double inv_sdf, inv_rgba, inv_occ;       // R / (hi - lo) of each grid
-  double inv_2eps;                         // 1 / (2 normal_eps)
   float cexp[2][VS_KSDF_MAX_SURFACES];     // exp(-beta_r o_j) for beta_r = beta / 2 (round 0) and beta
   int32_t factor;                          // 1: every |beta o_j| <= 60, so exp(-beta_r (d + o_j)) = E cexp
   int32_t k;
@@ -40,7 +39,6 @@ struct KsdfParams {
   double beta, occ_threshold, half_diag;
   int32_t n, m, steps;
   float pdf_floor;
-  double normal_eps;
 };
 
 // Grid element at a 32-bit element index (grids are limited to 2^32 bytes, so
@@ -84,69 +82,38 @@ __device__ inline double ksdf_sdf(const KsdfParams& P, double px, double py, dou
   return acc;
 }
 
-// Sum over the 4 grid lines through the cell along one axis: sum_q w4[q] lerp(g[b + o4[q]], g[b + o4[q] + stride], f).
-__device__ inline double ksdf_lines(const float* __restrict__ g, uint32_t b, uint32_t stride, const uint32_t o4[4],
-                                    const double w4[4], double f) {
-  double acc = 0.0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const double g0 = (double)ksdf_at(g, b + o4[q]), g1 = (double)ksdf_at(g, b + o4[q] + stride);
-    acc += w4[q] * (g0 + f * (g1 - g0));
-  }
-  return acc;
-}
-
-// Central differences of the SDF at p along x, y and z (step normal_eps),
-// each from the two shifted points; the weights and lines of the two axes
-// that do not move are shared by both points.
+// Gradient of the trilinear SDF inside the cell that holds p (the cell of
+// ksdf_sdf): along each axis, the corner differences of the cell's 4 grid
+// lines weighted by the other two axes' weights.
 __device__ inline void ksdf_sdf_grad(const KsdfParams& P, double px, double py, double pz, double& gx, double& gy,
                                      double& gz) {
   const int R = P.sdf_res;
-  const uint32_t R1 = R + 1, R2 = R1 * R1;
-  const double e = P.normal_eps;
   uint32_t ix, iy, iz;
   double fx, fy, fz;
   ksdf_cell(px, P.lo, P.inv_sdf, R, ix, fx);
   ksdf_cell(py, P.lo, P.inv_sdf, R, iy, fy);
   ksdf_cell(pz, P.lo, P.inv_sdf, R, iz, fz);
+  const uint32_t R1 = R + 1, base = (iz * R1 + iy) * R1 + ix;
+  double g[2][2][2];
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) g[dz][dy][dx] = (double)ksdf_at(P.sdf, base + (dz * R1 + dy) * R1 + dx);
   const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
-  double w4[4];
-  uint32_t o4[4];
-  uint32_t b;
-  double f, hi_v, lo_v;
-  // x
+  double sx = 0.0, sy = 0.0, sz = 0.0;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    w4[q] = wy[q & 1] * wz[q >> 1];
-    o4[q] = (iz + (q >> 1)) * R2 + (iy + (q & 1)) * R1;
-  }
-  ksdf_cell(px + e, P.lo, P.inv_sdf, R, b, f);
-  hi_v = ksdf_lines(P.sdf, b, 1, o4, w4, f);
-  ksdf_cell(px - e, P.lo, P.inv_sdf, R, b, f);
-  lo_v = ksdf_lines(P.sdf, b, 1, o4, w4, f);
-  gx = (hi_v - lo_v) * P.inv_2eps;
-  // y
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    w4[q] = wx[q & 1] * wz[q >> 1];
-    o4[q] = (iz + (q >> 1)) * R2 + ix + (q & 1);
-  }
-  ksdf_cell(py + e, P.lo, P.inv_sdf, R, b, f);
-  hi_v = ksdf_lines(P.sdf, b * R1, R1, o4, w4, f);
-  ksdf_cell(py - e, P.lo, P.inv_sdf, R, b, f);
-  lo_v = ksdf_lines(P.sdf, b * R1, R1, o4, w4, f);
-  gy = (hi_v - lo_v) * P.inv_2eps;
-  // z
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    w4[q] = wx[q & 1] * wy[q >> 1];
-    o4[q] = (iy + (q >> 1)) * R1 + ix + (q & 1);
-  }
-  ksdf_cell(pz + e, P.lo, P.inv_sdf, R, b, f);
-  hi_v = ksdf_lines(P.sdf, b * R2, R2, o4, w4, f);
-  ksdf_cell(pz - e, P.lo, P.inv_sdf, R, b, f);
-  lo_v = ksdf_lines(P.sdf, b * R2, R2, o4, w4, f);
-  gz = (hi_v - lo_v) * P.inv_2eps;
+    for (int b = 0; b < 2; ++b) {
+      sx += (wy[a] * wz[b]) * (g[b][a][1] - g[b][a][0]);
+      sy += (wx[a] * wz[b]) * (g[b][1][a] - g[b][0][a]);
+      sz += (wx[a] * wy[b]) * (g[1][b][a] - g[0][b][a]);
+    }
+  gx = sx * P.inv_sdf;
+  gy = sy * P.inv_sdf;
+  gz = sz * P.inv_sdf;
 }
 
 // Trilinear lookup of the RGBA grid: FP64 cell coordinates, FP32 weights and sum.

@@ -47,7 +47,7 @@ def test_struct_layouts_match_c(C, tmp_path):
                     'sizeof(vs_shade_opts), offsetof(vs_view, pix_offset), offsetof(vs_shade_opts, target),'
                     'offsetof(vs_raster_opts, list_capacity), sizeof(vs_sh_texture), sizeof(vs_sh_opts),'
                     'offsetof(vs_sh_opts, view_alpha)); printf("%zu %zu %zu %zu\\n", sizeof(vs_ngp_config),'
-                    'sizeof(vs_ksdf_field), sizeof(vs_ksdf_opts), offsetof(vs_ksdf_opts, normal_eps));'
+                    'sizeof(vs_ksdf_field), sizeof(vs_ksdf_opts), offsetof(vs_ksdf_opts, pdf_floor));'
                     'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
@@ -57,7 +57,7 @@ def test_struct_layouts_match_c(C, tmp_path):
             ctypes.sizeof(C.VsShadeOpts), C.VsView.pix_offset.offset, C.VsShadeOpts.target.offset,
             C.VsRasterOpts.list_capacity.offset, ctypes.sizeof(C.VsShTexture), ctypes.sizeof(C.VsShOpts),
             C.VsShOpts.view_alpha.offset, ctypes.sizeof(C.VsNgpConfig), ctypes.sizeof(C.VsKsdfField),
-            ctypes.sizeof(C.VsKsdfOpts), C.VsKsdfOpts.normal_eps.offset]
+            ctypes.sizeof(C.VsKsdfOpts), C.VsKsdfOpts.pdf_floor.offset]
     assert got == want
 
 
@@ -225,11 +225,11 @@ def test_ksdf_host_validation(C):
 
     def opts(**kw):
         a = dict(k=3, offsets=[0.0, 0.01, 0.02], beta=1000.0, occ_threshold=1e-4, occ_res=64, n_uniform=64,
-                 n_importance=32, march_steps=1024, pdf_floor=1e-5, normal_eps=1e-4)
+                 n_importance=32, march_steps=1024, pdf_floor=1e-5)
         a.update(kw)
         offs = list(a["offsets"]) + [0.0] * (16 - len(a["offsets"]))
         return C.VsKsdfOpts(a["k"], (ctypes.c_double * 16)(*offs), a["beta"], a["occ_threshold"], a["occ_res"],
-                            a["n_uniform"], a["n_importance"], a["march_steps"], a["pdf_floor"], a["normal_eps"])
+                            a["n_uniform"], a["n_importance"], a["march_steps"], a["pdf_floor"])
 
     def occ(o, f=field, out=0x30000):
         return L.vs_ksdf_occupancy(ctypes.byref(f), ctypes.byref(o), out, None)
