@@ -25,7 +25,8 @@ Definitions (our reading where the paper gives no formula):
     cube, clipped to t >= 0;
   * occupied space along a ray is resolved by S equal march steps over that
     interval: step s covers [t_in + s D, t_in + (s+1) D], D = (t_out - t_in)/S,
-    and is occupied iff the voxel holding its midpoint is; the n uniform
+    and is occupied iff the voxel holding its midpoint t_m is (voxel
+    coordinate (o - lo) Ro/(hi - lo) + t_m v Ro/(hi - lo)); the n uniform
     samples sit at occupied-length positions rho_i = (i + 1/2) M / n (M
     occupied steps): sample i lies in the floor(rho_i)-th occupied step at
     fraction rho_i - floor(rho_i);
@@ -195,8 +196,10 @@ def march_occupied(o, v, t_in, t_out, occ: np.ndarray, lo: float, hi: float, ste
     inv = Ro / (hi - lo)
     D = (t_out - t_in) / steps
     tm = t_in[:, None] + (np.arange(steps)[None, :] + 0.5) * D[:, None]
-    p = o[:, None, :] + tm[..., None] * v[:, None, :]
-    vox = np.clip(np.floor((p - lo) * inv), 0, Ro - 1).astype(np.int64)
+    # voxel coordinate of o + tm v, as (o - lo) inv + tm (v inv)
+    A = (o - lo) * inv
+    B = v * inv
+    vox = np.clip(np.floor(A[:, None, :] + tm[..., None] * B[:, None, :]), 0, Ro - 1).astype(np.int64)
     return occ[vox[..., 2], vox[..., 1], vox[..., 0]].astype(bool)
 
 
