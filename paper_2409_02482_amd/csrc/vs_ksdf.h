@@ -343,14 +343,21 @@ __global__ void __launch_bounds__(256) k_ksdf_render(const vs_view* __restrict__
   if (hit) {
     D = (t_out - t_in) / (double)P.steps;
     const int Ro = P.occ_res;
+    double A[3], B[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      A[a] = (o[a] - P.lo) * P.inv_occ;
+      B[a] = v[a] * P.inv_occ;
+    }
+#pragma unroll 4
     for (int q = 0; q < sp; ++q) {
       const int s = lane * sp + q;
       const double tm = t_in + ((double)s + 0.5) * D;
       uint32_t vox[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const double pa = o[a] + tm * v[a];
-        vox[a] = (uint32_t)fmin(fmax(floor((pa - P.lo) * P.inv_occ), 0.0), (double)(Ro - 1));
+        // floor, then clamp to [0, Ro - 1] (the coordinate stays within a rounding of [0, Ro])
+        vox[a] = (uint32_t)min(max((int)floor(A[a] + tm * B[a]), 0), Ro - 1);
       }
       const uint32_t idx = (vox[2] * (uint32_t)Ro + vox[1]) * (uint32_t)Ro + vox[0];
       mask |= ((*(const uint32_t*)((const char*)occ + ((idx >> 5) << 2)) >> (idx & 31)) & 1u) << q;
