@@ -213,16 +213,18 @@ def ksdf_flops_per_ray(k, n, m, steps):
     march: per step the midpoint (2) and three voxel coordinates (4 each);
     SDF lookup: three cell coordinates (2 each) and 8 corners (weight 2 + accumulate 2);
     RGBA lookup: cell coordinates (6) and 8 corners (weight 2 + 4 channels x 2);
+    SDF gradient: cell coordinates (6), per axis 4 grid lines (difference, two weight products,
+    accumulate) and a scale (3);
     interval weight per sample and surface: argument (2), logistic CDF (3), a_i (3), T_i and w_i (2);
-    per interval of the final samples: position (6), normal (6 lookups, 3 differences, normalise 9,
-    dot 5), alpha_w (4), per surface accumulation of C and A (10).
+    per interval of the final samples: position (6), normal (gradient, normalise 9, dot 5),
+    alpha_w (4), per surface accumulation of C and A (10).
     """
     N = n + m
-    sdf, rgba = 6 + 8 * 4, 6 + 8 * 10
+    sdf, rgba, grad = 6 + 8 * 4, 6 + 8 * 10, 6 + 3 * 4 * 4 + 3
     flops = steps * 14
     flops += N * (6 + sdf)                                   # sample positions and their SDF
     flops += (n + (n + m // 2) + N) * k * 10                 # weights of both importance rounds and the final pass
-    flops += (N - 1) * (6 + rgba + 6 * sdf + 3 + 9 + 5 + 4 + 10 * k)
+    flops += (N - 1) * (6 + rgba + grad + 9 + 5 + 4 + 10 * k)
     return flops
 
 
@@ -318,7 +320,7 @@ def run_ksdf(args):
         from oracle import ksdf as K
         oopts = K.KsdfOpts(offsets=offs, beta=beta, occ_res=256, n_uniform=n, n_importance=m, march_steps=steps)
         occ_np = K.occupancy(grids, oopts)
-        res_["cpu_baseline"] = ksdf_cpu_baseline(grids, oopts, occ_np, cams, 4000)
+        res_["cpu_baseline"] = ksdf_cpu_baseline(grids, oopts, occ_np, cams, 48000)
     print(json.dumps(res_), flush=True)
 
 
