@@ -324,6 +324,197 @@ def run_ksdf(args):
     print(json.dumps(res_), flush=True)
 
 
+FIT_METRICS = {
+    "fit": "shaded px·layers/s per texture-fitting iteration (k=7, 128 views at 800², RGB L2, Adam + clamp, "
+           "graph replay); % HBM peak",
+    "fit_l1q": "shaded px·layers/s per quantisation-aware fitting iteration (k=7, 128 views at 800², RGB L1, "
+               "Adam on logits of 8-bit textures, graph replay); % HBM peak",
+    "ngp": "shaded px·layers/s per neural-texture fitting iteration (k=7, 128 views at 800², hash grid + MLP "
+           "baked at 1024², RGB L2, Adam, graph replay); % HBM peak",
+}
+
+
+def fit_cpu_baseline(sc, targets_np, loss, n_threads, n_views):
+    """The oracle's fused-loss adjoint (forward recomputed inside) on a bounded sample of the views."""
+    import concurrent.futures as cf
+
+    import oracle as O
+    O.build(force=False)
+    vis = [O.raster_layers(sc.layers, sc.cameras[v]) for v in range(n_views)]
+
+    def one(v):
+        O.backward(sc.layers, sc.textures, sc.cameras[v], vis[v], target=targets_np[v], loss=loss)
+        return int((vis[v] != np.uint64(0xFFFFFFFFFFFFFFFF)).sum())
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(n_threads) as ex:
+        covered = sum(ex.map(one, range(n_views)))
+    dt = time.perf_counter() - t0
+    return {"value": covered / dt, "unit": "px*layers/s", "cores": n_threads, "kind": "oracle",
+            "sample": f"{n_views} of the 128 views (full 800x800, k=7, visibility given), fused {loss.upper()} "
+                      f"adjoint, {n_threads} threads, {dt:.1f} s wall"}
+
+
+def ngp_cpu_baseline(sc, targets_np, fit, n_threads, n_views):
+    """One iteration's parts on the oracle: one layer's bake + network backward at 1024^2 and the renderer's
+    adjoint on a sample of views, scaled to all 7 layers and 128 views."""
+    import concurrent.futures as cf
+
+    import threadpoolctl
+
+    import oracle as O
+    from oracle import ngp as N
+    O.build(force=False)
+    import scenes as S
+    cfg = N.NgpConfig(fit.cfg.resolutions, fit.cfg.log2_table)
+    prm = S.ngp_params(5, 0, len(cfg.resolutions), cfg.log2_table, table_scale=1e-2).astype(np.float64)
+    W = fit.sizes[0][0]
+    with threadpoolctl.threadpool_limits(n_threads):
+        t0 = time.perf_counter()
+        tex = N.bake(prm, cfg, W, W)
+        N.backward(prm, cfg, W, W, np.full((W, W, 4), 1e-3))
+        t_net = time.perf_counter() - t0
+    vis = [O.raster_layers(sc.layers, sc.cameras[v]) for v in range(n_views)]
+    texs = [tex.astype(np.float32)] * sc.k
+
+    def one(v):
+        O.backward(sc.layers, texs, sc.cameras[v], vis[v], target=targets_np[v])
+        return int((vis[v] != np.uint64(0xFFFFFFFFFFFFFFFF)).sum())
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(n_threads) as ex:
+        covered = sum(ex.map(one, range(n_views)))
+    t_ren = time.perf_counter() - t0
+    t_iter = t_net * sc.k + t_ren * len(sc.cameras) / n_views
+    covered_all = covered * len(sc.cameras) / n_views
+    return {"value": covered_all / t_iter, "unit": "px*layers/s", "cores": n_threads, "kind": "oracle",
+            "sample": f"1 of {sc.k} layers' bake + network backward at {W}^2 ({t_net:.1f} s) and {n_views} of "
+                      f"{len(sc.cameras)} views' adjoint ({t_ren:.1f} s), {n_threads} threads, scaled to one "
+                      f"iteration ({t_iter:.0f} s)"}
+
+
+def run_fit(args):
+    """Fitting iterations on fixed meshes (visibility rasterised once): graph-replayed, with a phase split
+    from eager iterations."""
+    import torch
+
+    import paper_2409_02482_amd as P
+    import scenes as S
+    from paper_2409_02482_amd.fit import NeuralTextureFit, TextureFit, render_targets
+    wl = args.workload
+    log("[bench] building the config-5 scene")
+    sc = S.make_config(5, n_views=128, resolution=(800, 800))
+    targets = render_targets(sc.layers, sc.cameras, sc.textures_gt)
+    iters = args.warmup + args.steps + 8
+    loss = "l1" if wl == "fit_l1q" else "l2"
+    if wl == "ngp":
+        fit = NeuralTextureFit(sc.layers, sc.cameras, targets, tex_size=sc.textures[0].shape[1], max_iters=2 * iters)
+    else:
+        fit = TextureFit(sc.layers, sc.cameras, sc.textures, targets, mode="graph", max_iters=2 * iters, loss=loss,
+                         quantize=(wl == "fit_l1q"))
+    s = fit.stream
+    k, views = fit.k, fit.views
+    P_tot = views.total_pixels
+    covered = int((fit.vis != -1).sum().item())
+
+    if wl == "ngp":
+        names = ["bake", "grad_zero", "shade_bwd", "ngp_backward", "adam"]
+
+        def phases(ev):
+            ev[0].record(s)
+            P.ngp_bake(fit.params, fit.cfg, fit.sizes, tex=fit.tex, ws=fit.nws, stream=s)
+            ev[1].record(s)
+            with torch.cuda.stream(s):
+                for g in fit.gtex:
+                    g.zero_()
+            ev[2].record(s)
+            P.render_backward(fit.layers, fit.tex, views, fit.vis, fit.ws, grad_tex=fit.gtex, target=fit.targets,
+                              loss_scale=1.0 / fit.n_scalars, sse=fit.sse, loss=fit.loss, stream=s)
+            ev[3].record(s)
+            P.ngp_backward(fit.params, fit.cfg, fit.sizes, fit.tex, fit.gtex, fit.nws, grad_params=fit.gp, stream=s)
+            ev[4].record(s)
+            P.adam_step(fit.params, fit.gp, fit.m, fit.v, fit.step, lr=fit.lr, lo=-1e30, hi=1e30, sse=fit.sse,
+                        history=fit.history, stream=s)
+            ev[5].record(s)
+    else:
+        names = ["shade_bwd", "adam"]
+
+        def phases(ev):
+            ev[0].record(s)
+            P.render_backward(fit.layers, fit.tex, views, fit.vis, fit.ws, grad_tex=fit.grads, target=fit.targets,
+                              loss_scale=fit.loss_scale, sse=fit.sse, loss=fit.loss, stream=s)
+            ev[1].record(s)
+            if fit.quantize:
+                P.adam_step_squeezed(fit.params, fit.grads, fit.m, fit.v, fit.tex, fit.step, levels=fit.levels,
+                                     lr=fit.lr, betas=fit.betas, eps=fit.eps, sse=fit.sse, history=fit.history,
+                                     stream=s)
+            else:
+                P.adam_step(fit.params, fit.grads, fit.m, fit.v, fit.step, lr=fit.lr, betas=fit.betas, eps=fit.eps,
+                            sse=fit.sse, history=fit.history, stream=s)
+            ev[2].record(s)
+
+    log("[bench] eager iterations (phase split)")
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for _ in range(args.warmup + 3)]
+    for ev in evs:
+        phases(ev)
+    s.synchronize()
+    ph = np.array([[ev[i].elapsed_time(ev[i + 1]) for i in range(len(names))] for ev in evs[args.warmup:]])
+    ms_phase = ph.mean(0)
+    log("[bench] graph replay")
+    fit.capture()
+    fit.run(max(args.warmup, 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms_graph = fit.run(args.steps)
+    torch.cuda.synchronize()
+    ms_wall = (time.perf_counter() - t0) / args.steps * 1e3
+
+    # algorithmic bytes per launch of the adjoint: keys, target, texels touched, gradient read-modify-write, mesh
+    grads = fit.gtex if wl == "ngp" else fit.grads
+    P.render_backward(fit.layers, fit.tex, views, fit.vis, fit.ws, grad_tex=grads, target=fit.targets,
+                      loss_scale=1.0, sse=None, loss=fit.loss, stream=s)
+    s.synchronize()
+    U = [int((g != 0).any(dim=-1).sum().item()) for g in grads]
+    G = sum(12 * m.n_vert + 8 * m.n_vert + 12 * m.n_tri for m in sc.layers)
+    planes = sum(16 * int(g.shape[0]) * int(g.shape[1]) for g in grads)
+    bm = {"shade_bwd": 8 * k * P_tot + 16 * P_tot + 16 * sum(U) + 2 * planes + G}
+    n_par = sum(int(p.numel()) for p in fit.params)
+    # Adam: parameter, gradient (read + reset), two moments, each read and written (+ texture write if squeezed)
+    bm["adam"] = n_par * (4 * 8 + (4 if wl == "fit_l1q" else 0))
+    dom = names[int(np.argmax(ms_phase))]
+    if dom not in bm:
+        dom = "shade_bwd"
+    i_dom = names.index(dom)
+    achieved = bm[dom] / (ms_phase[i_dom] * 1e-3) / 1e9
+    h = fit.loss_history()
+    res = {
+        "metric": FIT_METRICS[wl], "value": covered / (ms_graph * 1e-3), "unit": "px*layers/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_graph, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"k={k} displaced shells, 128 ring views at 800x800, targets rendered from seeded "
+                               f"ground-truth textures, {loss.upper()} loss"
+                               + (", 8-bit quantised logits" if wl == "fit_l1q" else "")
+                               + (", neural textures (8 levels 16..1024, 2^16 entries, MLP 64-64) baked at 1024^2"
+                                  if wl == "ngp" else ", 1024^2 f32 RGBA textures"),
+                   "views": len(sc.cameras), "k": k, "pixels": P_tot, "covered_px_layers": covered},
+        "wall_ms_per_step": ms_wall,
+        "phases_ms": {n: float(m) for n, m in zip(names, ms_phase)},
+        "loss_first_last": [float(h[0]), float(h[-1])] if len(h) else None,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(dom)},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        n = max(1, min(args.cpu_threads, os.cpu_count() or 1))
+        # seeded targets (the CPU timing takes no GPU output); 64 views keep the sample at seconds of CPU work
+        tg = S.uniform_targets(5, sc.cameras[:64 if wl != "ngp" else 32])
+        if wl == "ngp":
+            res["cpu_baseline"] = ngp_cpu_baseline(sc, tg, fit, n, len(tg))
+        else:
+            res["cpu_baseline"] = fit_cpu_baseline(sc, tg, loss, n, len(tg))
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -335,10 +526,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=8)
     ap.add_argument("--unfused", action="store_true", help="separate forward shading pass before the adjoint")
-    ap.add_argument("--workload", default="metric", choices=["metric", "cfg4", "sh", "ksdf"],
+    ap.add_argument("--workload", default="metric", choices=["metric", "cfg4", "sh", "ksdf", "fit", "fit_l1q", "ngp"],
                     help="metric: k=7, 64 views at 1024^2; cfg4: k=9, 299,208 tris/layer, 64 mixed-size views; "
                          "sh: the metric scene rendered forward with baked 8-bit SH textures (degree 3, 2048^2 base); "
-                         "ksdf: k-SDF volume rendering of the implicit stage (8 views at 512^2)")
+                         "ksdf: k-SDF volume rendering of the implicit stage (8 views at 512^2); "
+                         "fit / fit_l1q / ngp: texture-fitting iterations on config 5 (L2; L1 on 8-bit logits; "
+                         "neural textures)")
     ap.add_argument("--graph", action="store_true", help="replay the step from a captured HIP graph")
     ap.add_argument("--autotune", action="store_true", help="pick the raster bin size with vs_autotune")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -355,6 +548,8 @@ def main():
         return run_sh(args)
     if args.workload == "ksdf":
         return run_ksdf(args)
+    if args.workload in ("fit", "fit_l1q", "ngp"):
+        return run_fit(args)
 
     import torch
 
