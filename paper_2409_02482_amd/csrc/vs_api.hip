@@ -965,7 +965,7 @@ extern "C" vs_status vs_ksdf_render(const vs_ksdf_field* field, const vs_ksdf_op
   if ((uintptr_t)out_rgba % 16 || (layers && (uintptr_t)layers % 16) || (samples && (uintptr_t)samples % 8))
     return fail(VS_ERR_ARG, "vs_ksdf_render: misaligned output");
   const int64_t total = views->host[views->n_views].pix_offset;
-  const int64_t blocks = ((total + vs::kKsdfWaves - 1) / vs::kKsdfWaves + 7) / 8 * 8;
+  const int64_t blocks = ((total + vs::kKsdfRays - 1) / vs::kKsdfRays + 7) / 8 * 8;
   if (blocks > INT32_MAX) return fail(VS_ERR_SIZE, "vs_ksdf_render: too many pixels");
   hipLaunchKernelGGL(vs::k_ksdf_render, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, views->dev,
                      views->n_views, total, P, occ, (float4*)out_rgba, (float4*)layers, samples);

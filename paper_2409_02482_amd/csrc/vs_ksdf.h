@@ -3,11 +3,11 @@
 //
 // Fields live on vertex grids over the cube [lo, hi]^3 ([z][y][x] order) and
 // are read trilinearly.  The occupancy grid is one thread per voxel, decided in
-// FP64 and packed to bits with a wavefront ballot.  Rendering is one wavefront
-// per pixel ray: the ray's march steps are spread over the 64 lanes (a lane
-// owns a contiguous run of steps, so occupied-length ranks are a prefix sum of
-// per-lane counts), and the ray's samples sit one per lane in up to two slots
-// (sample i in lane i % 64, slot i / 64).  Transmittance is a multiplicative
+// FP64 and packed to bits with a wavefront ballot.  Rendering is one pixel ray
+// per half wavefront (32 lanes): the ray's march steps are spread over the
+// lanes (a lane owns a contiguous run of steps, so occupied-length ranks are a
+// prefix sum of per-lane counts), and the ray's samples sit one per lane in up
+// to four slots (sample i in lane i % 32, slot i / 32).  Transmittance is a multiplicative
 // scan across lanes, the importance CDF an additive scan, inversion a binary
 // search over the CDF in the wave's LDS, and the merge of new samples a rank
 // computation (existing samples first on ties) followed by a scatter in LDS.
@@ -23,7 +23,8 @@
 
 namespace vs {
 
-constexpr int kKsdfWaves = 4;      // rays in flight per 256-thread block
+constexpr int kKsdfWaves = 4;      // wavefronts per 256-thread block
+constexpr int kKsdfRays = 2 * kKsdfWaves;   // rays per block (two per wavefront)
 constexpr int kKsdfMaxN = VS_KSDF_MAX_SAMPLES;
 
 struct KsdfParams {
@@ -171,8 +172,10 @@ __global__ void __launch_bounds__(256) k_ksdf_occupancy(KsdfParams P, uint32_t* 
 }
 
 // ---------------------------------------------------------------------------
-// wavefront helpers (64 lanes, DPP: row shifts within 16-lane rows, row
-// broadcasts across rows, whole-wave shifts by one lane)
+// half-wavefront helpers: a wavefront renders two rays, one per 32-lane half
+// (DPP row shifts within 16-lane rows, a row broadcast from row 0 to row 1 and
+// from row 2 to row 3, whole-wave shifts by one lane with the half edges
+// patched)
 // ---------------------------------------------------------------------------
 template <int CTRL, int ROW_MASK = 0xf>
 __device__ inline float ksdf_dpp(float old, float x) {
@@ -183,46 +186,55 @@ __device__ inline int ksdf_dpp_i(int old, int x) {
   return __builtin_amdgcn_update_dpp(old, x, CTRL, ROW_MASK, 0xf, false);
 }
 
-// Inclusive prefix sum over the wave.
-__device__ inline int ksdf_scan_add_i(int x) {
+// Inclusive prefix sum / product within each half.
+__device__ inline int ksdf_hscan_add_i(int x) {
   x += ksdf_dpp_i<0x111>(0, x);
   x += ksdf_dpp_i<0x112>(0, x);
   x += ksdf_dpp_i<0x114>(0, x);
   x += ksdf_dpp_i<0x118>(0, x);
   x += ksdf_dpp_i<0x142, 0xa>(0, x);
-  x += ksdf_dpp_i<0x143, 0xc>(0, x);
   return x;
 }
-
-__device__ inline float ksdf_scan_add(float x) {
+__device__ inline float ksdf_hscan_add(float x) {
   x += ksdf_dpp<0x111>(0.f, x);
   x += ksdf_dpp<0x112>(0.f, x);
   x += ksdf_dpp<0x114>(0.f, x);
   x += ksdf_dpp<0x118>(0.f, x);
   x += ksdf_dpp<0x142, 0xa>(0.f, x);
-  x += ksdf_dpp<0x143, 0xc>(0.f, x);
   return x;
 }
-
-// Inclusive prefix product over the wave.
-__device__ inline float ksdf_scan_mul(float x) {
+__device__ inline float ksdf_hscan_mul(float x) {
   x *= ksdf_dpp<0x111>(1.f, x);
   x *= ksdf_dpp<0x112>(1.f, x);
   x *= ksdf_dpp<0x114>(1.f, x);
   x *= ksdf_dpp<0x118>(1.f, x);
   x *= ksdf_dpp<0x142, 0xa>(1.f, x);
-  x *= ksdf_dpp<0x143, 0xc>(1.f, x);
   return x;
 }
 
-__device__ inline float ksdf_lane(float x, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l)); }
+// Value of lane l of this lane's half.
+__device__ inline float ksdf_hlane(float x, int l, int h) {
+  const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+  const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32 + l));
+  return h ? b : a;
+}
+__device__ inline int ksdf_hlane_i(int x, int l, int h) {
+  const int a = __builtin_amdgcn_readlane(x, l), b = __builtin_amdgcn_readlane(x, 32 + l);
+  return h ? b : a;
+}
 
-// Sum over the wave (the same value in every lane).
-__device__ inline float ksdf_sum(float x) { return ksdf_lane(ksdf_scan_add(x), 63); }
+// Sum over this lane's half.
+__device__ inline float ksdf_hsum(float x, int h) { return ksdf_hlane(ksdf_hscan_add(x), 31, h); }
 
-// Value of lane - 1 (lane 0: old) and of lane + 1 (lane 63: old).
-__device__ inline float ksdf_from_below(float old, float x) { return ksdf_dpp<0x138>(old, x); }
-__device__ inline float ksdf_from_above(float old, float x) { return ksdf_dpp<0x130>(old, x); }
+// Value of lane - 1 of the half (old at the half's first lane) and of lane + 1 (nxt at its last lane).
+__device__ inline float ksdf_hbelow(float old, float x, int l) {
+  const float y = ksdf_dpp<0x138>(old, x);
+  return l == 0 ? old : y;
+}
+__device__ inline float ksdf_habove(float nxt, float x, int l) {
+  const float y = ksdf_dpp<0x130>(nxt, x);
+  return l == 31 ? nxt : y;
+}
 
 __device__ inline void ksdf_wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -230,14 +242,17 @@ __device__ inline void ksdf_wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+constexpr int kKsdfSlots = kKsdfMaxN / 32;     // sample slots per lane: sample i in lane i % 32, slot i / 32
+
+// LDS of one ray (half a wavefront).
 struct KsdfLds {
   double t[kKsdfMaxN];      // sorted sample parameters
   double d[kKsdfMaxN];      // their SDF values
   float cdf[kKsdfMaxN];     // importance CDF c_0..c_{N-1}
   double tn[64];            // samples of the current importance round
   double dn[64];
-  int32_t pre[64];          // march: exclusive prefix of occupied steps per lane
-  uint32_t mask[64];        // march: occupied-step bits per lane
+  uint64_t mask[32];        // march: occupied-step bits per lane
+  int32_t pre[32];          // march: exclusive prefix of occupied steps per lane
 };
 
 // NeuS opacity of the interval between two samples from E = exp(-beta d_j) at
@@ -249,38 +264,33 @@ __device__ inline float ksdf_alpha(float e, float en, bool valid) {
   return fmaxf((en - e) * __builtin_amdgcn_rcpf(1.f + en), 0.f);
 }
 
-// exp(-beta_r (d + o_j)) at the two slots: E cexp_j from E = exp(-beta_r d)
-// shared by all surfaces, or one exponential per surface when the offsets are
-// too large for the factor to stay a normal float.
-__device__ inline void ksdf_surface_exp(const KsdfParams& P, int round, int j, double beta_r, double d0, double d1,
-                                        float E0, float E1, float& e0, float& e1) {
-  if (P.factor) {
-    e0 = E0 * P.cexp[round][j];
-    e1 = E1 * P.cexp[round][j];
-  } else {
-    e0 = expf(-(float)(beta_r * (d0 + P.off[j])));
-    e1 = expf(-(float)(beta_r * (d1 + P.off[j])));
+// exp(-beta_r (d + o_j)) per slot: E cexp_j from E = exp(-beta_r d) shared by
+// all surfaces, or one exponential per surface when the offsets are too large
+// for the factor to stay a normal float.
+__device__ inline float ksdf_surface_exp(const KsdfParams& P, int round, int j, double beta_r, double d, float E) {
+  return P.factor ? E * P.cexp[round][j] : expf(-(float)(beta_r * (d + P.off[j])));
+}
+
+// NeuS interval weights of one surface over the NS slots of this half's ray,
+// w_i = a_i prod_{l<i} (1 - a_l) (a multiplicative scan per slot, carried
+// from slot to slot).
+__device__ inline void ksdf_weights(const float (&e)[kKsdfSlots], float (&w)[kKsdfSlots], int NS, int N, int l,
+                                    int h) {
+  float carry = 1.f;
+#pragma unroll
+  for (int sl = 0; sl < kKsdfSlots; ++sl) {
+    if (sl < NS) {
+      const float nxt = sl + 1 < kKsdfSlots && sl + 1 < NS ? ksdf_hlane(e[sl + 1 < kKsdfSlots ? sl + 1 : sl], 0, h)
+                                                           : e[sl];
+      const float en = ksdf_habove(nxt, e[sl], l);
+      const float a = ksdf_alpha(e[sl], en, 32 * sl + l < N - 1);
+      const float c = ksdf_hscan_mul(1.f - a) * carry;
+      w[sl] = ksdf_hbelow(carry, c, l) * a;
+      carry = ksdf_hlane(c, 31, h);
+    } else {
+      w[sl] = 0.f;
+    }
   }
-}
-
-// NeuS interval weights of one surface when all N <= 64 samples sit in slot 0.
-__device__ inline float ksdf_weights1(float e0, int N, int lane) {
-  const float n0 = ksdf_from_above(e0, e0);
-  const float a0 = ksdf_alpha(e0, n0, lane < N - 1);
-  return ksdf_from_below(1.f, ksdf_scan_mul(1.f - a0)) * a0;
-}
-
-// NeuS interval weights of one surface over the samples held in two slots,
-// w_i = a_i prod_{l<i} (1 - a_l), from e = exp(-beta_r d_j) at each sample.
-__device__ inline void ksdf_weights(float e0, float e1, int N, int lane, float& w0, float& w1) {
-  // the next sample: lane + 1 of the same slot; lane 63 of slot 0 continues with lane 0 of slot 1
-  const float n0 = ksdf_from_above(ksdf_lane(e1, 0), e0), n1 = ksdf_from_above(e1, e1);
-  const float a0 = ksdf_alpha(e0, n0, lane < N - 1), a1 = ksdf_alpha(e1, n1, lane + 64 < N - 1);
-  const float c0 = ksdf_scan_mul(1.f - a0);
-  const float tot0 = ksdf_lane(c0, 63);
-  const float c1 = ksdf_scan_mul(1.f - a1) * tot0;
-  w0 = ksdf_from_below(1.f, c0) * a0;
-  w1 = ksdf_from_below(tot0, c1) * a1;
 }
 
 // Block b -> a contiguous run of rays per XCD (blocks are dealt round-robin to the 8 XCDs).
@@ -289,28 +299,32 @@ __device__ inline int64_t ksdf_block() {
   return ((int64_t)blockIdx.x % 8) * chunk + (int64_t)blockIdx.x / 8;
 }
 
-// Five 256-thread blocks per CU (20 waves): the register budget this sets
-// (96 VGPRs) costs a few spills but hides more gather latency than four.
+// Two rays per wavefront, 32 lanes each: the 96 samples of the paper's
+// 64 + 32 fill three slots of 32 exactly.  Blocks of 256 threads (8 rays),
+// five per CU: the 102-register budget costs a few spills but the extra
+// wavefronts hide more of the gather and LDS latency than four blocks do.
 __global__ void __launch_bounds__(256, 5) k_ksdf_render(const vs_view* __restrict__ views, int n_views, int64_t total,
                                                      KsdfParams P, const uint32_t* __restrict__ occ,
                                                      float4* __restrict__ out, float4* __restrict__ layers,
                                                      double* __restrict__ samples) {
-  __shared__ KsdfLds lds_all[kKsdfWaves];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  KsdfLds& L = lds_all[wv];
-  const int64_t ray = ksdf_block() * kKsdfWaves + wv;
-  if (ray >= total) return;
+  __shared__ KsdfLds lds_all[kKsdfRays];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, h = lane >> 5, l = lane & 31;
+  KsdfLds& L = lds_all[2 * wv + h];
+  const int64_t ray = (ksdf_block() * kKsdfWaves + wv) * 2 + h;
+  const bool real = ray < total;
+  if (__builtin_amdgcn_readlane((int)real, 0) == 0) return;      // both halves past the end (ray grows with h)
   const int N = P.n + P.m, m2 = P.m / 2;
 
-  int lo_v = 0, hi_v = n_views - 1;      // the view holding this ray
+  // this half's camera ray
+  const int64_t rr = real ? ray : total - 1;
+  int lo_v = 0, hi_v = n_views - 1;
   while (lo_v < hi_v) {
     const int mid = (lo_v + hi_v + 1) / 2;
-    if (views[mid].pix_offset <= ray) lo_v = mid; else hi_v = mid - 1;
+    if (views[mid].pix_offset <= rr) lo_v = mid; else hi_v = mid - 1;
   }
   const vs_camera& C = views[lo_v].cam;
-  const int64_t pix = ray - views[lo_v].pix_offset;
+  const int64_t pix = rr - views[lo_v].pix_offset;
   const int64_t pi = pix % C.width, pj = pix / C.width;
-
   double o[3], v[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) o[q] = -((C.R[q] * C.t[0] + C.R[3 + q] * C.t[1]) + C.R[6 + q] * C.t[2]);
@@ -323,7 +337,7 @@ __global__ void __launch_bounds__(256, 5) k_ksdf_render(const vs_view* __restric
 
   // slab interval in the cube, t >= 0
   double t_in = 0.0, t_out = INFINITY;
-  bool hit = true;
+  bool hit = real;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (v[a] != 0.0) {
@@ -336,14 +350,11 @@ __global__ void __launch_bounds__(256, 5) k_ksdf_render(const vs_view* __restric
   }
   hit = hit && t_out > t_in;
 
-  // march: lane owns steps [lane sp, (lane + 1) sp)
-  int M = 0;
-  uint32_t mask = 0;
-  int pre = 0;
-  double D = 0.0;
-  const int sp = P.steps / 64;
+  // march: lane l of the half owns steps [l sp, (l + 1) sp)
+  const int sp = P.steps / 32;
+  const double D = hit ? (t_out - t_in) / (double)P.steps : 0.0;
+  uint64_t mask = 0;
   if (hit) {
-    D = (t_out - t_in) / (double)P.steps;
     const int Ro = P.occ_res;
     double A[3], B[3];
 #pragma unroll
@@ -353,7 +364,7 @@ __global__ void __launch_bounds__(256, 5) k_ksdf_render(const vs_view* __restric
     }
 #pragma unroll 4
     for (int q = 0; q < sp; ++q) {
-      const int s = lane * sp + q;
+      const int s = l * sp + q;
       const double tm = t_in + ((double)s + 0.5) * D;
       uint32_t vox[3];
 #pragma unroll
@@ -362,46 +373,50 @@ __global__ void __launch_bounds__(256, 5) k_ksdf_render(const vs_view* __restric
         vox[a] = (uint32_t)min(max((int)floor(A[a] + tm * B[a]), 0), Ro - 1);
       }
       const uint32_t idx = (vox[2] * (uint32_t)Ro + vox[1]) * (uint32_t)Ro + vox[0];
-      mask |= ((*(const uint32_t*)((const char*)occ + ((idx >> 5) << 2)) >> (idx & 31)) & 1u) << q;
+      const uint32_t word = *(const uint32_t*)((const char*)occ + ((idx >> 5) << 2));
+      mask |= (uint64_t)((word >> (idx & 31)) & 1u) << q;
     }
-    const int c = __popc(mask);
-    const int incl = ksdf_scan_add_i(c);
-    pre = incl - c;
-    M = __builtin_amdgcn_readlane(incl, 63);
   }
-  if (M == 0) {
-    if (lane == 0) out[ray] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (layers)
-      for (int j = lane; j < P.k; j += 64) layers[(int64_t)j * total + ray] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (samples)
-      for (int i = lane; i < N; i += 64) samples[ray * N + i] = -1.0;
+  const int cnt = __popcll(mask);
+  const int incl = ksdf_hscan_add_i(cnt);
+  const int M = ksdf_hlane_i(incl, 31, h);
+  const bool live = M > 0;
+  if (__builtin_amdgcn_readlane((int)live, 0) == 0 && __builtin_amdgcn_readlane((int)live, 32) == 0) {
+    if (real && l == 0) out[ray] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (real && layers)
+      for (int j = l; j < P.k; j += 32) layers[(int64_t)j * total + ray] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (real && samples)
+      for (int i = l; i < N; i += 32) samples[ray * N + i] = -1.0;
     return;
   }
-  L.pre[lane] = pre;
-  L.mask[lane] = mask;
+  L.pre[l] = incl - cnt;
+  L.mask[l] = mask;
   ksdf_wave_sync();
 
-  // uniform samples in occupied length
-  double ts[2] = {0.0, 0.0}, ds[2] = {0.0, 0.0};
+  // uniform samples in occupied length (a ray without any: parameter 0 and a far-outside SDF, no weight)
+  double ts[kKsdfSlots], ds[kKsdfSlots];
 #pragma unroll
-  for (int sl = 0; sl < 2; ++sl) {
-    const int i = lane + 64 * sl;
+  for (int sl = 0; sl < kKsdfSlots; ++sl) {
+    ts[sl] = 0.0;
+    ds[sl] = 1e30;
+    const int i = 32 * sl + l;
     if (i < P.n) {
-      const double rho = (((double)i + 0.5) * (double)M) / (double)P.n;
-      const double qf = floor(rho);
-      const int qi = (int)qf;
-      int a = 0, b = 63;                  // largest lane with pre <= qi
-      while (a < b) {
-        const int mid = (a + b + 1) / 2;
-        if (L.pre[mid] <= qi) a = mid; else b = mid - 1;
+      if (live) {
+        const double rho = (((double)i + 0.5) * (double)M) / (double)P.n;
+        const double qf = floor(rho);
+        const int qi = (int)qf;
+        int a = 0, b = 31;                  // largest lane with pre <= qi
+        while (a < b) {
+          const int mid = (a + b + 1) / 2;
+          if (L.pre[mid] <= qi) a = mid; else b = mid - 1;
+        }
+        uint64_t mk = L.mask[a];
+        for (int r = qi - L.pre[a]; r > 0; --r) mk &= mk - 1;
+        const int s = a * sp + (int)__builtin_ctzll(mk);
+        ts[sl] = t_in + ((double)s + (rho - qf)) * D;
+        ds[sl] = ksdf_sdf(P, o[0] + ts[sl] * v[0], o[1] + ts[sl] * v[1], o[2] + ts[sl] * v[2]);
       }
-      uint32_t mk = L.mask[a];
-      for (int r = qi - L.pre[a]; r > 0; --r) mk &= mk - 1;
-      const int s = a * sp + __builtin_ctz(mk);
-      const double t = t_in + ((double)s + (rho - qf)) * D;
-      ts[sl] = t;
-      ds[sl] = ksdf_sdf(P, o[0] + t * v[0], o[1] + t * v[1], o[2] + t * v[2]);
-      L.t[i] = t;
+      L.t[i] = ts[sl];
       L.d[i] = ds[sl];
     }
   }
@@ -411,78 +426,102 @@ __global__ void __launch_bounds__(256, 5) k_ksdf_render(const vs_view* __restric
   int Ncur = P.n;
   for (int round = 0; round < 2 && m2 > 0; ++round) {
     const double beta_r = round == 0 ? P.beta / 2.0 : P.beta;
-    const float E0 = expf(-(float)(beta_r * ds[0])), E1 = expf(-(float)(beta_r * ds[1]));
-    float W0 = 0.f, W1 = 0.f;
-    if (Ncur > 64) {
-      for (int j = 0; j < P.k; ++j) {
-        float e0, e1, w0, w1;
-        ksdf_surface_exp(P, round, j, beta_r, ds[0], ds[1], E0, E1, e0, e1);
-        ksdf_weights(e0, e1, Ncur, lane, w0, w1);
-        W0 += w0;
-        W1 += w1;
-      }
-    } else {
-      for (int j = 0; j < P.k; ++j) {
-        float e0, e1;
-        ksdf_surface_exp(P, round, j, beta_r, ds[0], ds[1], E0, E1, e0, e1);
-        W0 += ksdf_weights1(e0, Ncur, lane);
+    const int NS = (Ncur + 31) / 32;
+    float E[kKsdfSlots], W[kKsdfSlots];
+#pragma unroll
+    for (int sl = 0; sl < kKsdfSlots; ++sl) {
+      E[sl] = sl < NS ? expf(-(float)(beta_r * ds[sl])) : 0.f;
+      W[sl] = 0.f;
+    }
+    for (int j = 0; j < P.k; ++j) {
+      float e[kKsdfSlots], w[kKsdfSlots];
+#pragma unroll
+      for (int sl = 0; sl < kKsdfSlots; ++sl) e[sl] = ksdf_surface_exp(P, round, j, beta_r, ds[sl], E[sl]);
+      ksdf_weights(e, w, NS, Ncur, l, h);
+#pragma unroll
+      for (int sl = 0; sl < kKsdfSlots; ++sl) W[sl] += w[sl];
+    }
+    float q[kKsdfSlots], qs = 0.f;
+#pragma unroll
+    for (int sl = 0; sl < kKsdfSlots; ++sl) {
+      q[sl] = 32 * sl + l < Ncur - 1 ? W[sl] + P.pdf_floor : 0.f;
+      qs += q[sl];
+    }
+    const float rS = 1.f / ksdf_hsum(qs, h);
+    float carry = 0.f;
+#pragma unroll
+    for (int sl = 0; sl < kKsdfSlots; ++sl) {
+      if (sl < NS) {
+        const float c = ksdf_hscan_add(q[sl] * rS) + carry;
+        if (32 * sl + l < Ncur - 1) L.cdf[32 * sl + l + 1] = c;
+        carry = ksdf_hlane(c, 31, h);
       }
     }
-    const bool v0 = lane < Ncur - 1, v1 = lane + 64 < Ncur - 1;
-    const float q0 = v0 ? W0 + P.pdf_floor : 0.f, q1 = v1 ? W1 + P.pdf_floor : 0.f;
-    const float S = ksdf_sum(q0 + q1);
-    const float rS = 1.f / S;
-    const float c0 = ksdf_scan_add(q0 * rS);
-    const float c1 = ksdf_scan_add(q1 * rS) + ksdf_lane(c0, 63);
-    if (lane == 0) L.cdf[0] = 0.f;
-    if (v0) L.cdf[lane + 1] = c0;
-    if (v1) L.cdf[lane + 65] = c1;
+    if (l == 0) L.cdf[0] = 0.f;
     ksdf_wave_sync();
-    double tn = 0.0, dn = 0.0;
-    if (lane < m2) {
-      const double u = ((double)lane + 0.5) / (double)m2;
-      int a = 0, b = Ncur - 1;              // largest i with cdf[i] <= u
-      while (a < b) {
-        const int mid = (a + b + 1) / 2;
-        if ((double)L.cdf[mid] <= u) a = mid; else b = mid - 1;
+    double tn[2] = {0.0, 0.0}, dn[2] = {0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int qn = 32 * r + l;
+      if (qn < m2) {
+        const double u = ((double)qn + 0.5) / (double)m2;
+        int a = 0, b = Ncur - 1;              // largest i with cdf[i] <= u
+        while (a < b) {
+          const int mid = (a + b + 1) / 2;
+          if ((double)L.cdf[mid] <= u) a = mid; else b = mid - 1;
+        }
+        a = min(a, Ncur - 2);
+        const double ca = (double)L.cdf[a], cb = (double)L.cdf[a + 1];
+        const double fr = cb > ca ? (u - ca) / (cb - ca) : 0.0;
+        tn[r] = L.t[a] + fr * (L.t[a + 1] - L.t[a]);
+        dn[r] = live ? ksdf_sdf(P, o[0] + tn[r] * v[0], o[1] + tn[r] * v[1], o[2] + tn[r] * v[2]) : 1e30;
+        L.tn[qn] = tn[r];
+        L.dn[qn] = dn[r];
       }
-      a = min(a, Ncur - 2);
-      const double ca = (double)L.cdf[a], cb = (double)L.cdf[a + 1];
-      const double fr = cb > ca ? (u - ca) / (cb - ca) : 0.0;
-      tn = L.t[a] + fr * (L.t[a + 1] - L.t[a]);
-      dn = ksdf_sdf(P, o[0] + tn * v[0], o[1] + tn * v[1], o[2] + tn * v[2]);
-      L.tn[lane] = tn;
-      L.dn[lane] = dn;
     }
     ksdf_wave_sync();
     // ranks in the merged order (existing samples first on ties)
-    int r0 = -1, r1 = -1, rn = -1;
+    int rk[kKsdfSlots], rn[2] = {-1, -1};
 #pragma unroll
-    for (int sl = 0; sl < 2; ++sl) {
-      const int i = lane + 64 * sl;
-      if (i < Ncur) {
-        int cnt = 0;
-        for (int q = 0; q < m2; ++q) cnt += L.tn[q] < ts[sl];
-        (sl ? r1 : r0) = i + cnt;
+    for (int sl = 0; sl < kKsdfSlots; ++sl) {
+      rk[sl] = -1;
+      const int i = 32 * sl + l;
+      if (sl < NS && i < Ncur) {
+        int c = 0;
+        for (int qn = 0; qn < m2; ++qn) c += L.tn[qn] < ts[sl];
+        rk[sl] = i + c;
       }
     }
-    if (lane < m2) {
-      int a = 0, b = Ncur;                  // number of existing samples <= tn
-      while (a < b) {
-        const int mid = (a + b) / 2;
-        if (L.t[mid] <= tn) a = mid + 1; else b = mid;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int qn = 32 * r + l;
+      if (qn < m2) {
+        int a = 0, b = Ncur;                  // number of existing samples <= tn
+        while (a < b) {
+          const int mid = (a + b) / 2;
+          if (L.t[mid] <= tn[r]) a = mid + 1; else b = mid;
+        }
+        rn[r] = qn + a;
       }
-      rn = lane + a;
     }
     ksdf_wave_sync();
-    if (r0 >= 0) { L.t[r0] = ts[0]; L.d[r0] = ds[0]; }
-    if (r1 >= 0) { L.t[r1] = ts[1]; L.d[r1] = ds[1]; }
-    if (rn >= 0) { L.t[rn] = tn; L.d[rn] = dn; }
+#pragma unroll
+    for (int sl = 0; sl < kKsdfSlots; ++sl)
+      if (rk[sl] >= 0) {
+        L.t[rk[sl]] = ts[sl];
+        L.d[rk[sl]] = ds[sl];
+      }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+      if (rn[r] >= 0) {
+        L.t[rn[r]] = tn[r];
+        L.d[rn[r]] = dn[r];
+      }
     ksdf_wave_sync();
     Ncur += m2;
 #pragma unroll
-    for (int sl = 0; sl < 2; ++sl) {
-      const int i = lane + 64 * sl;
+    for (int sl = 0; sl < kKsdfSlots; ++sl) {
+      const int i = 32 * sl + l;
       if (i < Ncur) {
         ts[sl] = L.t[i];
         ds[sl] = L.d[i];
@@ -491,14 +530,14 @@ __global__ void __launch_bounds__(256, 5) k_ksdf_render(const vs_view* __restric
   }
 
   // appearance and view-dependent attenuation at each interval start
-  float4 app[2];
-  float aw[2];
+  const int NS = (N + 31) / 32;
+  float4 app[kKsdfSlots];
+  float aw[kKsdfSlots];
 #pragma unroll
-  for (int sl = 0; sl < 2; ++sl) {
+  for (int sl = 0; sl < kKsdfSlots; ++sl) {
     app[sl] = make_float4(0.f, 0.f, 0.f, 0.f);
     aw[sl] = 0.f;
-    const int i = lane + 64 * sl;
-    if (i < N - 1) {
+    if (32 * sl + l < N - 1) {
       const double px = o[0] + ts[sl] * v[0], py = o[1] + ts[sl] * v[1], pz = o[2] + ts[sl] * v[2];
       app[sl] = ksdf_rgba(P, px, py, pz);
       double gx, gy, gz;
@@ -511,25 +550,37 @@ __global__ void __launch_bounds__(256, 5) k_ksdf_render(const vs_view* __restric
 
   // per-surface quadrature and fixed-order blend
   float R = 0.f, G = 0.f, B = 0.f, T = 1.f;
-  const float E0 = expf(-(float)(P.beta * ds[0])), E1 = expf(-(float)(P.beta * ds[1]));
+  float E[kKsdfSlots];
+#pragma unroll
+  for (int sl = 0; sl < kKsdfSlots; ++sl) E[sl] = sl < NS ? expf(-(float)(P.beta * ds[sl])) : 0.f;
   for (int j = 0; j < P.k; ++j) {
-    float e0, e1, w0, w1;
-    ksdf_surface_exp(P, 1, j, P.beta, ds[0], ds[1], E0, E1, e0, e1);
-    ksdf_weights(e0, e1, N, lane, w0, w1);
-    const float cr = ksdf_sum(w0 * app[0].x + w1 * app[1].x);
-    const float cg = ksdf_sum(w0 * app[0].y + w1 * app[1].y);
-    const float cb = ksdf_sum(w0 * app[0].z + w1 * app[1].z);
-    const float ca = ksdf_sum(w0 * aw[0] * app[0].w + w1 * aw[1] * app[1].w);
+    float e[kKsdfSlots], w[kKsdfSlots];
+#pragma unroll
+    for (int sl = 0; sl < kKsdfSlots; ++sl) e[sl] = ksdf_surface_exp(P, 1, j, P.beta, ds[sl], E[sl]);
+    ksdf_weights(e, w, NS, N, l, h);
+    float pr = 0.f, pg = 0.f, pb = 0.f, pa = 0.f;
+#pragma unroll
+    for (int sl = 0; sl < kKsdfSlots; ++sl) {
+      pr += w[sl] * app[sl].x;
+      pg += w[sl] * app[sl].y;
+      pb += w[sl] * app[sl].z;
+      pa += w[sl] * aw[sl] * app[sl].w;
+    }
+    const float cr = ksdf_hsum(pr, h), cg = ksdf_hsum(pg, h), cb = ksdf_hsum(pb, h), ca = ksdf_hsum(pa, h);
     R += (T * ca) * cr;
     G += (T * ca) * cg;
     B += (T * ca) * cb;
     T *= 1.f - ca;
-    if (layers && lane == 0) layers[(int64_t)j * total + ray] = make_float4(cr, cg, cb, ca);
+    if (real && layers && l == 0)
+      layers[(int64_t)j * total + ray] = live ? make_float4(cr, cg, cb, ca) : make_float4(0.f, 0.f, 0.f, 0.f);
   }
-  if (lane == 0) out[ray] = make_float4(R, G, B, 1.f - T);
-  if (samples) {
-    if (lane < N) samples[ray * N + lane] = ts[0];
-    if (lane + 64 < N) samples[ray * N + lane + 64] = ts[1];
+  if (real && l == 0) out[ray] = live ? make_float4(R, G, B, 1.f - T) : make_float4(0.f, 0.f, 0.f, 0.f);
+  if (real && samples) {
+#pragma unroll
+    for (int sl = 0; sl < kKsdfSlots; ++sl) {
+      const int i = 32 * sl + l;
+      if (i < N) samples[ray * N + i] = live ? ts[sl] : -1.0;
+    }
   }
 }
 
