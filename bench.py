@@ -49,14 +49,15 @@ def byte_model(scene, n_views, P_v, U, fused=True):
     }
 
 
-def counter_traffic(kernel: str):
-    """HBM bytes per launch of a kernel from the committed rocprofv3 counter summary, if its sources match."""
+def counter_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of a kernel in a workload from the committed rocprofv3 counter summaries, if the
+    kernel sources are still the ones the counters were taken on."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path)).get(kernel)
+        rec = json.load(open(path)).get(f"{workload}/{kernel}")
     except Exception:
         return None
     if not rec:
@@ -194,7 +195,7 @@ def run_sh(args):
                    "covered_px_layers": covered, "bin": args.bin, "sh_texture_bytes": tex_bytes},
         "phases_ms": {n: float(m) for n, m in zip(names, ms_phase)},
         "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(names[dom])},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic("sh", names[dom])},
     }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
@@ -312,7 +313,7 @@ def run_ksdf(args):
         "phases_ms": {"occupancy": float(ms_phase[0]), "render": float(ms_phase[1])},
         "samples_per_s": sampled * (n + m) / (ms_wall * 1e-3),
         "roofline": {"bound": "alu", "kernel": "ksdf_render", "achieved": achieved, "peak": FP_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP_PEAK_TFLOPS, "traffic": counter_traffic("ksdf_render"),
+                     "unit": "TFLOP/s", "frac": achieved / FP_PEAK_TFLOPS, "traffic": counter_traffic("ksdf", "ksdf_render"),
                      "flops_per_ray": ksdf_flops_per_ray(k, n, m, steps)},
     }
     if not args.no_cpu_baseline:
@@ -501,7 +502,7 @@ def run_fit(args):
         "phases_ms": {n: float(m) for n, m in zip(names, ms_phase)},
         "loss_first_last": [float(h[0]), float(h[-1])] if len(h) else None,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(dom)},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(wl, dom)},
     }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
@@ -678,7 +679,7 @@ def main():
         "alg_bytes_per_step": int(sum(bm[n] for n in names)),
         "alg_frac_of_peak_step": sum(bm[n] for n in names) / (ms_wall * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(dom_name)},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(args.workload, dom_name)},
     }
     if graph is not None:
         res["graph_ms_per_step"] = graph_ms
