@@ -967,8 +967,14 @@ extern "C" vs_status vs_ksdf_render(const vs_ksdf_field* field, const vs_ksdf_op
   const int64_t total = views->host[views->n_views].pix_offset;
   const int64_t blocks = ((total + vs::kKsdfRays - 1) / vs::kKsdfRays + 7) / 8 * 8;
   if (blocks > INT32_MAX) return fail(VS_ERR_SIZE, "vs_ksdf_render: too many pixels");
-  hipLaunchKernelGGL(vs::k_ksdf_render, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, views->dev,
-                     views->n_views, total, P, occ, (float4*)out_rgba, (float4*)layers, samples);
+  auto launch = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, views->dev, views->n_views,
+                       total, P, occ, (float4*)out_rgba, (float4*)layers, samples);
+  };
+  const int n_total = P.n + P.m;
+  if (n_total <= 64) launch(vs::k_ksdf_render<2>);
+  else if (n_total <= 96) launch(vs::k_ksdf_render<3>);
+  else launch(vs::k_ksdf_render<4>);
   if ((st = check_launch("vs_ksdf_render"))) return st;
   return ok();
 }

@@ -274,14 +274,13 @@ __device__ inline float ksdf_surface_exp(const KsdfParams& P, int round, int j, 
 // NeuS interval weights of one surface over the NS slots of this half's ray,
 // w_i = a_i prod_{l<i} (1 - a_l) (a multiplicative scan per slot, carried
 // from slot to slot).
-__device__ inline void ksdf_weights(const float (&e)[kKsdfSlots], float (&w)[kKsdfSlots], int NS, int N, int l,
-                                    int h) {
+template <int NSL>
+__device__ inline void ksdf_weights(const float (&e)[NSL], float (&w)[NSL], int NS, int N, int l, int h) {
   float carry = 1.f;
 #pragma unroll
-  for (int sl = 0; sl < kKsdfSlots; ++sl) {
+  for (int sl = 0; sl < NSL; ++sl) {
     if (sl < NS) {
-      const float nxt = sl + 1 < kKsdfSlots && sl + 1 < NS ? ksdf_hlane(e[sl + 1 < kKsdfSlots ? sl + 1 : sl], 0, h)
-                                                           : e[sl];
+      const float nxt = sl + 1 < NSL && sl + 1 < NS ? ksdf_hlane(e[sl + 1 < NSL ? sl + 1 : sl], 0, h) : e[sl];
       const float en = ksdf_habove(nxt, e[sl], l);
       const float a = ksdf_alpha(e[sl], en, 32 * sl + l < N - 1);
       const float c = ksdf_hscan_mul(1.f - a) * carry;
@@ -300,9 +299,10 @@ __device__ inline int64_t ksdf_block() {
 }
 
 // Two rays per wavefront, 32 lanes each: the 96 samples of the paper's
-// 64 + 32 fill three slots of 32 exactly.  Blocks of 256 threads (8 rays),
-// five per CU: the 102-register budget costs a few spills but the extra
+// 64 + 32 fill three slots of 32 exactly (NSL = slots per lane, from the
+// sample count).  Blocks of 256 threads (8 rays), five per CU: the extra
 // wavefronts hide more of the gather and LDS latency than four blocks do.
+template <int NSL>
 __global__ void __launch_bounds__(256, 5) k_ksdf_render(const vs_view* __restrict__ views, int n_views, int64_t total,
                                                      KsdfParams P, const uint32_t* __restrict__ occ,
                                                      float4* __restrict__ out, float4* __restrict__ layers,
@@ -394,9 +394,9 @@ __global__ void __launch_bounds__(256, 5) k_ksdf_render(const vs_view* __restric
   ksdf_wave_sync();
 
   // uniform samples in occupied length (a ray without any: parameter 0 and a far-outside SDF, no weight)
-  double ts[kKsdfSlots], ds[kKsdfSlots];
+  double ts[NSL], ds[NSL];
 #pragma unroll
-  for (int sl = 0; sl < kKsdfSlots; ++sl) {
+  for (int sl = 0; sl < NSL; ++sl) {
     ts[sl] = 0.0;
     ds[sl] = 1e30;
     const int i = 32 * sl + l;
@@ -427,30 +427,30 @@ __global__ void __launch_bounds__(256, 5) k_ksdf_render(const vs_view* __restric
   for (int round = 0; round < 2 && m2 > 0; ++round) {
     const double beta_r = round == 0 ? P.beta / 2.0 : P.beta;
     const int NS = (Ncur + 31) / 32;
-    float E[kKsdfSlots], W[kKsdfSlots];
+    float E[NSL], W[NSL];
 #pragma unroll
-    for (int sl = 0; sl < kKsdfSlots; ++sl) {
+    for (int sl = 0; sl < NSL; ++sl) {
       E[sl] = sl < NS ? expf(-(float)(beta_r * ds[sl])) : 0.f;
       W[sl] = 0.f;
     }
     for (int j = 0; j < P.k; ++j) {
-      float e[kKsdfSlots], w[kKsdfSlots];
+      float e[NSL], w[NSL];
 #pragma unroll
-      for (int sl = 0; sl < kKsdfSlots; ++sl) e[sl] = ksdf_surface_exp(P, round, j, beta_r, ds[sl], E[sl]);
+      for (int sl = 0; sl < NSL; ++sl) e[sl] = ksdf_surface_exp(P, round, j, beta_r, ds[sl], E[sl]);
       ksdf_weights(e, w, NS, Ncur, l, h);
 #pragma unroll
-      for (int sl = 0; sl < kKsdfSlots; ++sl) W[sl] += w[sl];
+      for (int sl = 0; sl < NSL; ++sl) W[sl] += w[sl];
     }
-    float q[kKsdfSlots], qs = 0.f;
+    float q[NSL], qs = 0.f;
 #pragma unroll
-    for (int sl = 0; sl < kKsdfSlots; ++sl) {
+    for (int sl = 0; sl < NSL; ++sl) {
       q[sl] = 32 * sl + l < Ncur - 1 ? W[sl] + P.pdf_floor : 0.f;
       qs += q[sl];
     }
     const float rS = 1.f / ksdf_hsum(qs, h);
     float carry = 0.f;
 #pragma unroll
-    for (int sl = 0; sl < kKsdfSlots; ++sl) {
+    for (int sl = 0; sl < NSL; ++sl) {
       if (sl < NS) {
         const float c = ksdf_hscan_add(q[sl] * rS) + carry;
         if (32 * sl + l < Ncur - 1) L.cdf[32 * sl + l + 1] = c;
@@ -481,9 +481,9 @@ __global__ void __launch_bounds__(256, 5) k_ksdf_render(const vs_view* __restric
     }
     ksdf_wave_sync();
     // ranks in the merged order (existing samples first on ties)
-    int rk[kKsdfSlots], rn[2] = {-1, -1};
+    int rk[NSL], rn[2] = {-1, -1};
 #pragma unroll
-    for (int sl = 0; sl < kKsdfSlots; ++sl) {
+    for (int sl = 0; sl < NSL; ++sl) {
       rk[sl] = -1;
       const int i = 32 * sl + l;
       if (sl < NS && i < Ncur) {
@@ -506,7 +506,7 @@ __global__ void __launch_bounds__(256, 5) k_ksdf_render(const vs_view* __restric
     }
     ksdf_wave_sync();
 #pragma unroll
-    for (int sl = 0; sl < kKsdfSlots; ++sl)
+    for (int sl = 0; sl < NSL; ++sl)
       if (rk[sl] >= 0) {
         L.t[rk[sl]] = ts[sl];
         L.d[rk[sl]] = ds[sl];
@@ -520,7 +520,7 @@ __global__ void __launch_bounds__(256, 5) k_ksdf_render(const vs_view* __restric
     ksdf_wave_sync();
     Ncur += m2;
 #pragma unroll
-    for (int sl = 0; sl < kKsdfSlots; ++sl) {
+    for (int sl = 0; sl < NSL; ++sl) {
       const int i = 32 * sl + l;
       if (i < Ncur) {
         ts[sl] = L.t[i];
@@ -531,10 +531,10 @@ __global__ void __launch_bounds__(256, 5) k_ksdf_render(const vs_view* __restric
 
   // appearance and view-dependent attenuation at each interval start
   const int NS = (N + 31) / 32;
-  float4 app[kKsdfSlots];
-  float aw[kKsdfSlots];
+  float4 app[NSL];
+  float aw[NSL];
 #pragma unroll
-  for (int sl = 0; sl < kKsdfSlots; ++sl) {
+  for (int sl = 0; sl < NSL; ++sl) {
     app[sl] = make_float4(0.f, 0.f, 0.f, 0.f);
     aw[sl] = 0.f;
     if (32 * sl + l < N - 1) {
@@ -550,17 +550,17 @@ __global__ void __launch_bounds__(256, 5) k_ksdf_render(const vs_view* __restric
 
   // per-surface quadrature and fixed-order blend
   float R = 0.f, G = 0.f, B = 0.f, T = 1.f;
-  float E[kKsdfSlots];
+  float E[NSL];
 #pragma unroll
-  for (int sl = 0; sl < kKsdfSlots; ++sl) E[sl] = sl < NS ? expf(-(float)(P.beta * ds[sl])) : 0.f;
+  for (int sl = 0; sl < NSL; ++sl) E[sl] = sl < NS ? expf(-(float)(P.beta * ds[sl])) : 0.f;
   for (int j = 0; j < P.k; ++j) {
-    float e[kKsdfSlots], w[kKsdfSlots];
+    float e[NSL], w[NSL];
 #pragma unroll
-    for (int sl = 0; sl < kKsdfSlots; ++sl) e[sl] = ksdf_surface_exp(P, 1, j, P.beta, ds[sl], E[sl]);
+    for (int sl = 0; sl < NSL; ++sl) e[sl] = ksdf_surface_exp(P, 1, j, P.beta, ds[sl], E[sl]);
     ksdf_weights(e, w, NS, N, l, h);
     float pr = 0.f, pg = 0.f, pb = 0.f, pa = 0.f;
 #pragma unroll
-    for (int sl = 0; sl < kKsdfSlots; ++sl) {
+    for (int sl = 0; sl < NSL; ++sl) {
       pr += w[sl] * app[sl].x;
       pg += w[sl] * app[sl].y;
       pb += w[sl] * app[sl].z;
@@ -577,7 +577,7 @@ __global__ void __launch_bounds__(256, 5) k_ksdf_render(const vs_view* __restric
   if (real && l == 0) out[ray] = live ? make_float4(R, G, B, 1.f - T) : make_float4(0.f, 0.f, 0.f, 0.f);
   if (real && samples) {
 #pragma unroll
-    for (int sl = 0; sl < kKsdfSlots; ++sl) {
+    for (int sl = 0; sl < NSL; ++sl) {
       const int i = 32 * sl + l;
       if (i < N) samples[ray * N + i] = live ? ts[sl] : -1.0;
     }
