@@ -36,7 +36,7 @@ def log(*a):
 
 
 def byte_model(scene, n_views, P_v, U, fused=True):
-    """Algorithmic bytes per launch of each phase (byte model)."""
+    """Algorithmic bytes per launch of each phase: keys, images, targets, touched texels, gradient planes, mesh."""
     k = scene.k
     P = n_views * P_v
     G = sum(12 * m.n_vert + 8 * m.n_vert + 12 * m.n_tri for m in scene.layers)
@@ -541,7 +541,7 @@ def main():
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only; --gpus must be 1 (views would shard across GPUs, "
+        print("bench.py: this benchmark measures one GPU only; --gpus must be 1 (views would shard across GPUs, "
               "with one all-reduce of the texture gradients per step)", file=sys.stderr)
         sys.exit(2)
 

@@ -9,7 +9,7 @@ import scenes as S
 
 EMPTY = np.uint64(0xFFFFFFFFFFFFFFFF)
 
-# tolerances
+# tolerances: FP32 shading after FP64 texel coordinates, FP32 atomics for gradients
 COLOUR_ATOL = 1e-5          # max-abs per channel vs the FP64 oracle
 GRAD_RTOL = 1e-4            # ||g - g_ref||_inf / ||g_ref||_inf
 
