@@ -159,40 +159,131 @@ __device__ inline void ngp_mlp(const float* __restrict__ P, const NgpShape& S, c
 }
 
 // texture = sigmoid(MLP(encoding)) at every texel centre of every layer; with
-// STAGE the layer inputs [e | 1], [h1 | 1], [h2 | 1] are kept for the backward.
+// STAGE the layer inputs e, h1 and h2 are kept for the backward.
+//
+// The three layers are dense products over the block's 256 texels and run on
+// the matrix cores (v_mfma_f32_16x16x4_f32, FP32 in and out) in transposed
+// form, Z^T = W X^T + b: the hidden units are the 16-row M tiles, 16 texels
+// (one texel row of the tile) the N tile.  An MFMA leaves lane l with
+// D[4 (l / 16) + r][l % 16], r = 0..3, and takes its B operand as
+// B[k = l / 16][n = l % 16]; issuing the r-th of four MFMAs with the r-th
+// register of the previous layer's output therefore feeds that output straight
+// back as the next B operand, with the K index permuted to 4 (l / 16) + r; the
+// weights (A operands) are laid out in LDS in that permuted order, one 64-lane
+// fragment per MFMA.  Encodings go through LDS to become layer 1's B operand.
+typedef float ngp_f4 __attribute__((ext_vector_type(4)));
+
 template <int LMAX, bool STAGE>
 __global__ void __launch_bounds__(256) k_ngp_bake(NgpTable T, NgpShape S, NgpStage G) {
+  constexpr int KIN = 2 * LMAX, KS1 = KIN / 4, EST = KIN + 1;
+  __shared__ float w1f[4 * KS1 * 64];     // [mt][ks][lane]: W1[16 mt + lane % 16][4 ks + lane / 16]
+  __shared__ float w2f[64 * 64];          // [mt][it][r][lane]: W2[16 mt + lane % 16][16 it + 4 (lane / 16) + r]
+  __shared__ float w3f[16 * 64];          // [it][r][lane]: W3[lane % 16][16 it + 4 (lane / 16) + r] (rows >= 4: 0)
+  __shared__ float es[4][64 * EST];       // per wave: the encodings of its 64 texels
   const NgpTexel x = ngp_texel(T);
-  if (!x.valid) {
-    if (STAGE) {
-      const uint32_t r = (uint32_t)x.row, R = (uint32_t)G.R;
-      for (int q = 0; q < 2 * S.levels; ++q) G.a1[q * R + r] = 0.f;
-      for (int j = 0; j < kNgpHidden; ++j) G.a2[j * R + r] = 0.f, G.a3[j * R + r] = 0.f;
-    }
-    return;
-  }
-  const int l = x.l;
+  const int l = x.l, tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const float* P = T.params[l];
-  const double u = ((double)x.i + 0.5) / (double)T.w[l], v = ((double)x.j + 0.5) / (double)T.h[l];
-  float e[2 * LMAX];
+  const int nin = 2 * S.levels;
+  for (int f = tid; f < 4 * KS1 * 64; f += 256) {
+    const int ln = f & 63, fr = f >> 6, mt = fr / KS1, ks = fr - mt * KS1;
+    const int m = 16 * mt + (ln & 15), kk = 4 * ks + (ln >> 4);
+    w1f[f] = kk < nin ? P[S.o_w1 + m * nin + kk] : 0.f;
+  }
+  for (int f = tid; f < 64 * 64; f += 256) {
+    const int ln = f & 63, fr = f >> 6, mt = fr >> 4, it = (fr >> 2) & 3, r = fr & 3;
+    w2f[f] = P[S.o_w2 + (16 * mt + (ln & 15)) * kNgpHidden + 16 * it + 4 * (ln >> 4) + r];
+  }
+  for (int f = tid; f < 16 * 64; f += 256) {
+    const int ln = f & 63, fr = f >> 6, it = fr >> 2, r = fr & 3, m = ln & 15;
+    w3f[f] = m < kNgpOut ? P[S.o_w3 + m * kNgpHidden + 16 * it + 4 * (ln >> 4) + r] : 0.f;
+  }
+  // this thread's encoding (zeros outside the texture)
+  float e[KIN];
   uint32_t idx[LMAX][4];
   float wt[LMAX][4];
-  ngp_encode<LMAX>(P, S, u, v, e, idx, wt);
-  float h1[kNgpHidden], z2[kNgpHidden], o[kNgpOut];
-  ngp_mlp<LMAX>(P, S, e, h1, z2, o);
-  reinterpret_cast<float4*>(T.tex[l])[x.t] =
-      make_float4(ngp_sigmoid(o[0]), ngp_sigmoid(o[1]), ngp_sigmoid(o[2]), ngp_sigmoid(o[3]));
+#pragma unroll
+  for (int q = 0; q < KIN; ++q) e[q] = 0.f;
+  if (x.valid) {
+    const double u = ((double)x.i + 0.5) / (double)T.w[l], v = ((double)x.j + 0.5) / (double)T.h[l];
+    ngp_encode<LMAX>(P, S, u, v, e, idx, wt);
+  }
+  float* ew = es[wv];
+#pragma unroll
+  for (int q = 0; q < KIN; ++q) ew[lane * EST + q] = e[q];
   if (STAGE) {
-    // 32-bit element offsets (the workspace holds < 2^31 floats per array): one base + offset each
-    const int nin = 2 * S.levels;
-    const uint32_t r = (uint32_t)x.row, R = (uint32_t)G.R;
+    const uint32_t row = (uint32_t)x.row, R = (uint32_t)G.R;
 #pragma unroll
-    for (int q = 0; q < 2 * LMAX; ++q)
-      if (q < nin) G.a1[q * R + r] = e[q];
+    for (int q = 0; q < KIN; ++q)
+      if (q < nin) G.a1[q * R + row] = e[q];
+  }
+  __syncthreads();
+
+  const int g = lane >> 4, n = lane & 15;
+  const float* b1 = P + S.o_b1;
+  const float* b2 = P + S.o_b2;
+  const float* b3 = P + S.o_b3;
+  const int W = T.w[l], H = T.h[l];
+#pragma unroll 1
+  for (int it_n = 0; it_n < 4; ++it_n) {
+    // N tile: texels 16 it_n + n of this wave = texel row 4 wv + it_n of the tile
+    const int nb = 64 * wv + 16 * it_n + n;
+    const int ti = x.i - (tid & 15) + (nb & 15), tj = x.j - (tid >> 4) + (nb >> 4);
+    const bool valid = ti < W && tj < H;
+    ngp_f4 h[4];
 #pragma unroll
-    for (int j = 0; j < kNgpHidden; ++j) {
-      G.a2[j * R + r] = h1[j];
-      G.a3[j * R + r] = fmaxf(z2[j], 0.0f);
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h[mt][r] = b1[16 * mt + 4 * g + r];
+#pragma unroll
+    for (int ks = 0; ks < KS1; ++ks) {
+      const float bop = ew[(16 * it_n + n) * EST + 4 * ks + g];
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+        h[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(w1f[(mt * KS1 + ks) * 64 + lane], bop, h[mt], 0, 0, 0);
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h[mt][r] = fmaxf(h[mt][r], 0.f);
+    ngp_f4 z[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) z[mt][r] = b2[16 * mt + 4 * g + r];
+#pragma unroll
+    for (int it = 0; it < 4; ++it)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+          z[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(w2f[((mt * 4 + it) * 4 + r) * 64 + lane], h[it][r], z[mt], 0, 0,
+                                                       0);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) z[mt][r] = fmaxf(z[mt][r], 0.f);
+    ngp_f4 o;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o[r] = g == 0 ? b3[r] : 0.f;
+#pragma unroll
+    for (int it = 0; it < 4; ++it)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        o = __builtin_amdgcn_mfma_f32_16x16x4f32(w3f[(it * 4 + r) * 64 + lane], z[it][r], o, 0, 0, 0);
+    if (g == 0 && valid)
+      reinterpret_cast<float4*>(T.tex[l])[(int64_t)tj * W + ti] =
+          make_float4(ngp_sigmoid(o[0]), ngp_sigmoid(o[1]), ngp_sigmoid(o[2]), ngp_sigmoid(o[3]));
+    if (STAGE) {
+      // 32-bit element offsets (the workspace holds < 2^31 floats per array)
+      const uint32_t row = (uint32_t)(blockIdx.x * 256 + nb), R = (uint32_t)G.R;
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const uint32_t m = 16 * mt + 4 * g + r;
+          G.a2[m * R + row] = valid ? h[mt][r] : 0.f;
+          G.a3[m * R + row] = valid ? z[mt][r] : 0.f;
+        }
     }
   }
 }
