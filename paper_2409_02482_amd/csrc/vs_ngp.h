@@ -348,40 +348,75 @@ __global__ void __launch_bounds__(256) k_ngp_texel_bwd1(NgpTable T, NgpShape S, 
 
 // Backward, second half, per texel: d1 = (W2^T d2) [h1 > 0] (staged), de = W1^T d1,
 // and de scattered into the hash tables through the encoding's corners and weights.
+// The two products run on the matrix cores as in the bake (transposed form,
+// 16 texels per N tile, d1 chained into the de product through a permuted K);
+// de goes through LDS back to its texel's thread for the scatter.
 template <int LMAX>
 __global__ void __launch_bounds__(256) k_ngp_texel_bwd2(NgpTable T, NgpShape S, NgpStage G) {
-#pragma clang fp contract(fast)
+  constexpr int KIN = 2 * LMAX, MT1 = (KIN + 15) / 16, DST = KIN + 1;
+  __shared__ float w2t[64 * 64];         // [mt][ks][lane]: W2[4 ks + lane / 16][16 mt + lane % 16]
+  __shared__ float w1t[MT1 * 16 * 64];   // [mt][it][r][lane]: W1[16 it + 4 (lane / 16) + r][16 mt + lane % 16]
+  __shared__ float des[256 * DST];       // de per texel of the block
   const NgpTexel x = ngp_texel(T);
-  const int l = x.l;
+  const int l = x.l, tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, g = lane >> 4, n = lane & 15;
   const float* P = T.params[l];
   const int nin = 2 * S.levels;
-  const uint32_t r = (uint32_t)x.row, R = (uint32_t)G.R;
-  float d1[kNgpHidden];
-#pragma unroll
-  for (int q = 0; q < kNgpHidden; ++q) d1[q] = 0.f;
-  const float* W2 = P + S.o_w2;
-#pragma unroll
-  for (int j = 0; j < kNgpHidden; ++j) {
-    const float d = G.d2[j * R + r];   // zero outside the texture
-#pragma unroll
-    for (int q = 0; q < kNgpHidden; ++q) d1[q] += W2[j * kNgpHidden + q] * d;
+  const uint32_t R = (uint32_t)G.R;
+  for (int f = tid; f < 64 * 64; f += 256) {
+    const int ln = f & 63, fr = f >> 6, mt = fr >> 4, ks = fr & 15;
+    w2t[f] = P[S.o_w2 + (4 * ks + (ln >> 4)) * kNgpHidden + 16 * mt + (ln & 15)];
   }
-#pragma unroll
-  for (int q = 0; q < kNgpHidden; ++q) {
-    d1[q] = G.a2[q * R + r] > 0.0f ? d1[q] : 0.0f;
-    G.d1[q * R + r] = d1[q];
+  for (int f = tid; f < MT1 * 16 * 64; f += 256) {
+    const int ln = f & 63, fr = f >> 6, mt = fr >> 4, it = (fr >> 2) & 3, r = fr & 3;
+    const int q = 16 * mt + (ln & 15), j = 16 * it + 4 * (ln >> 4) + r;
+    w1t[f] = q < nin ? P[S.o_w1 + j * nin + q] : 0.f;
   }
-  const float* W1 = P + S.o_w1;
-  float de[2 * LMAX];
+  __syncthreads();
+#pragma unroll 1
+  for (int it_n = 0; it_n < 4; ++it_n) {
+    const int nb = 64 * wv + 16 * it_n + n;
+    const uint32_t row = (uint32_t)(blockIdx.x * 256 + nb);
+    ngp_f4 d1[4];
 #pragma unroll
-  for (int q = 0; q < 2 * LMAX; ++q) {
-    float acc = 0.f;
-    if (q < nin) {
+    for (int mt = 0; mt < 4; ++mt) d1[mt] = ngp_f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int j = 0; j < kNgpHidden; ++j) acc += W1[j * nin + q] * d1[j];
+    for (int ks = 0; ks < 16; ++ks) {
+      const float bop = G.d2[(4 * ks + g) * R + row];   // zero outside the texture
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+        d1[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(w2t[(mt * 16 + ks) * 64 + lane], bop, d1[mt], 0, 0, 0);
     }
-    de[q] = acc;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t q = 16 * mt + 4 * g + r;
+        d1[mt][r] = G.a2[q * R + row] > 0.0f ? d1[mt][r] : 0.0f;
+        G.d1[q * R + row] = d1[mt][r];
+      }
+    ngp_f4 de[MT1];
+#pragma unroll
+    for (int mt = 0; mt < MT1; ++mt) de[mt] = ngp_f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int it = 0; it < 4; ++it)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int mt = 0; mt < MT1; ++mt)
+          de[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(w1t[((mt * 4 + it) * 4 + r) * 64 + lane], d1[it][r], de[mt], 0,
+                                                        0, 0);
+#pragma unroll
+    for (int mt = 0; mt < MT1; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = 16 * mt + 4 * g + r;
+        if (q < KIN) des[nb * DST + q] = de[mt][r];
+      }
   }
+  __syncthreads();
+  float de[KIN];
+#pragma unroll
+  for (int q = 0; q < KIN; ++q) de[q] = des[tid * DST + q];
   // the encoding's corners and weights (no table reads needed)
   const double u = ((double)x.i + 0.5) / (double)T.w[l], v = ((double)x.j + 0.5) / (double)T.h[l];
   const uint32_t TT = 1u << S.log2_table, mask = TT - 1u;
