@@ -242,8 +242,6 @@ __device__ inline void ksdf_wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-constexpr int kKsdfSlots = kKsdfMaxN / 32;     // sample slots per lane: sample i in lane i % 32, slot i / 32
-
 // LDS of one ray (half a wavefront).
 struct KsdfLds {
   double t[kKsdfMaxN];      // sorted sample parameters

@@ -10,11 +10,11 @@
 //   z2 = W2 h1 + b2, h2 = relu(z2) (64), o = W3 h2 + b3 (4), texel = sigmoid(o).
 // Parameters per layer, flat f32:
 //   tables [L][T][2] | W1 [64][2L] | b1 [64] | W2 [64][64] | b2 [64] | W3 [4][64] | b3 [4].
-// Weights are uniform across a block's texels and are read through scalar
-// loads (no LDS).  The backward pass (two per-texel kernels, to keep each
-// one's registers, and so its occupancy, moderate) writes the layer inputs
-// and the deltas of every texel to a workspace; the weight gradients are then
-// tall-skinny products over texels (k_ngp_wgrad).
+// The per-texel products run on the matrix cores (see k_ngp_bake).  The
+// backward pass (two per-texel kernels, to keep each one's registers, and so
+// its occupancy, moderate) writes the layer inputs and the deltas of every
+// texel to a workspace; the weight gradients are then tall-skinny products
+// over texels (k_ngp_wgrad).
 #pragma once
 
 #include "vs_common.h"
@@ -121,42 +121,6 @@ __device__ inline void ngp_encode(const float* __restrict__ tables, const NgpSha
 }
 
 __device__ inline float ngp_sigmoid(float x) { return 1.0f / (1.0f + expf(-x)); }
-
-// Forward MLP of one texel: z1 kept as h1 (relu), z2 kept (pre-activation), o.
-template <int LMAX>
-__device__ inline void ngp_mlp(const float* __restrict__ P, const NgpShape& S, const float (&e)[2 * LMAX],
-                               float (&h1)[kNgpHidden], float (&z2)[kNgpHidden], float (&o)[kNgpOut]) {
-#pragma clang fp contract(fast)
-  const int nin = 2 * S.levels;
-  const float* W1 = P + S.o_w1;
-  const float* b1 = P + S.o_b1;
-#pragma unroll
-  for (int j = 0; j < kNgpHidden; ++j) {
-    float acc = b1[j];
-#pragma unroll
-    for (int q = 0; q < 2 * LMAX; ++q)
-      if (q < nin) acc += W1[j * nin + q] * e[q];
-    h1[j] = fmaxf(acc, 0.0f);
-  }
-  const float* W2 = P + S.o_w2;
-  const float* b2 = P + S.o_b2;
-#pragma unroll
-  for (int j = 0; j < kNgpHidden; ++j) {
-    float acc = b2[j];
-#pragma unroll
-    for (int q = 0; q < kNgpHidden; ++q) acc += W2[j * kNgpHidden + q] * h1[q];
-    z2[j] = acc;
-  }
-  const float* W3 = P + S.o_w3;
-  const float* b3 = P + S.o_b3;
-#pragma unroll
-  for (int c = 0; c < kNgpOut; ++c) {
-    float acc = b3[c];
-#pragma unroll
-    for (int q = 0; q < kNgpHidden; ++q) acc += W3[c * kNgpHidden + q] * fmaxf(z2[q], 0.0f);
-    o[c] = acc;
-  }
-}
 
 // texture = sigmoid(MLP(encoding)) at every texel centre of every layer; with
 // STAGE the layer inputs e, h1 and h2 are kept for the backward.
