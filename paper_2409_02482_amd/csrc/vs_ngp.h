@@ -26,6 +26,7 @@ constexpr int kNgpOut = 4;
 constexpr int kNgpMaxLevels = 16;
 constexpr uint32_t kNgpPrimeY = 2654435761u;
 constexpr int kNgpTile = 16;   // texels per tile side; a block of 256 threads covers one tile
+constexpr int kNgpSlots = 400; // LDS vertex sums per level in the table scatter (a 20 x 20 window)
 
 struct NgpShape {
   int32_t levels, log2_table;
@@ -318,9 +319,13 @@ __global__ void __launch_bounds__(256) k_ngp_texel_bwd1(NgpTable T, NgpShape S, 
 template <int LMAX>
 __global__ void __launch_bounds__(256) k_ngp_texel_bwd2(NgpTable T, NgpShape S, NgpStage G) {
   constexpr int KIN = 2 * LMAX, MT1 = (KIN + 15) / 16, DST = KIN + 1;
-  __shared__ float w2t[64 * 64];         // [mt][ks][lane]: W2[4 ks + lane / 16][16 mt + lane % 16]
-  __shared__ float w1t[MT1 * 16 * 64];   // [mt][it][r][lane]: W1[16 it + 4 (lane / 16) + r][16 mt + lane % 16]
-  __shared__ float des[256 * DST];       // de per texel of the block
+  constexpr int W2N = 64 * 64, W1N = MT1 * 16 * 64, DEN = 256 * DST;
+  // one LDS buffer, two phases: the products' operands and de, then the per-level vertex sums
+  __shared__ float lds[W2N + W1N + DEN];
+  static_assert(LMAX * kNgpSlots * 2 <= W2N + W1N + DEN, "vertex sums must fit the product buffers");
+  float* w2t = lds;                      // [mt][ks][lane]: W2[4 ks + lane / 16][16 mt + lane % 16]
+  float* w1t = lds + W2N;                // [mt][it][r][lane]: W1[16 it + 4 (lane / 16) + r][16 mt + lane % 16]
+  float* des = lds + W2N + W1N;          // de per texel of the block
   const NgpTexel x = ngp_texel(T);
   const int l = x.l, tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, g = lane >> 4, n = lane & 15;
   const float* P = T.params[l];
@@ -381,26 +386,73 @@ __global__ void __launch_bounds__(256) k_ngp_texel_bwd2(NgpTable T, NgpShape S, 
   float de[KIN];
 #pragma unroll
   for (int q = 0; q < KIN; ++q) de[q] = des[tid * DST + q];
-  // the encoding's corners and weights (no table reads needed)
-  const double u = ((double)x.i + 0.5) / (double)T.w[l], v = ((double)x.j + 0.5) / (double)T.h[l];
+  __syncthreads();
+  // Scatter of de into the tables.  The block's 16 x 16 texels touch a small
+  // window of each level's vertices; their contributions are summed per vertex
+  // in LDS (float atomics) and each window vertex is then added to its table
+  // entry once: neighbouring texels share corners, so this issues a quarter or
+  // less of the global atomics.  A level whose window does not fit uses
+  // direct global atomics.
+  const int W = T.w[l], H = T.h[l];
+  const double u = ((double)x.i + 0.5) / (double)W, v = ((double)x.j + 0.5) / (double)H;
+  const int i_first = x.i - (tid & 15), j_first = x.j - (tid >> 4);
   const uint32_t TT = 1u << S.log2_table, mask = TT - 1u;
   float* gtab = T.gparams[l];
+  float* vs = lds;                       // [level][kNgpSlots][2]
+  for (int e = tid; e < LMAX * kNgpSlots * 2; e += 256) vs[e] = 0.f;
+  __syncthreads();
+  uint32_t vx0[LMAX], vy0[LMAX];
+  int ex[LMAX], ey[LMAX];
 #pragma unroll
   for (int lv = 0; lv < LMAX; ++lv) {
+    ex[lv] = ey[lv] = 0;
+    vx0[lv] = vy0[lv] = 0;
     if (lv >= S.levels) continue;
     const int32_t N = S.res[lv];
+    // the window: vertices of the first and last texel of the tile along each axis (monotone in the texel)
+    const double xa = floor(((double)i_first + 0.5) / (double)W * (double)N);
+    const double xb = floor(((double)(i_first + 15) + 0.5) / (double)W * (double)N);
+    const double ya = floor(((double)j_first + 0.5) / (double)H * (double)N);
+    const double yb = floor(((double)(j_first + 15) + 0.5) / (double)H * (double)N);
+    vx0[lv] = (uint32_t)xa;
+    vy0[lv] = (uint32_t)ya;
+    ex[lv] = (int)(xb - xa) + 2;
+    ey[lv] = (int)(yb - ya) + 2;
+    const bool windowed = (int64_t)ex[lv] * ey[lv] <= kNgpSlots;
     const double xx = u * (double)N, yy = v * (double)N;
     const double x0 = floor(xx), y0 = floor(yy);
     const float fx = (float)(xx - x0), fy = (float)(yy - y0);
     const uint32_t xi = (uint32_t)x0, yi = (uint32_t)y0;
-    // several texels per cell: merge equal vertices across the wavefront first
-    const bool merge = (int64_t)4 * N <= (int64_t)min(T.w[l], T.h[l]);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const uint32_t dx = c & 1, dy = c >> 1;
-      const uint32_t q = x.valid ? ngp_index(xi + dx, yi + dy, N, S.dense[lv], mask) : 0u;
       const float w = (dx ? fx : 1.0f - fx) * (dy ? fy : 1.0f - fy);
-      ngp_table_add(gtab + (int64_t)lv * TT * 2, q, w * de[2 * lv], w * de[2 * lv + 1], x.valid, merge);
+      if (windowed) {
+        if (x.valid) {
+          const int slot = (int)(yi + dy - vy0[lv]) * ex[lv] + (int)(xi + dx - vx0[lv]);
+          atomicAdd(&vs[(lv * kNgpSlots + slot) * 2], w * de[2 * lv]);
+          atomicAdd(&vs[(lv * kNgpSlots + slot) * 2 + 1], w * de[2 * lv + 1]);
+        }
+      } else {
+        const uint32_t q = x.valid ? ngp_index(xi + dx, yi + dy, N, S.dense[lv], mask) : 0u;
+        ngp_table_add(gtab + (int64_t)lv * TT * 2, q, w * de[2 * lv], w * de[2 * lv + 1], x.valid, false);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int lv = 0; lv < LMAX; ++lv) {
+    if (lv >= S.levels || (int64_t)ex[lv] * ey[lv] > kNgpSlots) continue;
+    const int32_t N = S.res[lv];
+    for (int sl = tid; sl < ex[lv] * ey[lv]; sl += 256) {
+      const float a0 = vs[(lv * kNgpSlots + sl) * 2], a1 = vs[(lv * kNgpSlots + sl) * 2 + 1];
+      if (a0 != 0.0f || a1 != 0.0f) {
+        const uint32_t vx = vx0[lv] + (uint32_t)(sl % ex[lv]), vy = vy0[lv] + (uint32_t)(sl / ex[lv]);
+        const uint32_t q = ngp_index(vx, vy, N, S.dense[lv], mask);
+        float* gq = gtab + (int64_t)lv * TT * 2 + 2 * (int64_t)q;
+        unsafeAtomicAdd(gq, a0);
+        unsafeAtomicAdd(gq + 1, a1);
+      }
     }
   }
 }
