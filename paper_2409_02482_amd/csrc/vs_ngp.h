@@ -477,8 +477,10 @@ struct NgpGemm {
 
 __global__ void __launch_bounds__(256) k_ngp_wgrad(NgpGemm Q) {
 #pragma clang fp contract(fast)
-  __shared__ __align__(16) float sD[64][64];
-  __shared__ __align__(16) float sA[64][64];
+  // rows padded to 65 floats: the staging writes (64 lanes, 64 consecutive rows of one feature) then fall
+  // on distinct banks instead of all on one
+  __shared__ float sD[64][65];
+  __shared__ float sA[64][65];
   const int gi = blockIdx.x / Q.blocks_per_gemm, part = blockIdx.x - gi * Q.blocks_per_gemm;
   if (gi >= Q.n_gemm) return;
   const int M = Q.M[gi], K = Q.K[gi];
@@ -503,9 +505,8 @@ __global__ void __launch_bounds__(256) k_ngp_wgrad(NgpGemm Q) {
     }
     __syncthreads();
     for (int rr = 0; rr < nr; ++rr) {
-      const float4 d = *reinterpret_cast<const float4*>(&sD[rr][mb]);
-      const float4 av = *reinterpret_cast<const float4*>(&sA[rr][nb]);
-      const float dv[4] = {d.x, d.y, d.z, d.w}, aw[4] = {av.x, av.y, av.z, av.w};
+      const float dv[4] = {sD[rr][mb], sD[rr][mb + 1], sD[rr][mb + 2], sD[rr][mb + 3]};
+      const float aw[4] = {sA[rr][nb], sA[rr][nb + 1], sA[rr][nb + 2], sA[rr][nb + 3]};
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         bacc[a] += dv[a];
