@@ -268,7 +268,7 @@ __device__ inline int32_t abs_index(int32_t r, int32_t d, int32_t n, int wrap) {
   return i;
 }
 
-constexpr int kWaveWin = 256;     // texels in each wavefront's LDS gradient window
+constexpr int kWaveWin = 384;     // texels in each wavefront's LDS gradient window
 constexpr bool kMergeX2 = true;   // third butterfly step (x +- 2) before the window
 
 // Value of v in lane (lane ^ 1), (lane ^ 2) or (lane ^ 4), with DPP (no LDS):
@@ -318,10 +318,14 @@ __device__ inline void merge_by_key(int32_t& key, float (&v)[16], int lane) {
 // round (an owner word per cell elects it), and the window is flushed with
 // global float atomics whose lanes cover consecutive floats.  A footprint larger than the window
 // uses direct global atomics.
-// The scatter is latency bound, so up to 9 layers the register budget is held
-// to 6 wavefronts per SIMD (a few bytes of spill cost less than the lost waves).
+// The window holds 384 texels: a wavefront whose footprint does not fit falls
+// back to 16 uncoalesced atomics per lane, which with 256 texels happened for
+// 4 % of the layer-wavefronts at 1024^2 views and 7 % at 800^2 and cost 12-20 %
+// of the kernel; 384 texels (30 KiB of LDS per block) fit five blocks per CU,
+// and up to 9 layers the register budget is held to that (the scatter is
+// latency bound: a few bytes of spill cost less than lost wavefronts).
 template <int KMAX>
-__global__ void __launch_bounds__(256, KMAX <= 9 ? 6 : 3) k_shade_bwd(const vs_view* __restrict__ views, int n_views,
+__global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 3) k_shade_bwd(const vs_view* __restrict__ views, int n_views,
                                                    const int32_t* __restrict__ tile_view, int64_t n_tiles,
                                                    LayerTable L, TexTable X, const ProjVert* __restrict__ proj,
                                                    int64_t vpv, const uint64_t* __restrict__ vis,
