@@ -316,8 +316,9 @@ __device__ inline void merge_by_key(int32_t& key, float (&v)[16], int lane) {
 // x +- 1, y +- 1, x +- 2).  The survivors add into an LDS texel window
 // (wrap-aware) with plain read-modify-writes, one lane per base texel and
 // round (an owner word per cell elects it), and the window is flushed with
-// global float atomics whose lanes cover consecutive floats.  A footprint larger than the window
-// uses direct global atomics.
+// global float atomics whose lanes cover consecutive floats.  A footprint
+// larger than the window is retried per half wavefront; a half that still
+// does not fit uses direct global atomics.
 // The window holds 384 texels: a wavefront whose footprint does not fit falls
 // back to 16 uncoalesced atomics per lane, which with 256 texels happened for
 // 4 % of the layer-wavefronts at 1024^2 views and 7 % at 800^2 and cost 12-20 %
@@ -449,92 +450,101 @@ __global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 3) k_shade_bwd(const vs_v
     merge_by_key<0>(key, v, lane);
     merge_by_key<1>(key, v, lane);
     if (kMergeX2) merge_by_key<2>(key, v, lane);
-    const bool live = key >= 0;
+    const bool live_all = key >= 0;
     float* G = X.grad[l];
     const int32_t Wt = X.w[l], Ht = X.h[l];
-    // window relative to the base texel of the first surviving lane (one exists: the lower
-    // lane of every merged pair survives), wrap-aware; corners add +1
-    const int first = __builtin_ctzll(__ballot(live));
-    const int32_t ri = __builtin_amdgcn_readlane(i0, first), rj = __builtin_amdgcn_readlane(j0, first);
-    int32_t di0 = 0, di1 = 0, dj0 = 0, dj1 = 0;
-    if (live) {
-      di0 = rel_index(i0, ri, Wt, wrap); di1 = rel_index(i1, ri, Wt, wrap);
-      dj0 = rel_index(j0, rj, Ht, wrap); dj1 = rel_index(j1, rj, Ht, wrap);
-    }
-    const int32_t dmin_i = wave_min(live ? min(di0, di1) : INT32_MAX);
-    const int32_t dmax_i = wave_max(live ? max(di0, di1) : INT32_MIN);
-    const int32_t dmin_j = wave_min(live ? min(dj0, dj1) : INT32_MAX);
-    const int32_t dmax_j = wave_max(live ? max(dj0, dj1) : INT32_MIN);
-    const int32_t ww = dmax_i - dmin_i + 1, wh = dmax_j - dmin_j + 1;
-    if (ww * wh <= kWaveWin) {
-      float4* wg = reinterpret_cast<float4*>(win);                     // [cell] RGBA sums
-      int32_t* owner = reinterpret_cast<int32_t*>(win + kWaveWin * 4);  // [cell]
-      const int32_t ncell = ww * wh;
-      for (int e = lane; e < ncell; e += 64) wg[e] = make_float4(0.f, 0.f, 0.f, 0.f);
-      const int32_t x0 = di0 - dmin_i, x1 = di1 - dmin_i, y0 = dj0 - dmin_j, y1 = dj1 - dmin_j;
-      const int32_t cells[4] = {y0 * ww + x0, y0 * ww + x1, y1 * ww + x0, y1 * ww + x1};
-      // Corners that coincide (clamped at the last column or row) were folded onto the base
-      // texel's, so for each corner distinct base texels give distinct cells.  One owner word
-      // per base cell elects one lane per base texel and round; the winners then apply the four
-      // corners' read-modify-writes one corner at a time.  A wave's LDS instructions complete
-      // in order, so no atomics are needed; lanes that lost (equal base texel) retry.
-      const uint32_t skip = (i1 == i0 ? 0xau : 0u) | (j1 == j0 ? 0xcu : 0u);
-      bool pend = live;
-      while (__any(pend)) {
-        if (pend) owner[cells[0]] = lane;
-        wave_lds_sync();
-        const bool mine = pend && owner[cells[0]] == lane;
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-          if (mine && !((skip >> n) & 1u)) {
-            float4 acc = wg[cells[n]];
-            acc.x += v[n * 4 + 0]; acc.y += v[n * 4 + 1]; acc.z += v[n * 4 + 2]; acc.w += v[n * 4 + 3];
-            wg[cells[n]] = acc;
-          }
-          __asm__ volatile("" ::: "memory");   // keep the corners' LDS accesses in program order
-        }
-        pend = pend && !mine;
+    // A footprint larger than the window is retried per half wavefront (lanes
+    // 0-31, then 32-63); a half that still does not fit uses direct atomics.
+    for (int pass = 0, npass = 1; pass < npass; ++pass) {   // uniform control flow
+      const bool live = live_all && (npass == 1 || (lane >> 5) == pass);
+      const uint64_t live_bits = __ballot(live);
+      if (live_bits == 0) continue;
+      // window relative to the base texel of the first surviving lane, wrap-aware; corners add +1
+      const int first = __builtin_ctzll(live_bits);
+      const int32_t ri = __builtin_amdgcn_readlane(i0, first), rj = __builtin_amdgcn_readlane(j0, first);
+      int32_t di0 = 0, di1 = 0, dj0 = 0, dj1 = 0;
+      if (live) {
+        di0 = rel_index(i0, ri, Wt, wrap); di1 = rel_index(i1, ri, Wt, wrap);
+        dj0 = rel_index(j0, rj, Ht, wrap); dj1 = rel_index(j1, rj, Ht, wrap);
       }
-      wave_lds_sync();
-      // flush: consecutive lanes take consecutive floats of a window row (so each atomic
-      // instruction covers whole texture row segments), several rows per instruction when
-      // rows are short.  Lane -> (row offset rr, float cc0); the quotients are of small
-      // integers, exact in correctly rounded FP32 division.
-      const int32_t row = ww * 4;
-      const int32_t R = row >= 64 ? 1 : (int32_t)(64.0f / (float)row);
-      const int32_t rr = row >= 64 ? 0 : (int32_t)((float)lane / (float)row);
-      const int32_t cc0 = row >= 64 ? lane : lane - rr * row;
-      const bool flat = ri + dmin_i >= 0 && ri + dmax_i < Wt && rj + dmin_j >= 0 && rj + dmax_j < Ht;
-      if (rr < R) {
-        if (flat) {   // the window does not wrap: plain strided addresses
-          float* gbase = G + ((int64_t)(rj + dmin_j) * Wt + (ri + dmin_i)) * 4;
-          const int64_t gstride = (int64_t)Wt * 4;
-          for (int32_t y = rr; y < wh; y += R)
-            for (int32_t c = cc0; c < row; c += 64) {
-              const float val = win[y * row + c];
-              if (val != 0.0f) unsafeAtomicAdd(gbase + y * gstride + c, val);
+      const int32_t dmin_i = wave_min(live ? min(di0, di1) : INT32_MAX);
+      const int32_t dmax_i = wave_max(live ? max(di0, di1) : INT32_MIN);
+      const int32_t dmin_j = wave_min(live ? min(dj0, dj1) : INT32_MAX);
+      const int32_t dmax_j = wave_max(live ? max(dj0, dj1) : INT32_MIN);
+      const int32_t ww = dmax_i - dmin_i + 1, wh = dmax_j - dmin_j + 1;
+      if (ww * wh <= kWaveWin) {
+        float4* wg = reinterpret_cast<float4*>(win);                     // [cell] RGBA sums
+        int32_t* owner = reinterpret_cast<int32_t*>(win + kWaveWin * 4);  // [cell]
+        const int32_t ncell = ww * wh;
+        for (int e = lane; e < ncell; e += 64) wg[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int32_t x0 = di0 - dmin_i, x1 = di1 - dmin_i, y0 = dj0 - dmin_j, y1 = dj1 - dmin_j;
+        const int32_t cells[4] = {y0 * ww + x0, y0 * ww + x1, y1 * ww + x0, y1 * ww + x1};
+        // Corners that coincide (clamped at the last column or row) were folded onto the base
+        // texel's, so for each corner distinct base texels give distinct cells.  One owner word
+        // per base cell elects one lane per base texel and round; the winners then apply the four
+        // corners' read-modify-writes one corner at a time.  A wave's LDS instructions complete
+        // in order, so no atomics are needed; lanes that lost (equal base texel) retry.
+        const uint32_t skip = (i1 == i0 ? 0xau : 0u) | (j1 == j0 ? 0xcu : 0u);
+        bool pend = live;
+        while (__any(pend)) {
+          if (pend) owner[cells[0]] = lane;
+          wave_lds_sync();
+          const bool mine = pend && owner[cells[0]] == lane;
+#pragma unroll
+          for (int n = 0; n < 4; ++n) {
+            if (mine && !((skip >> n) & 1u)) {
+              float4 acc = wg[cells[n]];
+              acc.x += v[n * 4 + 0]; acc.y += v[n * 4 + 1]; acc.z += v[n * 4 + 2]; acc.w += v[n * 4 + 3];
+              wg[cells[n]] = acc;
             }
-        } else {
-          for (int32_t y = rr; y < wh; y += R) {
-            const int32_t tj = abs_index(rj, dmin_j + y, Ht, wrap);
-            for (int32_t c = cc0; c < row; c += 64) {
-              const float val = win[y * row + c];
-              if (val != 0.0f) {
-                const int32_t ti = abs_index(ri, dmin_i + (c >> 2), Wt, wrap);
-                unsafeAtomicAdd(G + ((int64_t)tj * Wt + ti) * 4 + (c & 3), val);
+            __asm__ volatile("" ::: "memory");   // keep the corners' LDS accesses in program order
+          }
+          pend = pend && !mine;
+        }
+        wave_lds_sync();
+        // flush: consecutive lanes take consecutive floats of a window row (so each atomic
+        // instruction covers whole texture row segments), several rows per instruction when
+        // rows are short.  Lane -> (row offset rr, float cc0); the quotients are of small
+        // integers, exact in correctly rounded FP32 division.
+        const int32_t row = ww * 4;
+        const int32_t R = row >= 64 ? 1 : (int32_t)(64.0f / (float)row);
+        const int32_t rr = row >= 64 ? 0 : (int32_t)((float)lane / (float)row);
+        const int32_t cc0 = row >= 64 ? lane : lane - rr * row;
+        const bool flat = ri + dmin_i >= 0 && ri + dmax_i < Wt && rj + dmin_j >= 0 && rj + dmax_j < Ht;
+        if (rr < R) {
+          if (flat) {   // the window does not wrap: plain strided addresses
+            float* gbase = G + ((int64_t)(rj + dmin_j) * Wt + (ri + dmin_i)) * 4;
+            const int64_t gstride = (int64_t)Wt * 4;
+            for (int32_t y = rr; y < wh; y += R)
+              for (int32_t c = cc0; c < row; c += 64) {
+                const float val = win[y * row + c];
+                if (val != 0.0f) unsafeAtomicAdd(gbase + y * gstride + c, val);
+              }
+          } else {
+            for (int32_t y = rr; y < wh; y += R) {
+              const int32_t tj = abs_index(rj, dmin_j + y, Ht, wrap);
+              for (int32_t c = cc0; c < row; c += 64) {
+                const float val = win[y * row + c];
+                if (val != 0.0f) {
+                  const int32_t ti = abs_index(ri, dmin_i + (c >> 2), Wt, wrap);
+                  unsafeAtomicAdd(G + ((int64_t)tj * Wt + ti) * 4 + (c & 3), val);
+                }
               }
             }
           }
         }
-      }
-      wave_lds_sync();   // the window is reused by the next layer
-    } else if (live) {
-      const int64_t q[4] = {((int64_t)j0 * Wt + i0) * 4, ((int64_t)j0 * Wt + i1) * 4,
-                            ((int64_t)j1 * Wt + i0) * 4, ((int64_t)j1 * Wt + i1) * 4};
+        wave_lds_sync();   // the window is reused by the next pass or layer
+      } else if (npass == 1) {
+        npass = 2;      // retry by halves
+        pass = -1;
+      } else if (live) {
+        const int64_t q[4] = {((int64_t)j0 * Wt + i0) * 4, ((int64_t)j0 * Wt + i1) * 4,
+                              ((int64_t)j1 * Wt + i0) * 4, ((int64_t)j1 * Wt + i1) * 4};
 #pragma unroll
-      for (int n = 0; n < 4; ++n) {
+        for (int n = 0; n < 4; ++n) {
 #pragma unroll
-        for (int ch = 0; ch < 4; ++ch) unsafeAtomicAdd(G + q[n] + ch, v[n * 4 + ch]);
+          for (int ch = 0; ch < 4; ++ch) unsafeAtomicAdd(G + q[n] + ch, v[n * 4 + ch]);
+        }
       }
     }
   }
