@@ -124,16 +124,22 @@ def test_ksdf_render_matches_oracle(torch_cuda, case):
 
 
 def test_ksdf_full_size_sampled_rays(torch_cuda):
-    """The bench workload (256^3 SDF, 128^3 RGBA, 256^3 occupancy, k = 7, 512^2 views) on sampled rays."""
+    """The benchmarked workload (256^3 SDF, 128^3 RGBA, 256^3 occupancy, k = 7, the same 8 ring views at
+    512^2) on sampled rays of every view: colours from the benchmarked call (image only, two calls over the
+    same buffers), per-surface values from a second call that also writes them."""
     torch = torch_cuda
     import paper_2409_02482_amd as P
     g = S.ksdf_grids(5, 256, 128)
     P, field, opts, oopts = _setup(torch, g, 7, 256)
-    cams = S.ring_cameras(5, 2, [(512, 512)] * 2)
+    cams = S.ring_cameras(5, 8, [(512, 512)] * 8)
     views = P.Views(cams)
     occ = P.ksdf_occupancy(field, opts)
+    img = torch.empty(views.total_pixels, 4, dtype=torch.float32, device="cuda")
+    for _ in range(2):
+        P.ksdf_render(field, opts, occ, views, out=img)
     rgba, lay, smp = P.ksdf_render(field, opts, occ, views, layers=True, samples=True)
     torch.cuda.synchronize()
+    assert torch.equal(img, rgba)
     rng = np.random.default_rng(64)
     vox = rng.integers(0, 256 ** 3, 200000)
     got_occ = _occ_bits(torch, occ, 256).reshape(-1)
@@ -144,12 +150,12 @@ def test_ksdf_full_size_sampled_rays(torch_cuda):
     off = 0
     for v, cam in enumerate(cams):
         o, d = K.camera_rays(cam)
-        pick = rng.choice(cam.width * cam.height, 150, replace=False)
+        pick = rng.choice(cam.width * cam.height, 60, replace=False)
         want = K.render_rays(g, oopts, occ_np, o[pick], d[pick])
         err = np.abs(rgba[off + pick] - want["rgba"]).max()
         lerr = np.abs(lay[:, off + pick] - want["layers"]).max()
         hit = (want["rgba"][:, 3] > 0).sum()
         say(f"[gpu] ksdf full size view {v}: colour err {err:.2e}, layer err {lerr:.2e} on {len(pick)} rays "
             f"({hit} covered)")
-        assert err <= TOL and lerr <= TOL and hit > 50
+        assert err <= TOL and lerr <= TOL and hit > 20
         off += cam.width * cam.height

@@ -97,3 +97,48 @@ def test_sh_early_exit_within_bound(torch_cuda):
     _, _, fast = _sh_render(sc, sh, eps_T=eps)
     # stopping once T < eps drops at most eps * max|c| <= eps of colour per channel
     assert float((exact - fast).abs().max()) <= eps + 1e-6
+
+
+def test_sh_full_batch_bench_launch(torch_cuda):
+    """The baked-SH workload at full size in its benchmarked launch: k = 7 shells, 64 ring views at 1024^2,
+    degree 3 in 8 bits with 2048^2 mixed-resolution levels, one batched raster and one vs_render_sh over all
+    views, two steps over the same buffers; every view against the oracle on host threads."""
+    import concurrent.futures as cf
+    import os
+
+    import torch
+    import paper_2409_02482_amd as P
+    say("[gpu] sh full batch: building the k = 7 scene, 64 views at 1024^2")
+    sc = S.make_config(6, n_views=64, resolution=(1024, 1024), with_targets=False)
+    k = sc.k
+    sh = [S.sh_texture(60, l, 2048, 2048, degree=3, opaque=(l == k - 1)) for l in range(k)]
+    layers, views = P.Layers(sc.layers, "cuda"), P.Views(sc.cameras, "cuda")
+    sh_dev = [(torch.from_numpy(t.data).cuda(), t.width, t.height) for t in sh]
+    out = torch.empty(views.total_pixels, 4, dtype=torch.float32, device="cuda")
+    vis = torch.empty(k * views.total_pixels, dtype=torch.int64, device="cuda")
+    ws = P.alloc_workspace(layers, views, 0, "cuda")
+    for step in range(2):
+        P.raster(layers, views, vis, ws, bin=0)
+        P.render_sh(layers, sh_dev, views, vis, ws, degree=3, out=out)
+    torch.cuda.synchronize()
+    st = P.read_status(ws)
+    assert st["bad_key"] == 0 and st["culled_invalid"] == 0, st
+    vis_h, out_h = vis.cpu(), out.cpu()
+    del vis, out, ws
+    torch.cuda.empty_cache()
+
+    def one(v):
+        cam = sc.cameras[v]
+        vis_o = O.raster_layers(sc.layers, cam)
+        if not np.array_equal(views.vis_planes(vis_h, k, v).numpy().view(np.uint64), vis_o):
+            return v, None
+        want = O.shade_sh(sc.layers, sh, cam, vis_o, degree=3)
+        return v, float(np.abs(views.image(out_h, v).numpy().astype(np.float64) - want).max())
+
+    with cf.ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1))) as ex:
+        res = list(ex.map(one, range(len(sc.cameras))))
+    bad = [v for v, e in res if e is None]
+    assert not bad, f"visibility differs in views {bad[:8]}"
+    worst = max(e for _, e in res)
+    say(f"[gpu] sh full batch: {len(res)} views, vis bit-exact, colour err {worst:.2e}")
+    assert worst <= COLOUR_ATOL
