@@ -286,3 +286,25 @@ def test_list_overflow_falls_back_exactly(torch_cuda):
     sc = small_mixed_scene(k=2, sizes=((96, 80), (64, 64)), config=97)
     st = _check_scene(sc, "overflow", list_capacity=200, expect_clean=True)
     assert st["bin_overflow"] > 0
+
+
+@pytest.mark.parametrize("k", [1, 8, 10, 16])
+def test_layer_counts_up_to_the_maximum(torch_cuda, k):
+    """Layer counts that select each variant of the adjoint (ceilings 4, 8 and 16; 7 and 9 are covered by
+    the configurations) up to the maximum of 16 layers, on ragged views: visibility bit-exact, colour, and
+    the texture gradient of a linear loss."""
+    torch = torch_cuda
+    sc = small_mixed_scene(k=k, config=120 + k)
+    _check_scene(sc, f"k={k}")
+    P, layers, views, vis, ws, rgba, tex = gpu_render(sc)
+    gs = [S.upstream_grad(120 + k, c, v) for v, c in enumerate(sc.cameras)]
+    flat = torch.from_numpy(np.concatenate([g.reshape(-1, 4) for g in gs])).cuda()
+    got = _gpu_backward(P, layers, views, vis, ws, tex, grad_rgba=flat)
+    want = [np.zeros(t.shape) for t in sc.textures]
+    for v, cam in enumerate(sc.cameras):
+        w = O.backward(sc.layers, sc.textures, cam, vis_numpy(views, vis, sc.k, v), grad_out=gs[v].astype(np.float64))
+        want = [a + b for a, b in zip(want, w)]
+    err = grad_rel_err(got, want)
+    say(f"[gpu] k={k}: grad rel err {err:.2e}")
+    assert err <= GRAD_RTOL
+    assert all(np.abs(w).max() > 0 for w in want[:1])
