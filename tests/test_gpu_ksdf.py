@@ -8,7 +8,7 @@ oracle's (the GPU's interval weights are FP32, which shifts the CDF by about
 1e-6 relative: a sample drawn where the pdf is only its floor moves by up to
 one gap, and carries no weight, which the colour bar confirms).
 Cases: ragged views, a distant camera whose corner rays miss the cube,
-k = 1 / 2 / 3 / 7, offsets inside and outside the main surface (up to
+k = 1 / 2 / 3 / 7 / 16 (the maximum), offsets inside and outside the main surface (up to
 77 / beta), no importance sampling, two-slot sample counts, 64 and
 2048 march steps, odd occupancy resolutions (a partial last bit word), and the
 full-size grids and views of the bench on sampled rays.
@@ -73,6 +73,8 @@ CASES = {
     "k7": dict(k=7, kw=dict(n_uniform=64, n_importance=32, march_steps=1024)),
     "k1_no_importance": dict(k=1, kw=dict(n_uniform=32, n_importance=0, march_steps=64)),
     "two_slots": dict(k=2, kw=dict(n_uniform=100, n_importance=28, march_steps=2048)),
+    # the maximum number of surfaces
+    "k16_max": dict(k=16, kw=dict(n_uniform=64, n_importance=32, march_steps=512)),
     # offsets beyond 60 / beta: one exponential per surface instead of a shared factor
     "wide_offsets": dict(k=3, kw=dict(n_uniform=64, n_importance=32, march_steps=512),
                          offsets=[-0.02, 0.03, 0.07]),
