@@ -77,7 +77,8 @@ enum {
 #define VS_EMPTY 0xFFFFFFFFFFFFFFFFull
 
 /* One shell.  Device pointers.  xyz f32 [n_vert][3] world positions,
- * uv f32 [n_vert][2], tri i32 [n_tri][3] vertex ids.  1 <= n_tri < 2^31. */
+ * uv f32 [n_vert][2], tri i32 [n_tri][3] vertex ids.  1 <= n_tri < 2^31 and
+ * n_vert >= 1: a layer without triangles or vertices is rejected (VS_ERR_SIZE). */
 typedef struct vs_mesh {
   const float* xyz;
   const float* uv;

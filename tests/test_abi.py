@@ -136,8 +136,15 @@ def test_raster_validation_without_gpu(C):
     assert L.vs_raster_layers(ctypes.addressof(meshes), 2, ctypes.byref(views), 0x5000, 0x100000, need, None,
                               None) == C.VS_ERR_ARG
     assert b"layer 1" in L.vs_last_error()
-    # a tampered view table
+    # an empty layer (no triangles, or no vertices) is rejected, not rastered
     meshes[1].tri = 0x3000
+    for field in ("n_tri", "n_vert"):
+        setattr(meshes[0], field, 0)
+        assert L.vs_raster_layers(ctypes.addressof(meshes), 2, ctypes.byref(views), 0x5000, 0x100000, need, None,
+                                  None) == C.VS_ERR_SIZE
+        assert b"layer 0: empty mesh" in L.vs_last_error()
+        meshes[0].n_tri, meshes[0].n_vert = 5, 10
+    # a tampered view table
     host[1].pix_offset += 1
     assert L.vs_raster_layers(ctypes.addressof(meshes), 2, ctypes.byref(views), 0x5000, 0x100000, need, None,
                               None) == C.VS_ERR_ARG
