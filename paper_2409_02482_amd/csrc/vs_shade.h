@@ -317,8 +317,8 @@ __device__ inline void merge_by_key(int32_t& key, float (&v)[16], int lane) {
 // (wrap-aware) with plain read-modify-writes, one lane per base texel and
 // round (an owner word per cell elects it), and the window is flushed with
 // global float atomics whose lanes cover consecutive floats.  A footprint
-// larger than the window is retried per half wavefront; a half that still
-// does not fit uses direct global atomics.
+// larger than the window is retried per half wavefront, then per quarter; a
+// quarter that still does not fit uses direct global atomics.
 // The window holds 384 texels: a wavefront whose footprint does not fit falls
 // back to 16 uncoalesced atomics per lane, which with 256 texels happened for
 // 4 % of the layer-wavefronts at 1024^2 views and 7 % at 800^2 and cost 12-20 %
@@ -454,9 +454,10 @@ __global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 3) k_shade_bwd(const vs_v
     float* G = X.grad[l];
     const int32_t Wt = X.w[l], Ht = X.h[l];
     // A footprint larger than the window is retried per half wavefront (lanes
-    // 0-31, then 32-63); a half that still does not fit uses direct atomics.
+    // 0-31, then 32-63), a half that does not fit per quarter (16 lanes: an
+    // 8 x 2 pixel block); a quarter that still does not fit uses direct atomics.
     for (int pass = 0, npass = 1; pass < npass; ++pass) {   // uniform control flow
-      const bool live = live_all && (npass == 1 || (lane >> 5) == pass);
+      const bool live = live_all && (npass == 1 || (lane >> (npass == 2 ? 5 : 4)) == pass);
       const uint64_t live_bits = __ballot(live);
       if (live_bits == 0) continue;
       // window relative to the base texel of the first surviving lane, wrap-aware; corners add +1
@@ -537,6 +538,9 @@ __global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 3) k_shade_bwd(const vs_v
       } else if (npass == 1) {
         npass = 2;      // retry by halves
         pass = -1;
+      } else if (npass == 2) {
+        npass = 4;      // this half again as two quarters, and the halves after it as quarters
+        pass = 2 * pass - 1;
       } else if (live) {
         const int64_t q[4] = {((int64_t)j0 * Wt + i0) * 4, ((int64_t)j0 * Wt + i1) * 4,
                               ((int64_t)j1 * Wt + i0) * 4, ((int64_t)j1 * Wt + i1) * 4};
