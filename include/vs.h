@@ -190,8 +190,17 @@ vs_status vs_views_prepare(const vs_camera* cams, int32_t n_views, vs_view* out)
 size_t vs_raster_workspace_bytes(const vs_mesh* layers, int32_t k, const vs_views* views,
                                  const vs_raster_opts* opts);
 
-/* Rasterise every layer in every view (visibility, steps 1-3).
+/* Rasterise every layer in every view: the visibility of the method's
+ * sampling positions.  Each pixel ray meets each shell once, at the shell's
+ * first intersection (Fig. 2c), and those positions are found by
+ * rasterising every shell separately (Sec. 1, sampling by rasterisation).
+ * Per (view, layer, pixel) the slot keeps the key of the nearest covering
+ * triangle (conventions above: snapping, fill rule, key).
  * layers: host array [k] of device meshes, layer 0 outermost.  1 <= k <= 16.
+ * n_views * total triangles must be below 2^30.  Bin-list offsets are 64-bit,
+ * so any total of (triangle, bin) entries is handled; bins whose list does
+ * not fit the reserved capacity (below 2^32 entries) are rasterised by the
+ * exact full-layer path and counted in VS_STAT_BIN_OVERFLOW.
  * vis:    device u64 [sum_v k H_v W_v], written in full.  Slot of (view v,
  *         layer l, pixel (x, y)) = k * pix_offset[v] + l * H_v W_v + y W_v + x.
  * ws:     device workspace of at least vs_raster_workspace_bytes bytes,
@@ -200,7 +209,12 @@ size_t vs_raster_workspace_bytes(const vs_mesh* layers, int32_t k, const vs_view
 vs_status vs_raster_layers(const vs_mesh* layers, int32_t k, const vs_views* views, uint64_t* vis, void* ws,
                            size_t ws_bytes, const vs_raster_opts* opts, void* stream);
 
-/* Shade and blend (forward, step 4).
+/* Shade and blend (forward): per slot, the perspective-correct UV of the hit,
+ * the layer's RGBA read bilinearly from the four surrounding texel centres
+ * (Fig. 5; texel-centre access as in OpenGL, Sec. 4.3 "Texturing Meshes"),
+ * and the layers alpha-blended front to back from the outermost shell
+ * inward (Sec. 4.2, Eq. 6, with the product over the layers in front,
+ * j < i; fixed order without sorting, Sec. 1 and Sec. 4.3 "Baking Textures").
  * tex:  host array [k] of device textures.
  * vis:  the visibility buffer of vs_raster_layers for the same layers/views.
  * ws:   the workspace that vs_raster_layers filled for the same layers/views.
@@ -209,9 +223,17 @@ vs_status vs_render(const vs_mesh* layers, const vs_texture* tex, int32_t k, con
                     const uint64_t* vis, const void* ws, size_t ws_bytes, float* out_rgba,
                     const vs_shade_opts* opts, void* stream);
 
-/* Texture adjoint (step 5).
+/* Texture adjoint: the derivative of vs_render's image with respect to the
+ * texels, which is what the texturing phase optimises on fixed meshes
+ * (Sec. 4.3 "Texturing Meshes").  The blend of Sec. 4.2, Eq. 6 is reversed
+ * back to front without divisions (dL/dc_l = g a_l T_l,
+ * dL/da_l = T_l <g, c_l - S_l> + g_A T_l prod_{m>l} (1 - a_m), S_l the colour
+ * blended behind layer l) and each corner texel of the bilinear read (Fig. 5)
+ * receives its weight times these.
  * grad_rgba: device f32 [sum_v H_v W_v][4] = dL/d(out_rgba); ignored (may be
- *            NULL) when opts->target is set (fused L2 loss).
+ *            NULL) when opts->target is set (fused L2 or L1 loss).
+ * opts->eps_T: the forward walk stops where vs_render's does, so the gradient
+ *            is that of the image vs_render returns with the same eps_T.
  * grad_tex:  host array [k] of device pointers, f32 [H_l][W_l][4] each,
  *            ACCUMULATED into (+=).  Summation order is not fixed (atomics).
  * out_rgba:  optional device f32 [sum_v H_v W_v][4]: when non-NULL the
@@ -378,9 +400,13 @@ vs_status vs_ngp_backward(const float* const* params, const vs_ngp_config* cfg, 
  * distance d (positive outside) by NeuS quadrature along each pixel ray and
  * blends them in fixed order, surface 0 (the outermost) first.  The fields are
  * given on vertex grids over the cube [lo, hi]^3 and read trilinearly: a grid
- * of resolution R has (R+1)^3 vertices in [z][y][x] order, spacing
- * h = (hi - lo)/R; a point p reads cell coordinate c = (p - lo)/h clamped to
- * [0, R], base vertex min(floor(c), R - 1), weights c - base. */
+ * of resolution R has (R+1)^3 vertices in [z][y][x] order; a point p reads
+ * cell coordinate c = (p - lo) * (R / (hi - lo)) (per axis, FP64) clamped to
+ * [0, R], base vertex min(floor(c), R - 1), weights c - base.  The occupancy
+ * grid uses the same coordinate with R = occ_res: a march step is occupied iff
+ * the voxel floor((p - lo) * (occ_res / (hi - lo))) of its midpoint
+ * p = o + t v is.  A midpoint within a few ulps of a voxel face may be
+ * assigned to either neighbouring voxel. */
 #define VS_KSDF_MAX_SURFACES 16
 #define VS_KSDF_MAX_SAMPLES 128
 typedef struct vs_ksdf_field {

@@ -19,7 +19,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vs_oracle.cpp")
-_LIB = os.path.join(_HERE, "libvs_oracle.so")
+# VS_ORACLE_LIB names another build of the same source (the sanitizer test loads an instrumented one)
+_LIB = os.environ.get("VS_ORACLE_LIB") or os.path.join(_HERE, "libvs_oracle.so")
 EMPTY = np.uint64(0xFFFFFFFFFFFFFFFF)
 
 CXXFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fno-finite-math-only",

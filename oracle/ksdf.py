@@ -25,8 +25,8 @@ Definitions (our reading where the paper gives no formula):
     cube, clipped to t >= 0;
   * occupied space along a ray is resolved by S equal march steps over that
     interval: step s covers [t_in + s D, t_in + (s+1) D], D = (t_out - t_in)/S,
-    and is occupied iff the voxel holding its midpoint t_m is (voxel
-    coordinate (o - lo) Ro/(hi - lo) + t_m v Ro/(hi - lo)); the n uniform
+    and is occupied iff the voxel holding its midpoint p = o + t_m v is
+    (voxel coordinate (p - lo) Ro/(hi - lo), as for the fields); the n uniform
     samples sit at occupied-length positions rho_i = (i + 1/2) M / n (M
     occupied steps): sample i lies in the floor(rho_i)-th occupied step at
     fraction rho_i - floor(rho_i);
@@ -190,17 +190,41 @@ def box_interval(o: np.ndarray, v: np.ndarray, lo: float, hi: float):
     return t_in, t_out, hit
 
 
-def march_occupied(o, v, t_in, t_out, occ: np.ndarray, lo: float, hi: float, steps: int) -> np.ndarray:
-    """bool [n_rays, S]: march step s of each ray is occupied (voxel of its midpoint)."""
-    Ro = occ.shape[0]
-    inv = Ro / (hi - lo)
+def march_midpoint_coords(o, v, t_in, t_out, Ro: int, lo: float, hi: float, steps: int) -> np.ndarray:
+    """[n_rays, S, 3] voxel coordinates (before the floor) of the march-step midpoints.
+
+    Step s spans [t_in + s D, t_in + (s+1) D] with D = (t_out - t_in)/S; its
+    midpoint is the point p = o + t_m v, whose voxel coordinate is the grid's
+    cell coordinate (p - lo) Ro/(hi - lo), the reading used for every grid.
+    """
     D = (t_out - t_in) / steps
     tm = t_in[:, None] + (np.arange(steps)[None, :] + 0.5) * D[:, None]
-    # voxel coordinate of o + tm v, as (o - lo) inv + tm (v inv)
-    A = (o - lo) * inv
-    B = v * inv
-    vox = np.clip(np.floor(A[:, None, :] + tm[..., None] * B[:, None, :]), 0, Ro - 1).astype(np.int64)
+    p = o[:, None, :] + tm[..., None] * v[:, None, :]
+    return (p - lo) * (Ro / (hi - lo))
+
+
+def march_occupied(o, v, t_in, t_out, occ: np.ndarray, lo: float, hi: float, steps: int) -> np.ndarray:
+    """bool [n_rays, S]: march step s of each ray is occupied (the voxel holding its midpoint is)."""
+    Ro = occ.shape[0]
+    c = march_midpoint_coords(o, v, t_in, t_out, Ro, lo, hi, steps)
+    vox = np.clip(np.floor(c), 0, Ro - 1).astype(np.int64)
     return occ[vox[..., 2], vox[..., 1], vox[..., 0]].astype(bool)
+
+
+def march_on_face(o, v, occ_res: int, lo: float, hi: float, steps: int, tol: float = 1e-9) -> np.ndarray:
+    """bool [n_rays]: some march midpoint of the ray lies within ``tol`` (in voxel units) of an interior
+    voxel face.  There the voxel it falls in is decided by the last bits of its coordinate, which any other
+    correct evaluation order may round the other way; the result of such a ray is not unique."""
+    t_in, t_out, hit = box_interval(o, v, lo, hi)
+    out = np.zeros(o.shape[0], bool)
+    rows = np.flatnonzero(hit)
+    for a in range(0, rows.size, 2048):
+        r = rows[a:a + 2048]
+        c = march_midpoint_coords(o[r], v[r], t_in[r], t_out[r], occ_res, lo, hi, steps)
+        near = np.abs(c - np.rint(c)) <= tol
+        interior = (np.rint(c) >= 1) & (np.rint(c) <= occ_res - 1)
+        out[r] = (near & interior).any(axis=(1, 2))
+    return out
 
 
 def uniform_samples(t_in, t_out, occ_steps: np.ndarray, n: int):

@@ -9,7 +9,8 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libvs.so")
+# VS_LIB names another build of the same sources (the sanitizer test loads one with instrumented host code)
+LIB_PATH = os.environ.get("VS_LIB") or os.path.join(_HERE, "libvs.so")
 
 c_vp, c_i32, c_i64, c_f32, c_f64, c_sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
                                           ctypes.c_double, ctypes.c_size_t)

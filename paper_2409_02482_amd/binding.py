@@ -36,6 +36,33 @@ def _dev(t: torch.Tensor, dtype, what: str) -> torch.Tensor:
     return t
 
 
+def _shape(t: torch.Tensor, shape, what: str) -> torch.Tensor:
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def _arg(t: torch.Tensor, dtype, shape, what: str) -> torch.Tensor:
+    """Shape first (a mismatch is reported even for a host tensor), then device, dtype and layout."""
+    return _dev(_shape(t, shape, what), dtype, what)
+
+
+def _count(seq, n: int, what: str):
+    if len(seq) != n:
+        raise ValueError(f"{what}: {len(seq)} given, {n} expected (one per layer)")
+    return seq
+
+
+def _check_vis(vis: torch.Tensor, layers: "Layers", views: "Views") -> torch.Tensor:
+    if vis.numel() != layers.k * views.total_pixels:
+        raise ValueError(f"vis has {vis.numel()} slots, k * total pixels = {layers.k * views.total_pixels}")
+    return _dev(vis, torch.int64, "vis")
+
+
+def _check_ws(ws: torch.Tensor) -> torch.Tensor:
+    return _dev(ws, torch.uint8, "workspace")
+
+
 class Layers:
     """k meshes on the device.  ``meshes``: objects with xyz [V,3], uv [V,2], tri [T,3] (numpy or torch)."""
 
@@ -97,12 +124,20 @@ class Views:
         return vis[o:o + k * h * w].view(k, h, w)
 
 
-def textures_struct(textures: Sequence[torch.Tensor]):
+def _check_textures(textures: Sequence[torch.Tensor], k: Optional[int] = None):
+    """Count and shapes of the layer textures ([H, W, 4] each), before any device check."""
+    if k is not None:
+        _count(textures, k, "textures")
+    for l, t in enumerate(textures):
+        if t.dim() != 3 or t.shape[2] != 4:
+            raise ValueError(f"texture {l} must be [H, W, 4], got {tuple(t.shape)}")
+
+
+def textures_struct(textures: Sequence[torch.Tensor], k: Optional[int] = None):
+    _check_textures(textures, k)
     arr = (C.VsTexture * len(textures))()
     for l, t in enumerate(textures):
         _dev(t, torch.float32, f"texture {l}")
-        if t.dim() != 3 or t.shape[2] != 4:
-            raise ValueError(f"texture {l} must be [H, W, 4]")
         arr[l] = C.VsTexture(t.data_ptr(), t.shape[1], t.shape[0])
     return arr
 
@@ -134,7 +169,8 @@ def raster(layers: Layers, views: Views, vis: Optional[torch.Tensor] = None, ws:
         vis = torch.empty(layers.k * views.total_pixels, dtype=torch.int64, device=dev)
     if ws is None:
         ws = alloc_workspace(layers, views, bin, dev, list_capacity)
-    _dev(vis, torch.int64, "vis")
+    _check_vis(vis, layers, views)
+    _check_ws(ws)
     opts = _raster_opts(bin, count_fragments, direct, list_capacity)
     C.check(C.load().vs_raster_layers(ctypes.addressof(layers.c), layers.k, ctypes.byref(views.c), vis.data_ptr(),
                                       ws.data_ptr(), ws.numel(), ctypes.byref(opts), _stream(stream)),
@@ -150,10 +186,15 @@ def _shade_opts(eps_T=0.0, wrap=0, target=None, loss_scale=1.0, loss="l2"):
 def render(layers: Layers, textures, views: Views, vis: torch.Tensor, ws: torch.Tensor,
            out: Optional[torch.Tensor] = None, eps_T: float = 0.0, wrap: int = 0, stream=None) -> torch.Tensor:
     """vs_render: [sum_v H_v W_v, 4] RGBA (A = 1 - transmittance)."""
+    _check_textures(textures, layers.k)
+    if out is not None:
+        _shape(out, (views.total_pixels, 4), "out")
+    _check_vis(vis, layers, views)
+    _check_ws(ws)
     if out is None:
         out = torch.empty(views.total_pixels, 4, dtype=torch.float32, device=vis.device)
-    _dev(out, torch.float32, "out")
-    tex = textures_struct(textures)
+    _arg(out, torch.float32, (views.total_pixels, 4), "out")
+    tex = textures_struct(textures, layers.k)
     opts = _shade_opts(eps_T, wrap)
     C.check(C.load().vs_render(ctypes.addressof(layers.c), ctypes.addressof(tex), layers.k, ctypes.byref(views.c),
                                vis.data_ptr(), ws.data_ptr(), ws.numel(), out.data_ptr(), ctypes.byref(opts),
@@ -161,11 +202,22 @@ def render(layers: Layers, textures, views: Views, vis: torch.Tensor, ws: torch.
     return out
 
 
-def sh_textures_struct(sh_textures: Sequence) -> ctypes.Array:
+def sh_texture_bytes(width: int, height: int, degree: int) -> int:
+    """Bytes of one shell's packed SH levels 0..degree (level d: max(1, W >> d) x max(1, H >> d) texels,
+    2d + 1 RGBA byte words each)."""
+    return sum(max(1, int(width) >> d) * max(1, int(height) >> d) * (2 * d + 1) * 4 for d in range(int(degree) + 1))
+
+
+def sh_textures_struct(sh_textures: Sequence, k: Optional[int] = None, degree: Optional[int] = None) -> ctypes.Array:
     """sh_textures[l] = (data, width, height): data a contiguous uint8 device tensor of packed levels."""
+    if k is not None:
+        _count(sh_textures, k, "SH textures")
     arr = (C.VsShTexture * len(sh_textures))()
     for l, (data, w, h) in enumerate(sh_textures):
         _dev(data, torch.uint8, f"SH texture {l}")
+        if degree is not None and data.numel() < sh_texture_bytes(w, h, degree):
+            raise ValueError(f"SH texture {l}: {data.numel()} bytes, degree {degree} at {w}x{h} needs "
+                             f"{sh_texture_bytes(w, h, degree)}")
         arr[l] = C.VsShTexture(data.data_ptr(), int(w), int(h))
     return arr
 
@@ -174,10 +226,21 @@ def render_sh(layers: Layers, sh_textures, views: Views, vis: torch.Tensor, ws: 
               vmin: float = -15.0, vmax: float = 15.0, view_alpha: bool = True, out: Optional[torch.Tensor] = None,
               eps_T: float = 0.0, wrap: int = 0, stream=None) -> torch.Tensor:
     """vs_render_sh: [sum_v H_v W_v, 4] RGBA from baked 8-bit SH textures (A = 1 - transmittance)."""
+    _count(sh_textures, layers.k, "SH textures")
+    for l, (data, w, h) in enumerate(sh_textures):
+        if 0 <= int(degree) <= 3 and data.numel() < sh_texture_bytes(w, h, degree):
+            raise ValueError(f"SH texture {l}: {data.numel()} bytes, degree {degree} at {w}x{h} needs "
+                             f"{sh_texture_bytes(w, h, degree)}")
+    if out is not None:
+        _shape(out, (views.total_pixels, 4), "out")
+    _check_vis(vis, layers, views)
+    _check_ws(ws)
     if out is None:
         out = torch.empty(views.total_pixels, 4, dtype=torch.float32, device=vis.device)
-    _dev(out, torch.float32, "out")
-    tex = sh_textures_struct(sh_textures)
+    _arg(out, torch.float32, (views.total_pixels, 4), "out")
+    if not 0 <= int(degree) <= 3:
+        raise ValueError(f"SH degree {degree} outside 0..3")
+    tex = sh_textures_struct(sh_textures, layers.k, degree)
     opts = C.VsShOpts(float(vmin), float(vmax), float(eps_T), int(wrap), int(degree), int(bool(view_alpha)))
     C.check(C.load().vs_render_sh(ctypes.addressof(layers.c), ctypes.addressof(tex), layers.k, ctypes.byref(views.c),
                                   vis.data_ptr(), ws.data_ptr(), ws.numel(), out.data_ptr(), ctypes.byref(opts),
@@ -189,24 +252,38 @@ def render_backward(layers: Layers, textures, views: Views, vis: torch.Tensor, w
                     grad_rgba: Optional[torch.Tensor] = None, grad_tex: Optional[List[torch.Tensor]] = None,
                     target: Optional[torch.Tensor] = None, loss_scale: float = 1.0,
                     out: Optional[torch.Tensor] = None, sse: Optional[torch.Tensor] = None, wrap: int = 0,
-                    loss: str = "l2",
+                    loss: str = "l2", eps_T: float = 0.0,
                     stream=None) -> List[torch.Tensor]:
-    """vs_render_backward: accumulates dL/dtexture into grad_tex (zeros if None) and returns it."""
+    """vs_render_backward: accumulates dL/dtexture into grad_tex (zeros if None) and returns it.
+    With eps_T > 0 the layer walk stops where vs_render's does (the gradient of that image)."""
+    # counts and shapes first, then devices and dtypes
+    _check_textures(textures, layers.k)
+    if grad_tex is not None:
+        _count(grad_tex, layers.k, "grad_tex")
+        for l, (g, t) in enumerate(zip(grad_tex, textures)):
+            _shape(g, t.shape, f"grad_tex[{l}]")
+    img = (views.total_pixels, 4)
+    if grad_rgba is None and target is None:
+        raise ValueError("render_backward needs grad_rgba or target")
+    for name, t in (("grad_rgba", grad_rgba), ("target", target), ("out", out)):
+        if t is not None:
+            _shape(t, img, name)
+    if sse is not None and sse.numel() < 1:
+        raise ValueError("sse must hold one float64")
+    _check_vis(vis, layers, views)
+    _check_ws(ws)
+    tex = textures_struct(textures, layers.k)
     if grad_tex is None:
         grad_tex = [torch.zeros_like(t) for t in textures]
-    for l, g in enumerate(grad_tex):
-        _dev(g, torch.float32, f"grad_tex[{l}]")
-    if grad_rgba is not None:
-        _dev(grad_rgba, torch.float32, "grad_rgba")
-    if target is not None:
-        _dev(target, torch.float32, "target")
-    if out is not None:
-        _dev(out, torch.float32, "out")
+    for l, (g, t) in enumerate(zip(grad_tex, textures)):
+        _arg(g, torch.float32, t.shape, f"grad_tex[{l}]")
+    for name, t in (("grad_rgba", grad_rgba), ("target", target), ("out", out)):
+        if t is not None:
+            _arg(t, torch.float32, img, name)
     if sse is not None:
         _dev(sse, torch.float64, "sse")
-    tex = textures_struct(textures)
     gp = (ctypes.c_void_p * layers.k)(*[g.data_ptr() for g in grad_tex])
-    opts = _shade_opts(0.0, wrap, target, loss_scale, loss)
+    opts = _shade_opts(eps_T, wrap, target, loss_scale, loss)
     C.check(C.load().vs_render_backward(
         ctypes.addressof(layers.c), ctypes.addressof(tex), layers.k, ctypes.byref(views.c), vis.data_ptr(),
         ws.data_ptr(), ws.numel(), None if grad_rgba is None else grad_rgba.data_ptr(), ctypes.addressof(gp),
@@ -238,9 +315,12 @@ def adam_step(params, grads, m, v, step: torch.Tensor, lr=1e-2, betas=(0.9, 0.99
     """vs_adam_step: fused Adam + projection to [lo, hi] + gradient reset on k texture planes."""
     k = len(params)
     for name, arr in (("params", params), ("grads", grads), ("m", m), ("v", v)):
+        _count(arr, k, name)
         for l, t in enumerate(arr):
-            _dev(t, torch.float32, f"{name}[{l}]")
+            _arg(t, torch.float32, params[l].shape, f"{name}[{l}]")
     _dev(step, torch.int32, "step")
+    if history is not None:
+        _dev(history, torch.float64, "history")
     ptr = lambda arr: (ctypes.c_void_p * k)(*[t.data_ptr() for t in arr])  # noqa: E731
     counts = (ctypes.c_int64 * k)(*[t.numel() for t in params])
     opts = C.VsAdamOpts(lr, betas[0], betas[1], eps, lo, hi)
@@ -257,8 +337,9 @@ def squeeze(params, tex, levels: int = 255, stream=None):
     """vs_squeeze: tex = q(sigmoid(params)) (q: rounding to levels steps; 0 = none)."""
     k = len(params)
     for name, arr in (("params", params), ("tex", tex)):
+        _count(arr, k, name)
         for l, t in enumerate(arr):
-            _dev(t, torch.float32, f"{name}[{l}]")
+            _arg(t, torch.float32, params[l].shape, f"{name}[{l}]")
     keep = [(ctypes.c_void_p * k)(*[t.data_ptr() for t in a]) for a in (params, tex)]
     counts = (ctypes.c_int64 * k)(*[t.numel() for t in params])
     C.check(C.load().vs_squeeze(ctypes.addressof(keep[0]), ctypes.addressof(keep[1]), ctypes.addressof(counts), k,
@@ -271,9 +352,12 @@ def adam_step_squeezed(params, grads, m, v, tex, step: torch.Tensor, levels: int
     """vs_adam_step_squeezed: Adam on logits (straight-through quantiser), tex rewritten, gradient reset."""
     k = len(params)
     for name, arr in (("params", params), ("grads", grads), ("m", m), ("v", v), ("tex", tex)):
+        _count(arr, k, name)
         for l, t in enumerate(arr):
-            _dev(t, torch.float32, f"{name}[{l}]")
+            _arg(t, torch.float32, params[l].shape, f"{name}[{l}]")
     _dev(step, torch.int32, "step")
+    if history is not None:
+        _dev(history, torch.float64, "history")
     keep = [(ctypes.c_void_p * k)(*[t.data_ptr() for t in a]) for a in (params, grads, m, v, tex)]
     counts = (ctypes.c_int64 * k)(*[t.numel() for t in params])
     opts = C.VsAdamOpts(lr, betas[0], betas[1], eps, 0.0, 0.0)
@@ -309,12 +393,16 @@ def ngp_bake(params, cfg: NgpConfig, sizes, tex=None, ws: Optional[torch.Tensor]
     """vs_ngp_bake: RGBA textures [H, W, 4] of the neural textures params[l] at sizes[l] = (W, H);
     with ws (ngp_workspace) the activations are kept for ngp_backward."""
     k = len(params)
+    _count(sizes, k, "sizes")
     for l, p in enumerate(params):
-        _dev(p, torch.float32, f"params[{l}]")
+        _shape(_dev(p, torch.float32, f"params[{l}]"), (cfg.param_count,), f"params[{l}]")
     if tex is None:
         tex = [torch.empty(h, w, 4, dtype=torch.float32, device=params[0].device) for w, h in sizes]
-    for l, t in enumerate(tex):
-        _dev(t, torch.float32, f"tex[{l}]")
+    _count(tex, k, "tex")
+    for l, (t, (w, h)) in enumerate(zip(tex, sizes)):
+        _arg(t, torch.float32, (h, w, 4), f"tex[{l}]")
+    if ws is not None:
+        _check_ws(ws)
     ws_, hs_ = _sizes(sizes)
     keep = [(ctypes.c_void_p * k)(*[t.data_ptr() for t in a]) for a in (params, tex)]
     C.check(C.load().vs_ngp_bake(ctypes.addressof(keep[0]), ctypes.byref(cfg.c), k, ctypes.addressof(ws_),
@@ -335,11 +423,16 @@ def ngp_backward(params, cfg: NgpConfig, sizes, tex, grad_tex, ws: torch.Tensor,
     """vs_ngp_backward of the last ngp_bake given ws (with the same params and textures tex):
     accumulates dL/dparams (zeros if None) from dL/dtexture and returns it."""
     k = len(params)
+    _count(sizes, k, "sizes")
     if grad_params is None:
         grad_params = [torch.zeros_like(p) for p in params]
     for name, arr in (("params", params), ("tex", tex), ("grad_tex", grad_tex), ("grad_params", grad_params)):
+        _count(arr, k, name)
         for l, t in enumerate(arr):
-            _dev(t, torch.float32, f"{name}[{l}]")
+            w, h = sizes[l]
+            want = (cfg.param_count,) if name in ("params", "grad_params") else (h, w, 4)
+            _arg(t, torch.float32, want, f"{name}[{l}]")
+    _check_ws(ws)
     ws_, hs_ = _sizes(sizes)
     keep = [(ctypes.c_void_p * k)(*[t.data_ptr() for t in a]) for a in (params, tex, grad_tex, grad_params)]
     C.check(C.load().vs_ngp_backward(ctypes.addressof(keep[0]), ctypes.byref(cfg.c), k, ctypes.addressof(ws_),
@@ -392,10 +485,12 @@ def ksdf_render(field: KsdfField, opts: C.VsKsdfOpts, occ: torch.Tensor, views: 
     dev = field.sdf.device
     if out is None:
         out = torch.empty(total, 4, dtype=torch.float32, device=dev)
-    _dev(out, torch.float32, "out")
+    _arg(out, torch.float32, (total, 4), "out")
     lay = torch.empty(opts.k, total, 4, dtype=torch.float32, device=dev) if layers else None
     smp = torch.empty(total, opts.n_uniform + opts.n_importance, dtype=torch.float64, device=dev) if samples else None
     _dev(occ, torch.int32, "occ")
+    if occ.numel() < int(C.load().vs_ksdf_occupancy_words(opts.occ_res)):
+        raise ValueError("occ too small for occ_res")
     C.check(C.load().vs_ksdf_render(ctypes.byref(field.c), ctypes.byref(opts), occ.data_ptr(), ctypes.byref(views.c),
                                     out.data_ptr(), None if lay is None else lay.data_ptr(),
                                     None if smp is None else smp.data_ptr(), _stream(stream)), "vs_ksdf_render")
@@ -447,7 +542,7 @@ class _RenderFn(torch.autograd.Function):
         r = ctx.renderer
         textures = ctx.saved_tensors
         grads = render_backward(r.layers, textures, r.views, r.vis, r.ws, grad_rgba=grad_out.contiguous(),
-                                wrap=r.wrap)
+                                wrap=r.wrap, eps_T=r.eps_T)
         return (None, *grads)
 
 
@@ -468,6 +563,7 @@ class Renderer:
         return self.vis
 
     def __call__(self, *textures: torch.Tensor) -> torch.Tensor:
+        _count(textures, self.layers.k, "textures")
         return _RenderFn.apply(self, *textures)
 
     def status(self) -> dict:

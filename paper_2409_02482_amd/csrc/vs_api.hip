@@ -150,10 +150,10 @@ vs::WsLayout ws_layout(const vs::LayerTable& L, const vs_views* views, int bin, 
   // everything below depends on the bin size; render and backward read only the part above
   w.bin_view = take((size_t)w.n_tiles_bin * 4);
   w.count = take((size_t)w.n_bins * 4);
-  w.offset = take((size_t)w.n_bins * 4);
+  w.offset = take((size_t)w.n_bins * 8);
   w.cursor = take((size_t)w.n_bins * 8);
   w.spans = take((size_t)n_views * (size_t)L.tri_off[L.k] * 8);
-  w.partial = take((size_t)w.n_partial * 4);
+  w.partial = take((size_t)w.n_partial * 8);
   w.list = take((size_t)w.capacity * 4);
   w.total = off;
   return w;
@@ -248,10 +248,10 @@ vs_status vs_raster_layers(const vs_mesh* layers, int32_t k, const vs_views* vie
   auto* tile_view = (int32_t*)(base + lay.tile_view);
   auto* bin_view = (int32_t*)(base + lay.bin_view);
   auto* count = (uint32_t*)(base + lay.count);
-  auto* offset = (uint32_t*)(base + lay.offset);
+  auto* offset = (uint64_t*)(base + lay.offset);
   auto* cursor = (uint32_t*)(base + lay.cursor);
   auto* spans = (uint64_t*)(base + lay.spans);
-  auto* partial = (uint32_t*)(base + lay.partial);
+  auto* partial = (uint64_t*)(base + lay.partial);
   auto* list = (int32_t*)(base + lay.list);
   const int64_t vpv = L.vert_off[k];
   const int nv = views->n_views;
@@ -282,15 +282,15 @@ vs_status vs_raster_layers(const vs_mesh* layers, int32_t k, const vs_views* vie
                      offset, partial, lay.n_bins);
   hipLaunchKernelGGL(vs::k_scan_partials, dim3(1), dim3(1024), 0, s, partial, lay.n_partial);
   hipLaunchKernelGGL(vs::k_scan_add, dim3(grid_1d(lay.n_bins, 256)), dim3(256), 0, s, offset,
-                     (const uint32_t*)partial, lay.n_bins);
+                     (const uint64_t*)partial, lay.n_bins);
   hipLaunchKernelGGL(vs::k_bin_scatter, dim3(bin_blocks), dim3(256), 0, s, views->dev, nv, L, B, slot,
-                     (const uint64_t*)spans, (const uint32_t*)count, (const uint32_t*)offset, cursor, list,
+                     (const uint64_t*)spans, (const uint32_t*)count, (const uint64_t*)offset, cursor, list,
                      lay.capacity);
   const unsigned nblk = (unsigned)((lay.n_bins + 7) / 8 * 8);
   auto raster = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(nblk), dim3(vs::kRasterThreads), 0, s, views->dev, (const int32_t*)bin_view,
                        lay.n_tiles_bin, L, (const vs::ProjVert*)proj, vpv, slot, (const uint32_t*)count,
-                       (const uint32_t*)offset, (const int32_t*)list, lay.capacity, (unsigned long long*)vis, status,
+                       (const uint64_t*)offset, (const int32_t*)list, lay.capacity, (unsigned long long*)vis, status,
                        count_frags);
   };
   switch (B) {
@@ -423,6 +423,8 @@ vs_status vs_render_backward(const vs_mesh* layers, const vs_texture* tex, int32
   if (wrap != 0 && wrap != 1) return fail(VS_ERR_UNSUPPORTED, "wrap = %d", wrap);
   const int loss = opts ? opts->loss : VS_LOSS_L2;
   if (loss != VS_LOSS_L2 && loss != VS_LOSS_L1) return fail(VS_ERR_UNSUPPORTED, "loss = %d", loss);
+  const float eps = opts ? opts->eps_T : 0.0f;
+  if (!(eps >= 0.0f && eps < 1.0f)) return fail(VS_ERR_ARG, "eps_T must be in [0, 1)");
   const vs::WsLayout lay = ws_layout(L, views, 0);
   if ((st = check_ws(ws, ws_bytes, lay.proj + (size_t)views->n_views * L.vert_off[k] * sizeof(vs::ProjVert))))
     return st;
@@ -436,7 +438,7 @@ vs_status vs_render_backward(const vs_mesh* layers, const vs_texture* tex, int32
     hipLaunchKernelGGL(kern, dim3((unsigned)vs::shade_grid_blocks(tiles)), dim3(256), 0, s, views->dev,
                        views->n_views, tile_view, tiles, L, X, proj,
                        L.vert_off[k], vis, (const float4*)grad_rgba, (const float4*)target, scale, loss,
-                       (float4*)out_rgba, target ? sse : nullptr, wrap, status);
+                       (float4*)out_rgba, target ? sse : nullptr, wrap, eps, status);
   };
   // per-layer state lives in registers, so the common layer counts get their own instantiation
   if (k <= 4) launch(vs::k_shade_bwd<4>);

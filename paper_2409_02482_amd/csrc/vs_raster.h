@@ -171,14 +171,17 @@ __global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ v
     }
 }
 
-// Exclusive scan, pass 1: each block scans 1024 counts, writes local prefixes and its total.
-__global__ void __launch_bounds__(256) k_scan_local(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
-                                                    uint32_t* __restrict__ partial, int64_t n) {
-  __shared__ uint32_t s[256];
+// Exclusive scan of the per-bin counts into 64-bit list offsets (the total
+// can pass 2^32 when triangles cover many bins; a bin's own count stays below
+// 2^30 because n_views * triangles does).
+// Pass 1: each block scans 1024 counts, writes local prefixes and its total.
+__global__ void __launch_bounds__(256) k_scan_local(const uint32_t* __restrict__ in, uint64_t* __restrict__ out,
+                                                    uint64_t* __restrict__ partial, int64_t n) {
+  __shared__ uint64_t s[256];
   const int tid = threadIdx.x;
   const int64_t base = (int64_t)blockIdx.x * 1024 + tid * 4;
   uint32_t v[4];
-  uint32_t sum = 0;
+  uint64_t sum = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     v[q] = base + q < n ? in[base + q] : 0u;
@@ -187,12 +190,12 @@ __global__ void __launch_bounds__(256) k_scan_local(const uint32_t* __restrict__
   s[tid] = sum;
   __syncthreads();
   for (int off = 1; off < 256; off <<= 1) {
-    const uint32_t add = tid >= off ? s[tid - off] : 0u;
+    const uint64_t add = tid >= off ? s[tid - off] : 0u;
     __syncthreads();
     s[tid] += add;
     __syncthreads();
   }
-  uint32_t run = s[tid] - sum;  // exclusive prefix of this thread
+  uint64_t run = s[tid] - sum;  // exclusive prefix of this thread
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     if (base + q < n) out[base + q] = run;
@@ -202,18 +205,18 @@ __global__ void __launch_bounds__(256) k_scan_local(const uint32_t* __restrict__
 }
 
 // Pass 2: one block scans the block totals in place (exclusive), carrying across chunks.
-__global__ void __launch_bounds__(1024) k_scan_partials(uint32_t* __restrict__ partial, int64_t n) {
-  __shared__ uint32_t s[1024];
-  __shared__ uint32_t carry;
+__global__ void __launch_bounds__(1024) k_scan_partials(uint64_t* __restrict__ partial, int64_t n) {
+  __shared__ uint64_t s[1024];
+  __shared__ uint64_t carry;
   const int tid = threadIdx.x;
   if (tid == 0) carry = 0;
   __syncthreads();
   for (int64_t base = 0; base < n; base += 1024) {
-    const uint32_t v = base + tid < n ? partial[base + tid] : 0u;
+    const uint64_t v = base + tid < n ? partial[base + tid] : 0u;
     s[tid] = v;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
-      const uint32_t add = tid >= off ? s[tid - off] : 0u;
+      const uint64_t add = tid >= off ? s[tid - off] : 0u;
       __syncthreads();
       s[tid] += add;
       __syncthreads();
@@ -226,7 +229,7 @@ __global__ void __launch_bounds__(1024) k_scan_partials(uint32_t* __restrict__ p
 }
 
 // Pass 3: add the block prefixes.
-__global__ void __launch_bounds__(256) k_scan_add(uint32_t* __restrict__ out, const uint32_t* __restrict__ partial,
+__global__ void __launch_bounds__(256) k_scan_add(uint64_t* __restrict__ out, const uint64_t* __restrict__ partial,
                                                   int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] += partial[i / 1024];
@@ -240,7 +243,7 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__
                                                      int B, int slot,
                                                      const uint64_t* __restrict__ spans,
                                                      const uint32_t* __restrict__ count,
-                                                     const uint32_t* __restrict__ offset,
+                                                     const uint64_t* __restrict__ offset,
                                                      uint32_t* __restrict__ cursor, int32_t* __restrict__ list,
                                                      uint64_t capacity) {
   int v = 0, l = 0;
@@ -275,7 +278,7 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__
     base = __shfl(base, leader);
     if (c0 == lc) {
       const uint32_t rank = base + (uint32_t)__popcll(same & lt);
-      const uint64_t end = (uint64_t)offset[b0] + count[b0];
+      const uint64_t end = offset[b0] + count[b0];
       if (end <= capacity) list[front ? offset[b0] + rank : end - 1 - rank] = t;
     }
     active &= ~same;
@@ -286,7 +289,7 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__
       if (ty == ty0 && tx == tx0) continue;
       const int64_t b = bin_index(g0 + (int64_t)ty * ntx + tx, l, k);
       const uint32_t rank = atomicAdd(cursor + 2 * b + (front ? 0 : 1), 1u);
-      const uint64_t end = (uint64_t)offset[b] + count[b];
+      const uint64_t end = offset[b] + count[b];
       if (end <= capacity) list[front ? offset[b] + rank : end - 1 - rank] = t;
     }
 }
@@ -309,7 +312,7 @@ template <int B>
 __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
     const vs_view* __restrict__ views, const int32_t* __restrict__ bin_view, int64_t n_tiles, LayerTable L,
     const ProjVert* __restrict__ proj, int64_t vpv, int slot, const uint32_t* __restrict__ count,
-    const uint32_t* __restrict__ offset, const int32_t* __restrict__ list, uint64_t capacity,
+    const uint64_t* __restrict__ offset, const int32_t* __restrict__ list, uint64_t capacity,
     unsigned long long* __restrict__ vis, unsigned long long* __restrict__ status, int count_frags) {
   __shared__ unsigned long long tile[B * B];
   const int k = L.k;
@@ -334,9 +337,9 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
   const int32_t* tri = L.tri[l];
   const int32_t nvert = L.n_vert[l];
   const uint32_t cnt = count[bid];
-  const bool overflow = (uint64_t)offset[bid] + cnt > capacity;
+  const bool overflow = offset[bid] + cnt > capacity;
   const uint32_t n = overflow ? (uint32_t)L.n_tri[l] : cnt;
-  const int32_t* lst = list + offset[bid];
+  const int32_t* lst = list + (overflow ? 0 : offset[bid]);
   unsigned long long frags = 0;
   __syncthreads();
   for (uint32_t c0 = 0; c0 < n; c0 += kRasterThreads) {

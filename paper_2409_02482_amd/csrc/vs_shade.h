@@ -217,9 +217,6 @@ __global__ void __launch_bounds__(256) k_shade_fwd(const vs_view* __restrict__ v
   if (c.valid) out[V.pix_offset + pix] = make_float4(Cr, Cg, Cb, 1.0f - T);
 }
 
-// Relative texel offset of index i from reference r in [-n/2, n/2) (repeat) or plain difference (clamp).
-
-
 // Wavefront min / max without the LDS pipe: inclusive row scans with DPP
 // row shifts (row_shr:n moves lane i - n into lane i; lanes with no source
 // keep the identity), then the four row results from lanes 15, 31, 47, 63.
@@ -334,7 +331,7 @@ __global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 3) k_shade_bwd(const vs_v
                                                    const float4* __restrict__ target, float loss_scale,
                                                    int loss,
                                                    float4* __restrict__ out, double* __restrict__ sse, int wrap,
-                                                   unsigned long long* __restrict__ status) {
+                                                   float eps_T, unsigned long long* __restrict__ status) {
 #pragma clang fp contract(fast)
   __shared__ __align__(16) float win_all[4][kWaveWin * 5];   // per wave: RGBA sums, then the owner words
   __shared__ double sred[4];
@@ -361,11 +358,13 @@ __global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 3) k_shade_bwd(const vs_v
   float Tl[KMAX], fxs[KMAX], fys[KMAX];
   int32_t ij[KMAX];   // packed (j0 << 16 | i0); i1, j1 follow from them
   uint32_t hitmask = 0;
-  float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.0f;
+  // T starts at 0 on padding lanes, as in k_shade_fwd, so that both kernels take the same early exit
+  float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = c.valid ? 1.0f : 0.0f;
+  bool walk = true;
 #pragma unroll
   for (int l = 0; l < KMAX; ++l) {
     Foot f;
-    if (keys[l] != kEmpty &&
+    if (walk && keys[l] != kEmpty &&
         slot_footprint(L.tri[l], L.n_tri[l], L.n_vert[l], pview + L.vert_off[l],
                        reinterpret_cast<const float2*>(L.uv[l]), keys[l], px, py, X.w[l], X.h[l], X.inv_w[l],
                        X.inv_h[l], wrap, f, status)) {
@@ -378,6 +377,8 @@ __global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 3) k_shade_bwd(const vs_v
       Cr += ta * s.x; Cg += ta * s.y; Cb += ta * s.z;
       T *= (1.0f - s.w);
     }
+    // the forward kernel's early exit: the layers behind it are neither blended nor differentiated
+    if (l < k && eps_T > 0.f && __all(T < eps_T)) walk = false;
   }
   float gr = 0.f, gg = 0.f, gb = 0.f, gA = 0.f;
   double my_sse = 0.0;

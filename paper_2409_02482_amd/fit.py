@@ -22,6 +22,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import os
 import sys
 import time
 from typing import List, Optional, Sequence
@@ -35,6 +36,51 @@ from . import binding as R
 def psnr_from_sse(sse: np.ndarray, n_scalars: int) -> np.ndarray:
     mse = np.asarray(sse, np.float64) / n_scalars
     return 10.0 * np.log10(1.0 / np.maximum(mse, 1e-30))
+
+
+CHECKPOINT_VERSION = 1
+
+
+def save_state(path: str, state: dict, meta: Optional[dict] = None) -> None:
+    """Write named tensors or lists of tensors (copied to host memory) with torch.save."""
+    out = {"version": CHECKPOINT_VERSION, "meta": dict(meta or {}), "tensors": {}}
+    for name, val in state.items():
+        if isinstance(val, (list, tuple)):
+            out["tensors"][name] = [t.detach().to("cpu", copy=True) for t in val]
+        else:
+            out["tensors"][name] = val.detach().to("cpu", copy=True)
+    tmp = path + ".tmp"
+    torch.save(out, tmp)
+    os.replace(tmp, path)
+
+
+def load_state(path: str, into: dict, meta: Optional[dict] = None) -> None:
+    """Copy a save_state file into existing tensors of the same names, shapes and dtypes, in place (so a
+    captured graph that holds their addresses stays valid).  Nothing is written unless every tensor fits."""
+    rec = torch.load(path, map_location="cpu", weights_only=True)
+    if rec.get("version") != CHECKPOINT_VERSION:
+        raise ValueError(f"{path}: checkpoint version {rec.get('version')} (expected {CHECKPOINT_VERSION})")
+    if meta is not None:
+        for key, val in meta.items():
+            if rec["meta"].get(key) != val:
+                raise ValueError(f"{path}: {key} = {rec['meta'].get(key)!r}, this run has {val!r}")
+    saved = rec["tensors"]
+    pairs = []
+    for name, dst in into.items():
+        if name not in saved:
+            raise ValueError(f"{path}: no tensor {name!r}")
+        src = saved[name]
+        dl = list(dst) if isinstance(dst, (list, tuple)) else [dst]
+        sl = list(src) if isinstance(src, (list, tuple)) else [src]
+        if len(dl) != len(sl):
+            raise ValueError(f"{path}: {name} has {len(sl)} tensors, expected {len(dl)}")
+        for i, (d, t) in enumerate(zip(dl, sl)):
+            if d.shape != t.shape or d.dtype != t.dtype:
+                raise ValueError(f"{path}: {name}[{i}] is {tuple(t.shape)} {t.dtype}, expected "
+                                 f"{tuple(d.shape)} {d.dtype}")
+            pairs.append((d, t))
+    for d, t in pairs:
+        d.copy_(t)
 
 
 class TextureFit:
@@ -128,6 +174,31 @@ class TextureFit:
         self.stream.synchronize()
         n = int(self.step.item())
         return self.history[:min(n, self.history.numel())].cpu().numpy()
+
+    def _state(self) -> dict:
+        # the rendered texture of the quantised mode is a function of the logits: re-derived on load
+        return {"params": self.params, "m": self.m, "v": self.v, "step": self.step, "history": self.history}
+
+    def _meta(self) -> dict:
+        return {"k": self.k, "loss": self.loss, "quantize": bool(self.quantize), "levels": int(self.levels),
+                "lr": float(self.lr), "betas": [float(b) for b in self.betas], "eps": float(self.eps),
+                "views": [list(hw) for hw in self.views.sizes]}
+
+    def save(self, path: str) -> None:
+        """Checkpoint the fit between iterations: parameters, Adam moments, step and loss history."""
+        self.stream.synchronize()
+        save_state(path, self._state(), self._meta())
+
+    def load(self, path: str) -> None:
+        """Resume from save(): the same tensors are overwritten in place, so a captured graph stays valid."""
+        self.stream.synchronize()
+        load_state(path, self._state(), self._meta())
+        if self.quantize:
+            R.squeeze(self.params, self.tex, self.levels, stream=self.stream)
+        for g in self.grads:
+            g.zero_()
+        self.sse.zero_()
+        torch.cuda.synchronize()
 
     def psnr(self) -> np.ndarray:
         if self.loss != "l2":

@@ -265,3 +265,62 @@ def test_status_strings(C):
     assert L.vs_status_string(0) == b"VS_OK"
     assert L.vs_status_string(3) == b"VS_ERR_WORKSPACE"
     assert L.vs_version().startswith(b"volsurf")
+
+
+# ---------------------------------------------------------------------------- binding argument checks
+class _NoCalls:
+    """Stands in for the library: any entry point reached means a check came too late."""
+
+    def __getattr__(self, name):
+        raise AssertionError(f"the library was called ({name}) before the arguments were checked")
+
+
+@pytest.fixture()
+def host_scene(C, monkeypatch):
+    """A k = 3 scene whose layers and views live in host memory, and a library that must not be called."""
+    import torch
+
+    from paper_2409_02482_amd import binding as B
+    sc = S.make_config(1, resolution=(24, 16), tex_res=8, with_targets=False)
+    layers = B.Layers(sc.layers, device="cpu")
+    views = B.Views(sc.cameras, device="cpu")
+    monkeypatch.setattr(B.C, "load", lambda: _NoCalls())
+    tex = [torch.zeros(8, 8, 4) for _ in range(3)]
+    vis = torch.zeros(3 * views.total_pixels, dtype=torch.int64)
+    ws = torch.zeros(1024, dtype=torch.uint8)
+    return B, layers, views, tex, vis, ws
+
+
+def test_binding_rejects_wrong_counts_and_shapes(host_scene):
+    import torch
+    B, layers, views, tex, vis, ws = host_scene
+    P = views.total_pixels
+    img = torch.zeros(P, 4)
+    bad = [
+        ("textures", lambda: B.render(layers, tex[:2], views, vis, ws)),
+        ("texture shape", lambda: B.render(layers, tex[:2] + [torch.zeros(8, 8, 3)], views, vis, ws)),
+        ("vis", lambda: B.render(layers, tex, views, vis[:-1], ws)),
+        ("out", lambda: B.render(layers, tex, views, vis, ws, out=torch.zeros(P - 1, 4))),
+        ("bwd textures", lambda: B.render_backward(layers, tex[:1], views, vis, ws, grad_rgba=img)),
+        ("grad_tex count", lambda: B.render_backward(layers, tex, views, vis, ws, grad_rgba=img,
+                                                     grad_tex=[torch.zeros(8, 8, 4)] * 2)),
+        ("grad_tex shape", lambda: B.render_backward(layers, tex, views, vis, ws, grad_rgba=img,
+                                                     grad_tex=[torch.zeros(8, 8, 4)] * 2 + [torch.zeros(4, 8, 4)])),
+        ("grad_rgba", lambda: B.render_backward(layers, tex, views, vis, ws, grad_rgba=torch.zeros(P, 3))),
+        ("target", lambda: B.render_backward(layers, tex, views, vis, ws, target=torch.zeros(P + 1, 4))),
+        ("bwd out", lambda: B.render_backward(layers, tex, views, vis, ws, grad_rgba=img, out=torch.zeros(2, 4))),
+        ("no upstream", lambda: B.render_backward(layers, tex, views, vis, ws)),
+        ("bwd vis", lambda: B.render_backward(layers, tex, views, vis[:5], ws, grad_rgba=img)),
+        ("raster vis", lambda: B.raster(layers, views, vis=vis[:-3], ws=ws)),
+        ("sh count", lambda: B.render_sh(layers, [(torch.zeros(8 * 8 * 64, dtype=torch.uint8), 8, 8)] * 2,
+                                         views, vis, ws)),
+        ("sh bytes", lambda: B.render_sh(layers, [(torch.zeros(100, dtype=torch.uint8), 8, 8)] * 3,
+                                         views, vis, ws)),
+        ("adam count", lambda: B.adam_step(tex, tex, tex[:2], tex, torch.zeros(1, dtype=torch.int32))),
+        ("adam shape", lambda: B.adam_step(tex, tex, tex[:2] + [torch.zeros(4, 4, 4)], tex,
+                                           torch.zeros(1, dtype=torch.int32))),
+        ("squeeze", lambda: B.squeeze(tex, tex[:1])),
+    ]
+    for what, call in bad:
+        with pytest.raises(ValueError):
+            call()

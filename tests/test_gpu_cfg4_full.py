@@ -3,8 +3,9 @@ layer, 64 ring views of uneven size from 512 x 512 to 1920 x 1080, the bin
 size picked by vs_autotune, then one batched raster and one fused shade + RGB
 L2 adjoint launch over all views, two steps over the same buffers.
 
-Every view is checked against the FP64 oracle, the views spread over host
-threads: visibility bit-exact, the image written by the fused launch within
+The step is also captured in a HIP graph and replayed twice; each replay
+equals the eager step.  Every view is checked against the FP64 oracle, the
+views spread over host threads: visibility bit-exact, the image written by the fused launch within
 1e-5, the squared-error sum within 1e-5 relative, and the texture gradient
 summed over all 64 views within 1e-4 normwise.
 """
@@ -61,6 +62,36 @@ def test_cfg4_step_full_batch(torch_cuda):
         torch.cuda.synchronize()
     st = P.read_status(ws)
     assert st["culled_invalid"] == 0 and st["bad_index"] == 0 and st["bad_key"] == 0, st
+
+    # The same step captured in a HIP graph (raster, gradient and SSE reset, fused shade + adjoint) and
+    # replayed twice, with eager work and synchronisations between the replays: every replay must equal
+    # the eager step, which is checked against the oracle below (visibility and image bit for bit, the
+    # SSE and the gradient up to the order of their floating-point atomics).
+    eager = (vis.clone(), out.clone(), [g.clone() for g in grads], sse.item())
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        P.raster(layers, views, vis, ws, bin=bin_size)
+        for g in grads:
+            g.zero_()
+        sse.zero_()
+        P.render_backward(layers, tex, views, vis, ws, grad_tex=grads, target=target, loss_scale=loss_scale,
+                          out=out, sse=sse)
+    for rep in range(2):
+        vis.fill_(0)
+        out.fill_(-1.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        gerr = max((a - b).abs().max().item() for a, b in zip(grads, eager[2])) / \
+            max(b.abs().max().item() for b in eager[2])
+        serr = abs(sse.item() - eager[3]) / eager[3]
+        say(f"[gpu] cfg4 graph replay {rep}: vis {'equal' if torch.equal(vis, eager[0]) else 'DIFFERS'}, "
+            f"image {'equal' if torch.equal(out, eager[1]) else 'DIFFERS'}, sse rel {serr:.1e}, grad rel {gerr:.1e}")
+        assert torch.equal(vis, eager[0]) and torch.equal(out, eager[1])
+        assert serr <= 1e-9 and gerr <= 1e-5
+    del graph, eager
     vis_h = vis.cpu()
     out_h = out.cpu()
     got = [g.cpu().numpy().astype(np.float64) for g in grads]

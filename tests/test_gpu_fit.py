@@ -108,3 +108,41 @@ def test_autotune_picks_a_bin_and_results_are_identical(torch_cuda, tmp_path):
     # cache hit returns the same answer without timing
     assert P.autotune(layers, views, vis, ws, cache_path=cache) == b
     assert open(cache).read().count("\n") == 1
+
+
+@pytest.mark.parametrize("quantize", [False, True], ids=["texels", "quantised_logits"])
+def test_checkpoint_resume_continues_the_curve(torch_cuda, tmp_path, quantize):
+    """Save after 10 iterations; a fresh fit (graph-captured) that loads the file continues the run: its
+    state after loading equals the saved one bit for bit, and its next 10 PSNR values and final texels equal
+    those of the uninterrupted run (up to the order of floating-point atomics)."""
+    torch = torch_cuda
+    from paper_2409_02482_amd.fit import TextureFit, render_targets
+    sc, gt, init = _small_fit_scene()
+    targets = render_targets(sc.layers, sc.cameras, gt)
+    loss = "l1" if quantize else "l2"
+    a = TextureFit(sc.layers, sc.cameras, init, targets, mode="graph", max_iters=64, loss=loss, quantize=quantize)
+    a.capture()
+    a.run(10)
+    path = str(tmp_path / "fit.pt")
+    a.save(path)
+    saved = [p.clone() for p in a.params] + [m.clone() for m in a.m] + [v.clone() for v in a.v]
+    a.run(10)
+    b = TextureFit(sc.layers, sc.cameras, init, targets, mode="graph", max_iters=64, loss=loss, quantize=quantize)
+    b.capture()          # captured before loading: the load writes in place
+    b.load(path)
+    now = [p.clone() for p in b.params] + [m.clone() for m in b.m] + [v.clone() for v in b.v]
+    assert all(torch.equal(x, y) for x, y in zip(saved, now))
+    assert int(b.step.item()) == 10
+    b.run(10)
+    ha, hb = a.loss_history(), b.loss_history()
+    assert len(ha) == len(hb) == 20
+    assert np.array_equal(ha[:10], hb[:10])
+    rel = np.abs(ha[10:] - hb[10:]) / ha[10:]
+    say(f"[gpu] resume ({loss}{', quantised' if quantize else ''}): loss curve rel gap {rel.max():.2e}")
+    assert rel.max() < 1e-4
+    # parameters (the texels, or their logits); a quantised texel may land on the neighbouring 8-bit level
+    for x, y in zip(a.params, b.params):
+        assert torch.allclose(x, y, atol=1e-4)
+    with pytest.raises(ValueError):
+        TextureFit(sc.layers, sc.cameras, init, targets, mode="graph", max_iters=64,
+                   loss="l2" if quantize else "l1").load(path)

@@ -11,7 +11,11 @@ Cases: ragged views, a distant camera whose corner rays miss the cube,
 k = 1 / 2 / 3 / 7 / 16 (the maximum), offsets inside and outside the main surface (up to
 77 / beta), no importance sampling, two-slot sample counts, 64 and
 2048 march steps, odd occupancy resolutions (a partial last bit word), and the
-full-size grids and views of the bench on sampled rays.
+full-size grids and views of the bench on 4,800 sampled rays per view (half
+of them in the silhouette band).  A ray with a march midpoint within 1e-9
+voxel of an interior voxel face (the oracle flags it from its own
+coordinates) is left out and counted: which voxel holds such a midpoint
+depends on the last bits of its coordinate, so its result is not unique.
 """
 import math
 
@@ -102,24 +106,28 @@ def test_ksdf_render_matches_oracle(torch_cuda, case):
         want = K.render(g, oopts, occ_np, cam)
         n = cam.width * cam.height
         sl = slice(off, off + n)
-        err = np.abs(rgba[sl] - want["rgba"]).max()
-        lerr = np.abs(lay[:, sl] - want["layers"]).max()
         empty_w = want["samples"][:, 0] < 0
         empty_g = smp[sl, 0] < 0
         o, d = K.camera_rays(cam)
+        # rays with a march midpoint on a voxel face have no unique result: left out, and counted
+        keep = ~K.march_on_face(o, d, oopts.occ_res, g.lo, g.hi, oopts.march_steps)
         t_in, t_out, _ = K.box_interval(o, d, g.lo, g.hi)
         span = np.where(empty_w, 1.0, t_out - t_in)
         dt = np.abs(smp[sl] - want["samples"])
-        terr = (dt / span[:, None])[~empty_w].max() if (~empty_w).any() else 0.0
+        terr = (dt / span[:, None])[~empty_w & keep].max() if (~empty_w & keep).any() else 0.0
         gap = np.diff(want["samples"], axis=1).max(1)
+        err = np.abs(rgba[sl] - want["rgba"])[keep].max()
+        lerr = np.abs(lay[:, sl] - want["layers"])[:, keep].max()
         say(f"[gpu] ksdf {case} view {v}: colour err {err:.2e}, layer err {lerr:.2e}, "
-            f"sample err {terr:.2e} (x interval), empty rays {int(empty_w.sum())}/{n}")
-        assert np.array_equal(empty_g, empty_w)
-        assert (smp[sl][empty_w] == -1.0).all() and (rgba[sl][empty_w] == 0.0).all()
+            f"sample err {terr:.2e} (x interval), empty rays {int(empty_w.sum())}/{n}, "
+            f"face rays left out {int((~keep).sum())}")
+        assert (~keep).sum() <= max(1, n // 100)
+        assert np.array_equal(empty_g[keep], empty_w[keep])
+        assert (smp[sl][empty_w & keep] == -1.0).all() and (rgba[sl][empty_w & keep] == 0.0).all()
         assert err <= TOL and lerr <= TOL
-        assert (dt.max(1) <= np.maximum(gap, 0.0))[~empty_w].all()
+        assert (dt.max(1) <= np.maximum(gap, 0.0))[~empty_w & keep].all()
         if oopts.n_importance == 0:
-            assert np.array_equal(smp[sl], want["samples"])
+            assert np.array_equal(smp[sl][keep], want["samples"][keep])
         off += n
     # the distant view has rays that miss the cube and rays that meet no occupied voxel
     assert empty_w.sum() > 0
@@ -152,12 +160,20 @@ def test_ksdf_full_size_sampled_rays(torch_cuda):
     off = 0
     for v, cam in enumerate(cams):
         o, d = K.camera_rays(cam)
-        pick = rng.choice(cam.width * cam.height, 60, replace=False)
+        n = cam.width * cam.height
+        # 2,400 rays drawn uniformly over the view and 2,400 from the silhouette band of the main surface
+        # (rays passing the centre at a distance between 0.9 and 1.1, where the surfaces are grazed)
+        miss = np.linalg.norm(np.cross(o, d), axis=1)
+        band = np.flatnonzero((miss > 0.9) & (miss < 1.1))
+        pick = np.unique(np.concatenate([rng.choice(n, 2400, replace=False), rng.choice(band, 2400, replace=False)]))
+        face = K.march_on_face(o[pick], d[pick], oopts.occ_res, g.lo, g.hi, oopts.march_steps)
+        pick = pick[~face]
         want = K.render_rays(g, oopts, occ_np, o[pick], d[pick])
         err = np.abs(rgba[off + pick] - want["rgba"]).max()
         lerr = np.abs(lay[:, off + pick] - want["layers"]).max()
         hit = (want["rgba"][:, 3] > 0).sum()
         say(f"[gpu] ksdf full size view {v}: colour err {err:.2e}, layer err {lerr:.2e} on {len(pick)} rays "
-            f"({hit} covered)")
-        assert err <= TOL and lerr <= TOL and hit > 20
-        off += cam.width * cam.height
+            f"({hit} covered, {int(face.sum())} face rays left out)")
+        assert err <= TOL and lerr <= TOL and hit > 1000 and len(pick) >= 4000
+        assert face.sum() <= len(face) // 100
+        off += n

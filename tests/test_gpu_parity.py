@@ -10,7 +10,7 @@ import pytest
 import oracle as O
 import scenes as S
 from vs_testlib import (EMPTY, GRAD_RTOL, assert_colour_close, assert_vis_equal, gpu_render, grad_rel_err,
-                        img_numpy, pick_entries, say, small_mixed_scene, vis_numpy)
+                        img_numpy, oracle_vis, pick_entries, say, small_mixed_scene, vis_numpy)
 
 pytestmark = pytest.mark.gpu
 
@@ -152,7 +152,7 @@ def test_cfg1_gradient_linear_loss(torch_cuda):
     P, layers, views, vis, ws, rgba, tex = gpu_render(sc)
     g = S.upstream_grad(1, cam)
     got = _gpu_backward(P, layers, views, vis, ws, tex, grad_rgba=torch.from_numpy(g.reshape(-1, 4)).cuda())
-    visn = vis_numpy(views, vis, sc.k, 0)
+    visn = oracle_vis(sc, views, vis, 0)
     want = O.backward(sc.layers, sc.textures, cam, visn, grad_out=g.astype(np.float64))
     err = grad_rel_err(got, want)
     say(f"[gpu] cfg1 grad rel err {err:.2e}")
@@ -178,7 +178,7 @@ def test_cfg3_gradient_l2_full_size(torch_cuda):
     torch.cuda.synchronize()
     got = [g.cpu().numpy().astype(np.float64) for g in grads]
     assert torch.allclose(out2, rgba, rtol=0, atol=1e-6), "fused backward's forward image differs from vs_render"
-    visn = vis_numpy(views, vis, sc.k, 0)
+    visn = oracle_vis(sc, views, vis, 0)
     say("[gpu] cfg3 oracle backward")
     want = O.backward(sc.layers, sc.textures, cam, visn, target=sc.targets[0])
     err = grad_rel_err(got, want)
@@ -203,7 +203,7 @@ def test_ragged_gradient_matches_oracle(torch_cuda):
     got = _gpu_backward(P, layers, views, vis, ws, tex, grad_rgba=flat)
     want = [np.zeros(t.shape) for t in sc.textures]
     for v, cam in enumerate(sc.cameras):
-        w = O.backward(sc.layers, sc.textures, cam, vis_numpy(views, vis, sc.k, v), grad_out=gs[v].astype(np.float64))
+        w = O.backward(sc.layers, sc.textures, cam, oracle_vis(sc, views, vis, v), grad_out=gs[v].astype(np.float64))
         want = [a + b for a, b in zip(want, w)]
     assert grad_rel_err(got, want) <= GRAD_RTOL
 
@@ -232,7 +232,7 @@ def test_gradient_scatter_paths(torch_cuda, case, wrap):
     got = _gpu_backward(P, layers, views, vis, ws, tex, grad_rgba=flat, wrap=wrap)
     want = [np.zeros(t.shape) for t in sc.textures]
     for v, cam in enumerate(sc.cameras):
-        w = O.backward(sc.layers, sc.textures, cam, vis_numpy(views, vis, sc.k, v), grad_out=gs[v].astype(np.float64),
+        w = O.backward(sc.layers, sc.textures, cam, oracle_vis(sc, views, vis, v), grad_out=gs[v].astype(np.float64),
                        wrap=wrap)
         want = [a + b for a, b in zip(want, w)]
     err = grad_rel_err(got, want)
@@ -302,7 +302,7 @@ def test_layer_counts_up_to_the_maximum(torch_cuda, k):
     got = _gpu_backward(P, layers, views, vis, ws, tex, grad_rgba=flat)
     want = [np.zeros(t.shape) for t in sc.textures]
     for v, cam in enumerate(sc.cameras):
-        w = O.backward(sc.layers, sc.textures, cam, vis_numpy(views, vis, sc.k, v), grad_out=gs[v].astype(np.float64))
+        w = O.backward(sc.layers, sc.textures, cam, oracle_vis(sc, views, vis, v), grad_out=gs[v].astype(np.float64))
         want = [a + b for a, b in zip(want, w)]
     err = grad_rel_err(got, want)
     say(f"[gpu] k={k}: grad rel err {err:.2e}")

@@ -15,7 +15,7 @@ import pytest
 
 import oracle as O
 import scenes as S
-from vs_testlib import GRAD_RTOL, gpu_render, grad_rel_err, say, small_mixed_scene, vis_numpy
+from vs_testlib import GRAD_RTOL, gpu_render, grad_rel_err, oracle_vis, say, small_mixed_scene
 
 pytestmark = pytest.mark.gpu
 
@@ -43,7 +43,7 @@ def test_l1_adjoint_matches_oracle(torch_cuda):
     want = [np.zeros(t.shape) for t in sc.textures]
     l1 = 0.0
     for v, cam in enumerate(sc.cameras):
-        visn = vis_numpy(views, vis, sc.k, v)
+        visn = oracle_vis(sc, views, vis, v)
         w = O.backward(sc.layers, sc.textures, cam, visn, target=tg[v], loss="l1")
         want = [a + scale * b for a, b in zip(want, w)]
         img = O.shade(sc.layers, sc.textures, cam, visn)

@@ -11,7 +11,7 @@ import pytest
 
 import oracle as O
 import scenes as S
-from vs_testlib import COLOUR_ATOL, assert_colour_close, img_numpy, say, small_mixed_scene, vis_numpy
+from vs_testlib import COLOUR_ATOL, assert_colour_close, img_numpy, oracle_vis, say, small_mixed_scene
 
 pytestmark = pytest.mark.gpu
 
@@ -45,7 +45,7 @@ def _check(scene, sh, what, views_to_check=None, **kw):
     worst = 0.0
     for v in (views_to_check if views_to_check is not None else range(len(scene.cameras))):
         cam = scene.cameras[v]
-        visn = vis_numpy(views, vis, scene.k, v)
+        visn = oracle_vis(scene, views, vis, v)
         want = O.shade_sh(scene.layers, sh, cam, visn, degree=kw.get("degree", 3), vmin=kw.get("vmin", -15.0),
                           vmax=kw.get("vmax", 15.0), wrap=kw.get("wrap", 0), view_alpha=kw.get("view_alpha", True))
         worst = max(worst, assert_colour_close(img_numpy(views, out, v), want, f"sh {what} view {v}"))

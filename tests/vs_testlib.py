@@ -38,6 +38,17 @@ def vis_numpy(views, vis, k, v):
     return views.vis_planes(vis, k, v).cpu().numpy().view(np.uint64)
 
 
+def oracle_vis(scene, views, vis, v):
+    """The oracle's own visibility of view v, asserted equal to the GPU's buffer first.
+
+    The oracle's shading, adjoint and finite differences then run on the oracle's own rasterisation:
+    no input of the oracle ever comes from the HIP path."""
+    import oracle as O
+    want = O.raster_layers(scene.layers, scene.cameras[v])
+    assert_vis_equal(vis_numpy(views, vis, scene.k, v), want, f"view {v}")
+    return want
+
+
 def img_numpy(views, rgba, v):
     return views.image(rgba, v).cpu().numpy().astype(np.float64)
 
