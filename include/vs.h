@@ -223,6 +223,30 @@ vs_status vs_render(const vs_mesh* layers, const vs_texture* tex, int32_t k, con
                     const uint64_t* vis, const void* ws, size_t ws_bytes, float* out_rgba,
                     const vs_shade_opts* opts, void* stream);
 
+/* Raster and shade in one call WITHOUT ALLOCATING: for callers that cannot
+ * allocate device memory or pass a workspace (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The result is that
+ * of vs_raster_layers(layers, k, views, vis, ws, ..., raster_opts) followed by
+ * vs_render(layers, tex, k, views, vis, ws, ..., out_rgba, shade_opts): the
+ * same kernels, with the workspace taken from a static device array of
+ * VS_NOALLOC_SCRATCH_BYTES bytes that the library holds on every device it
+ * runs on until the process ends (its address is looked up once per device,
+ * at the first call on that device).
+ * vis:      device u64 [sum_v k H_v W_v], written in full (as vs_raster_layers).
+ * out_rgba: device f32 [sum_v H_v W_v][4] (as vs_render).
+ * raster_opts, shade_opts: may be NULL (defaults).
+ * Errors: VS_ERR_WORKSPACE, before anything is enqueued, when
+ * vs_raster_workspace_bytes for these layers, views and raster options
+ * exceeds VS_NOALLOC_SCRATCH_BYTES; other argument errors as the two calls.
+ * Every call on one device shares that device's array and leaves its
+ * contents behind (each call re-initialises what it reads): calls that
+ * overlap in time on one device, on any streams, race and must be ordered
+ * by the caller. */
+#define VS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+vs_status vs_render_noalloc(const vs_mesh* layers, const vs_texture* tex, int32_t k, const vs_views* views,
+                            uint64_t* vis, float* out_rgba, const vs_raster_opts* raster_opts,
+                            const vs_shade_opts* shade_opts, void* stream);
+
 /* Texture adjoint: the derivative of vs_render's image with respect to the
  * texels, which is what the texturing phase optimises on fixed meshes
  * (Sec. 4.3 "Texturing Meshes").  The blend of Sec. 4.2, Eq. 6 is reversed

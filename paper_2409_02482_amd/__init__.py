@@ -9,10 +9,11 @@ behind a C ABI (include/vs.h).
 from ._lib import LIB_PATH, VsError, load  # noqa: F401
 from .binding import (Graph, KsdfField, Layers, NgpConfig, Renderer, Views, adam_step,  # noqa: F401
                      adam_step_squeezed, alloc_workspace, autotune, ksdf_occupancy, ksdf_opts, ksdf_render,
-                     ngp_backward, ngp_bake, ngp_workspace, raster, read_status, render, render_backward, render_sh,
+                     ngp_backward, ngp_bake, ngp_workspace, raster, read_status, render, render_backward,
+                     render_noalloc, render_sh,
                      squeeze, workspace_bytes)
 
-__all__ = ["Layers", "Views", "Renderer", "raster", "render", "render_backward", "render_sh", "read_status",
+__all__ = ["Layers", "Views", "Renderer", "raster", "render", "render_backward", "render_noalloc", "render_sh", "read_status",
            "workspace_bytes", "alloc_workspace", "autotune", "adam_step", "adam_step_squeezed", "squeeze",
            "NgpConfig", "ngp_bake", "ngp_backward", "ngp_workspace", "KsdfField", "ksdf_opts", "ksdf_occupancy",
            "ksdf_render", "Graph",

@@ -23,6 +23,7 @@ VS_RASTER_DIRECT = 2
 STAT_NAMES = ["culled_invalid", "culled_degenerate", "bad_index", "fragments", "bad_key", "bin_overflow",
               "reserved6", "reserved7"]
 VS_STAT_COUNT = 8
+VS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class VsMesh(ctypes.Structure):
@@ -93,6 +94,7 @@ SIGNATURES = {
     "vs_raster_workspace_bytes": (c_sz, [c_vp, c_i32, c_vp, c_vp]),
     "vs_raster_layers": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp, c_vp]),
     "vs_render": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp, c_vp, c_vp]),
+    "vs_render_noalloc": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "vs_render_sh": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp, c_vp, c_vp]),
     "vs_render_backward": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "vs_read_status": (c_i32, [c_vp, c_sz, c_vp, c_vp]),

@@ -202,6 +202,23 @@ def render(layers: Layers, textures, views: Views, vis: torch.Tensor, ws: torch.
     return out
 
 
+def render_noalloc(layers: Layers, textures, views: Views, vis: torch.Tensor, out: torch.Tensor, bin: int = 0,
+                   eps_T: float = 0.0, wrap: int = 0, stream=None) -> torch.Tensor:
+    """vs_render_noalloc: raster into ``vis`` and shade into ``out`` with the library's static workspace
+    (no device allocation by the library; both buffers are the caller's)."""
+    _check_textures(textures, layers.k)
+    _shape(out, (views.total_pixels, 4), "out")
+    _check_vis(vis, layers, views)
+    _arg(out, torch.float32, (views.total_pixels, 4), "out")
+    tex = textures_struct(textures, layers.k)
+    ropts = _raster_opts(bin)
+    sopts = _shade_opts(eps_T, wrap)
+    C.check(C.load().vs_render_noalloc(ctypes.addressof(layers.c), ctypes.addressof(tex), layers.k,
+                                       ctypes.byref(views.c), vis.data_ptr(), out.data_ptr(), ctypes.byref(ropts),
+                                       ctypes.byref(sopts), _stream(stream)), "vs_render_noalloc")
+    return out
+
+
 def sh_texture_bytes(width: int, height: int, degree: int) -> int:
     """Bytes of one shell's packed SH levels 0..degree (level d: max(1, W >> d) x max(1, H >> d) texels,
     2d + 1 RGBA byte words each)."""

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -330,6 +331,78 @@ vs_status vs_render(const vs_mesh* layers, const vs_texture* tex, int32_t k, con
                      views->n_views, tile_view, tiles, L, X, proj, L.vert_off[k], vis, (float4*)out_rgba, eps, wrap,
                      status);
   if ((st = check_launch("vs_render"))) return st;
+  return ok();
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ no-alloc entry point
+
+// The workspace of vs_render_noalloc.  In host code this name is only a
+// stand-in for the device symbol: kernels and copies get the per-device
+// address that hipGetSymbolAddress returns, never the name itself.
+static __device__ __align__(256) unsigned char scratch[VS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];   // device address of `scratch` on each device, looked up once
+
+vs_status scratch_for_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(VS_ERR_HIP, "vs_render_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(VS_ERR_HIP, "vs_render_noalloc: device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(VS_ERR_HIP, "vs_render_noalloc: hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    if ((uintptr_t)p % 256) return fail(VS_ERR_HIP, "vs_render_noalloc: scratch not 256-byte aligned");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return VS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vs_status vs_render_noalloc(const vs_mesh* layers, const vs_texture* tex, int32_t k, const vs_views* views,
+                            uint64_t* vis, float* out_rgba, const vs_raster_opts* raster_opts,
+                            const vs_shade_opts* shade_opts, void* stream) {
+  // everything both calls check is checked here first, so that an error enqueues nothing
+  vs::LayerTable L;
+  vs::TexTable X;
+  vs_status st = build_layers(layers, k, L);
+  if (st) return st;
+  if ((st = build_textures(tex, k, X))) return st;
+  if ((st = check_views(views))) return st;
+  if (!vis || !out_rgba) return fail(VS_ERR_ARG, "vis/out_rgba: null");
+  const int bin = raster_opts ? raster_opts->bin : 0;
+  if (bin && bin_slot(bin) < 0) return fail(VS_ERR_UNSUPPORTED, "bin = %d (use 0, 8, 16, 32 or 64)", bin);
+  const int64_t cap = raster_opts ? raster_opts->list_capacity : 0;
+  if (cap < 0 || cap >= (1ll << 32)) return fail(VS_ERR_SIZE, "list_capacity must be in [0, 2^32)");
+  if ((uint64_t)views->n_views * (uint64_t)L.tri_off[k] >= (1ull << 30))
+    return fail(VS_ERR_SIZE, "n_views * total triangles must be below 2^30");
+  const int wrap = shade_opts ? shade_opts->wrap : 0;
+  if (wrap != 0 && wrap != 1) return fail(VS_ERR_UNSUPPORTED, "wrap = %d", wrap);
+  const float eps = shade_opts ? shade_opts->eps_T : 0.0f;
+  if (!(eps >= 0.0f && eps < 1.0f)) return fail(VS_ERR_ARG, "eps_T must be in [0, 1)");
+  const size_t need = ws_layout(L, views, bin, cap).total;
+  if (need > (size_t)VS_NOALLOC_SCRATCH_BYTES)
+    return fail(VS_ERR_WORKSPACE, "vs_render_noalloc: %zu workspace bytes needed, the static scratch holds %llu",
+                need, (unsigned long long)VS_NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  if ((st = scratch_for_current_device(&ws))) return st;
+  if ((st = vs_raster_layers(layers, k, views, vis, ws, (size_t)VS_NOALLOC_SCRATCH_BYTES, raster_opts, stream)))
+    return st;
+  if ((st = vs_render(layers, tex, k, views, vis, ws, (size_t)VS_NOALLOC_SCRATCH_BYTES, out_rgba, shade_opts,
+                      stream)))
+    return st;
   return ok();
 }
 

@@ -173,6 +173,34 @@ def test_render_validation_without_gpu(C):
                                 0x100000, need, None, ctypes.addressof(gp), None, None, None, None) == C.VS_ERR_ARG
 
 
+def test_render_noalloc_validation_without_gpu(C):
+    """vs_render_noalloc rejects, before any HIP call, arguments either of its two steps would reject and a
+    problem whose workspace exceeds the static scratch."""
+    L = C.load()
+    host, views, meshes, tex = _fake_call_args(C)
+    call = lambda ro=None, so=None, vis=0x5000, out=0x6000, k=2: L.vs_render_noalloc(  # noqa: E731
+        ctypes.addressof(meshes), ctypes.addressof(tex), k, ctypes.byref(views), vis, out,
+        None if ro is None else ctypes.byref(ro), None if so is None else ctypes.byref(so), None)
+    assert call(k=0) == C.VS_ERR_SIZE
+    assert call(vis=None) == C.VS_ERR_ARG
+    assert call(out=None) == C.VS_ERR_ARG
+    assert call(ro=C.VsRasterOpts(12, 0, 0)) == C.VS_ERR_UNSUPPORTED
+    assert call(ro=C.VsRasterOpts(0, 0, -1)) == C.VS_ERR_SIZE
+    assert call(so=C.VsShadeOpts(0.0, 3, None, 1.0, 0)) == C.VS_ERR_UNSUPPORTED
+    assert call(so=C.VsShadeOpts(1.5, 0, None, 1.0, 0)) == C.VS_ERR_ARG
+    tex[1].width = 0
+    assert call() == C.VS_ERR_SIZE
+    tex[1].width = 8
+    # a list capacity that alone needs more than the scratch
+    big = C.VsRasterOpts(0, 0, C.VS_NOALLOC_SCRATCH_BYTES // 4)
+    assert call(ro=big) == C.VS_ERR_WORKSPACE
+    assert b"static scratch" in L.vs_last_error()
+    # the same limit from the problem size: 5M triangles per layer need more than 64 MiB
+    for m in meshes:
+        m.n_tri, m.n_vert = 5_000_000, 2_600_000
+    assert call() == C.VS_ERR_WORKSPACE
+
+
 def test_render_sh_validation_without_gpu(C):
     L = C.load()
     host, views, meshes, _ = _fake_call_args(C)
