@@ -153,7 +153,7 @@ vs::WsLayout ws_layout(const vs::LayerTable& L, const vs_views* views, int bin, 
   w.count = take((size_t)w.n_bins * 4);
   w.offset = take((size_t)w.n_bins * 8);
   w.cursor = take((size_t)w.n_bins * 8);
-  w.spans = take((size_t)n_views * (size_t)L.tri_off[L.k] * 8);
+  w.spans = take((size_t)n_views * (size_t)L.tri_off[L.k] * sizeof(vs::SpanRec));
   w.partial = take((size_t)w.n_partial * 8);
   w.list = take((size_t)w.capacity * 4);
   w.total = off;
@@ -251,7 +251,7 @@ vs_status vs_raster_layers(const vs_mesh* layers, int32_t k, const vs_views* vie
   auto* count = (uint32_t*)(base + lay.count);
   auto* offset = (uint64_t*)(base + lay.offset);
   auto* cursor = (uint32_t*)(base + lay.cursor);
-  auto* spans = (uint64_t*)(base + lay.spans);
+  auto* spans = (vs::SpanRec*)(base + lay.spans);
   auto* partial = (uint64_t*)(base + lay.partial);
   auto* list = (int32_t*)(base + lay.list);
   const int64_t vpv = L.vert_off[k];
@@ -285,14 +285,14 @@ vs_status vs_raster_layers(const vs_mesh* layers, int32_t k, const vs_views* vie
   hipLaunchKernelGGL(vs::k_scan_add, dim3(grid_1d(lay.n_bins, 256)), dim3(256), 0, s, offset,
                      (const uint64_t*)partial, lay.n_bins);
   hipLaunchKernelGGL(vs::k_bin_scatter, dim3(bin_blocks), dim3(256), 0, s, views->dev, nv, L, B, slot,
-                     (const uint64_t*)spans, (const uint32_t*)count, (const uint64_t*)offset, cursor, list,
+                     (const vs::SpanRec*)spans, (const uint32_t*)count, (const uint64_t*)offset, cursor, list,
                      lay.capacity);
   const unsigned nblk = (unsigned)((lay.n_bins + 7) / 8 * 8);
   auto raster = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(nblk), dim3(vs::kRasterThreads), 0, s, views->dev, (const int32_t*)bin_view,
                        lay.n_tiles_bin, L, (const vs::ProjVert*)proj, vpv, slot, (const uint32_t*)count,
-                       (const uint64_t*)offset, (const int32_t*)list, lay.capacity, (unsigned long long*)vis, status,
-                       count_frags);
+                       (const uint64_t*)offset, (const uint32_t*)cursor, (const int32_t*)list,
+                       (const vs::SpanRec*)spans, lay.capacity, (unsigned long long*)vis, status, count_frags);
   };
   switch (B) {
     case 8: raster(vs::k_raster_bins<8>); break;

@@ -56,7 +56,7 @@ struct WsLayout {
   size_t count;      // u32 [n_bins] triangles per bin
   size_t offset;     // u64 [n_bins] exclusive prefix of count
   size_t cursor;     // u32 [2 n_bins] scatter cursors (front from the head, others from the tail)
-  size_t spans;      // u64 [n_views][sum n_tri] packed tile span of every triangle
+  size_t spans;      // SpanRec [n_views][sum n_tri]: box and depth bound of every triangle
   size_t partial;    // u64 [ceil(n_bins / 1024)] scan block totals
   size_t list;       // int32 [capacity] triangle ids of all bins
   int64_t n_tiles16, n_tiles_bin, n_bins, n_partial;

@@ -12,7 +12,9 @@
 //                  bin's triangles take 64-bit LDS minima, and the finished
 //                  tile is stored once, coalesced (so no clear pass is needed);
 //                  a fragment whose depth lower bound already loses to the
-//                  tile's key skips the exact FP64 depth
+//                  tile's key skips the exact FP64 depth, and a back-facing
+//                  triangle whose bound loses everywhere in its bounding box
+//                  is skipped whole
 // Atomics on bin counters are aggregated per wavefront: lanes that hit the
 // same bin elect one lane that adds the whole group.
 #pragma once
@@ -71,17 +73,31 @@ __device__ inline int cull_slot(int r) {
 // Bin index of (global tile g, layer l): bins of one tile are consecutive.
 __device__ inline int64_t bin_index(int64_t g, int l, int k) { return g * k + l; }
 
-// Tile span of one (view, layer, triangle), packed in 64 bits:
-// tx0 | tx1 << 13 | ty0 << 26 | ty1 << 39 | front << 52 | valid << 53.
+// Record of one (view, layer, triangle) written by k_bin_count: its pixel
+// bounding box clipped to the view, packed in 64 bits,
+//   i0 | i1 << 13 | j0 << 26 | j1 << 39 | front << 52 | valid << 53,
+// and the depth bits of its lower-bound key (depth_lower_key >> 32).
 // "front" marks a negative screen area before orientation normalisation,
 // which is the front side of an outward, counter-clockwise wound closed mesh
-// under this camera convention (y down).  It only orders the bin lists.
+// under this camera convention (y down).  It orders the bin lists, front
+// faces first; the raster uses the box and the bound to skip, without
+// loading its vertices, a back-facing triangle that cannot lower any key.
 constexpr uint64_t kSpanValid = 1ull << 53;
 constexpr uint64_t kSpanFront = 1ull << 52;
 
-__device__ inline uint64_t pack_span(int tx0, int tx1, int ty0, int ty1, bool front) {
-  return (uint64_t)tx0 | ((uint64_t)tx1 << 13) | ((uint64_t)ty0 << 26) | ((uint64_t)ty1 << 39) |
+struct alignas(16) SpanRec {
+  uint64_t box;
+  uint32_t zlo;    // high word of the triangle's depth lower-bound key
+  uint32_t pad;
+};
+
+__device__ inline uint64_t pack_box(int i0, int i1, int j0, int j1, bool front) {
+  return (uint64_t)i0 | ((uint64_t)i1 << 13) | ((uint64_t)j0 << 26) | ((uint64_t)j1 << 39) |
          (front ? kSpanFront : 0ull) | kSpanValid;
+}
+
+__device__ inline void unpack_box(uint64_t b, int& i0, int& i1, int& j0, int& j1) {
+  i0 = (int)(b & 8191); i1 = (int)((b >> 13) & 8191); j0 = (int)((b >> 26) & 8191); j1 = (int)((b >> 39) & 8191);
 }
 
 struct BinWork {
@@ -118,10 +134,10 @@ __device__ inline bool bin_thread(const LayerTable& L, int n_views, int& v, int&
   return true;
 }
 
-// Count triangles per bin and record each triangle's tile span.
+// Count triangles per bin and record each triangle's box and depth bound.
 __global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ views, int n_views, LayerTable L,
                                                    const ProjVert* __restrict__ proj, int64_t vpv, int B, int slot,
-                                                   uint32_t* __restrict__ count, uint64_t* __restrict__ spans,
+                                                   uint32_t* __restrict__ count, SpanRec* __restrict__ spans,
                                                    unsigned long long* __restrict__ status) {
   int v = 0, l = 0;
   int32_t t = 0;
@@ -129,7 +145,8 @@ __global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ v
   bool ok = bin_thread(L, n_views, v, l, t, g);
   const int k = L.k;
   BinWork w;
-  uint64_t span = 0;
+  SpanRec span;
+  span.box = 0; span.zlo = 0; span.pad = 0;
   if (ok) {
     const vs_view& V = views[v];
     const int W = V.cam.width, H = V.cam.height;
@@ -148,7 +165,8 @@ __global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ v
         w.tx0 = pr.i0 / B; w.tx1 = pr.i1 / B; w.ty0 = pr.j0 / B; w.ty1 = pr.j1 / B;
         w.g0 = V.tile_offset[slot];
         w.ntx = (W + B - 1) / B;
-        span = pack_span(w.tx0, w.tx1, w.ty0, w.ty1, T.orig_sign < 0);
+        span.box = pack_box(pr.i0, pr.i1, pr.j0, pr.j1, T.orig_sign < 0);
+        span.zlo = (uint32_t)(depth_lower_key(T, (uint32_t)t) >> 32);
       }
     }
     spans[(int64_t)v * L.tri_off[k] + g] = span;
@@ -241,7 +259,7 @@ __global__ void __launch_bounds__(256) k_scan_add(uint64_t* __restrict__ out, co
 // triangle of its layer instead (slow but exact) and the overflow is counted.
 __global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__ views, int n_views, LayerTable L,
                                                      int B, int slot,
-                                                     const uint64_t* __restrict__ spans,
+                                                     const SpanRec* __restrict__ spans,
                                                      const uint32_t* __restrict__ count,
                                                      const uint64_t* __restrict__ offset,
                                                      uint32_t* __restrict__ cursor, int32_t* __restrict__ list,
@@ -251,14 +269,15 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__
   int64_t g = 0;
   bool ok = bin_thread(L, n_views, v, l, t, g);
   const int k = L.k;
-  uint64_t span = ok ? spans[(int64_t)v * L.tri_off[k] + g] : 0ull;
+  const uint64_t span = ok ? spans[(int64_t)v * L.tri_off[k] + g].box : 0ull;
   ok = ok && (span & kSpanValid);
   int tx0 = 0, tx1 = 0, ty0 = 0, ty1 = 0, ntx = 0;
   int64_t g0 = 0;
   bool front = false;
   if (ok) {
-    tx0 = (int)(span & 8191); tx1 = (int)((span >> 13) & 8191);
-    ty0 = (int)((span >> 26) & 8191); ty1 = (int)((span >> 39) & 8191);
+    int i0, i1, j0, j1;
+    unpack_box(span, i0, i1, j0, j1);
+    tx0 = i0 / B; tx1 = i1 / B; ty0 = j0 / B; ty1 = j1 / B;
     front = (span & kSpanFront) != 0;
     const vs_view& V = views[v];
     g0 = V.tile_offset[slot];
@@ -306,15 +325,32 @@ __global__ void __launch_bounds__(256) k_tile_view_slot(const vs_view* __restric
 // few candidate pixels) are walked by one lane with exact int32 edge values;
 // larger ones are tested by the lane's whole wavefront, each lane owning
 // B*B/64 pixels, with exact FP64 edge values.  Wavefronts work independently
-// on the LDS tile (64-bit atomic minimum), so the tile is the block's only LDS
-// and, at B = 64, five blocks fit a CU.
+// on the LDS tile (64-bit atomic minimum).
+//
+// The bin's list holds its front-facing triangles first.  They are drawn
+// first; then the tile's largest key per 8 x 8 sub-tile is taken, and a
+// back-facing triangle whose depth lower bound (a key no larger than any key it
+// can produce) is at least every sub-tile maximum under its bounding box is
+// skipped: every pixel it could reach already holds a key no larger than any
+// of its own, so the minimum cannot change (keys only decrease).  On a closed
+// shell seen from outside, the back faces lie behind the front faces covering
+// the same pixels, so most of them are skipped without a pixel walk.  An empty
+// pixel keeps its sub-tile maximum at EMPTY, so nothing is skipped there.  With
+// fragment counting on, nothing is skipped (the count covers every covered
+// pixel of every triangle).
 template <int B>
 __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
     const vs_view* __restrict__ views, const int32_t* __restrict__ bin_view, int64_t n_tiles, LayerTable L,
     const ProjVert* __restrict__ proj, int64_t vpv, int slot, const uint32_t* __restrict__ count,
-    const uint64_t* __restrict__ offset, const int32_t* __restrict__ list, uint64_t capacity,
-    unsigned long long* __restrict__ vis, unsigned long long* __restrict__ status, int count_frags) {
+    const uint64_t* __restrict__ offset, const uint32_t* __restrict__ cursor, const int32_t* __restrict__ list,
+    const SpanRec* __restrict__ spans, uint64_t capacity, unsigned long long* __restrict__ vis,
+    unsigned long long* __restrict__ status, int count_frags) {
+  constexpr int kSub = B < 8 ? B : 8;          // sub-tile edge of the depth bound
+  constexpr int kNs = B / kSub;                // sub-tiles per row
   __shared__ unsigned long long tile[B * B];
+  __shared__ unsigned long long smax[kNs * kNs];
+  __shared__ int32_t queue[2 * kRasterThreads];   // back-facing triangles that may lower a key
+  __shared__ uint32_t qn;
   const int k = L.k;
   const int64_t n_bins = n_tiles * k;
   // XCD-contiguous remap of the block index
@@ -340,69 +376,123 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
   const bool overflow = offset[bid] + cnt > capacity;
   const uint32_t n = overflow ? (uint32_t)L.n_tri[l] : cnt;
   const int32_t* lst = list + (overflow ? 0 : offset[bid]);
+  const SpanRec* srec = spans + (int64_t)v * L.tri_off[k] + L.tri_off[l];   // records of this view and layer
+  // front-facing entries head the list (an overflowing bin scans its whole layer in one phase)
+  const uint32_t n_front = (overflow || count_frags) ? n : min(cursor[2 * bid], cnt);
   unsigned long long frags = 0;
   __syncthreads();
-  for (uint32_t c0 = 0; c0 < n; c0 += kRasterThreads) {
-    const uint32_t c = c0 + tid;
+  // Draw triangle t of this layer (t < 0: nothing).  Called by every thread of the block in
+  // step (the wavefront path for large triangles loops over the wavefront's lanes).
+  auto draw = [&](int32_t tq) {
     int32_t big = -1;   // a triangle for the whole wavefront
-    if (c < n) {
-      const int32_t t = overflow ? (int32_t)c : lst[c];
-      TriSetup T;
-      if (setup_triangle(tri + 3 * (int64_t)t, nvert, P, T) == kTriOk) {
-        PixRange pr = pixel_range(T, W, H);
-        const int ci0 = max(pr.i0, x0), ci1 = min(pr.i1, x1), cj0 = max(pr.j0, y0), cj1 = min(pr.j1, y1);
-        if (ci0 <= ci1 && cj0 <= cj1) {
-          const double spanx = fmax(T.X[0], fmax(T.X[1], T.X[2])) - fmin(T.X[0], fmin(T.X[1], T.X[2]));
-          const double spany = fmax(T.Y[0], fmax(T.Y[1], T.Y[2])) - fmin(T.Y[0], fmin(T.Y[1], T.Y[2]));
-          const int area = (ci1 - ci0 + 1) * (cj1 - cj0 + 1);
-          if (spanx <= kSmallSpan && spany <= kSmallSpan && area <= kSmallArea) {
-            const unsigned long long lbkey = depth_lower_key(T, (uint32_t)t);
-            // exact int32 edge walk: every edge value inside the bbox is below 2^30 in magnitude
-            double E[3];
-            edge_values(T, 256.0 * ci0 + 128.0, 256.0 * cj0 + 128.0, E);
-            int32_t er0 = (int32_t)E[0] - (int32_t)T.th[0];
-            int32_t er1 = (int32_t)E[1] - (int32_t)T.th[1];
-            int32_t er2 = (int32_t)E[2] - (int32_t)T.th[2];
-            const int32_t ax0 = (int32_t)(-(T.Y[2] - T.Y[1]) * 256.0), ay0 = (int32_t)((T.X[2] - T.X[1]) * 256.0);
-            const int32_t ax1 = (int32_t)(-(T.Y[0] - T.Y[2]) * 256.0), ay1 = (int32_t)((T.X[0] - T.X[2]) * 256.0);
-            const int32_t ax2 = (int32_t)(-(T.Y[1] - T.Y[0]) * 256.0), ay2 = (int32_t)((T.X[1] - T.X[0]) * 256.0);
-            for (int j = cj0; j <= cj1; ++j) {
-              int32_t e0 = er0, e1 = er1, e2 = er2;
-              for (int i = ci0; i <= ci1; ++i) {
-                if ((e0 | e1 | e2) >= 0) {
-                  unsigned long long* slotp = &tile[(j - y0) * B + (i - x0)];
-                  // keys only decrease, so a single-copy-atomic read at or below the bound proves a loss
-                  if (__hip_atomic_load(slotp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) > lbkey) {
-                    const double E0 = (double)e0 + T.th[0], E1 = (double)e1 + T.th[1], E2 = (double)e2 + T.th[2];
-                    atomicMin(slotp, (unsigned long long)depth_key(T, E0, E1, E2, (uint32_t)t));
-                  }
-                  ++frags;
+    TriSetup T;
+    if (tq >= 0 && setup_triangle(tri + 3 * (int64_t)tq, nvert, P, T) == kTriOk) {
+      const int32_t t = tq;
+      PixRange pr = pixel_range(T, W, H);
+      const int ci0 = max(pr.i0, x0), ci1 = min(pr.i1, x1), cj0 = max(pr.j0, y0), cj1 = min(pr.j1, y1);
+      if (ci0 <= ci1 && cj0 <= cj1) {
+        const unsigned long long lbkey = depth_lower_key(T, (uint32_t)t);
+        const double spanx = fmax(T.X[0], fmax(T.X[1], T.X[2])) - fmin(T.X[0], fmin(T.X[1], T.X[2]));
+        const double spany = fmax(T.Y[0], fmax(T.Y[1], T.Y[2])) - fmin(T.Y[0], fmin(T.Y[1], T.Y[2]));
+        const int area = (ci1 - ci0 + 1) * (cj1 - cj0 + 1);
+        if (spanx <= kSmallSpan && spany <= kSmallSpan && area <= kSmallArea) {
+          // exact int32 edge walk: every edge value inside the bbox is below 2^30 in magnitude
+          double E[3];
+          edge_values(T, 256.0 * ci0 + 128.0, 256.0 * cj0 + 128.0, E);
+          int32_t er0 = (int32_t)E[0] - (int32_t)T.th[0];
+          int32_t er1 = (int32_t)E[1] - (int32_t)T.th[1];
+          int32_t er2 = (int32_t)E[2] - (int32_t)T.th[2];
+          const int32_t ax0 = (int32_t)(-(T.Y[2] - T.Y[1]) * 256.0), ay0 = (int32_t)((T.X[2] - T.X[1]) * 256.0);
+          const int32_t ax1 = (int32_t)(-(T.Y[0] - T.Y[2]) * 256.0), ay1 = (int32_t)((T.X[0] - T.X[2]) * 256.0);
+          const int32_t ax2 = (int32_t)(-(T.Y[1] - T.Y[0]) * 256.0), ay2 = (int32_t)((T.X[1] - T.X[0]) * 256.0);
+          for (int j = cj0; j <= cj1; ++j) {
+            int32_t e0 = er0, e1 = er1, e2 = er2;
+            for (int i = ci0; i <= ci1; ++i) {
+              if ((e0 | e1 | e2) >= 0) {
+                unsigned long long* slotp = &tile[(j - y0) * B + (i - x0)];
+                // keys only decrease, so a single-copy-atomic read at or below the bound proves a loss
+                if (__hip_atomic_load(slotp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) > lbkey) {
+                  const double E0 = (double)e0 + T.th[0], E1 = (double)e1 + T.th[1], E2 = (double)e2 + T.th[2];
+                  atomicMin(slotp, (unsigned long long)depth_key(T, E0, E1, E2, (uint32_t)t));
                 }
-                e0 += ax0; e1 += ax1; e2 += ax2;
+                ++frags;
               }
-              er0 += ay0; er1 += ay1; er2 += ay2;
+              e0 += ax0; e1 += ax1; e2 += ax2;
             }
-          } else {
-            big = t;
+            er0 += ay0; er1 += ay1; er2 += ay2;
           }
+        } else {
+          big = t;
         }
       }
     }
     for (uint64_t bm = __ballot(big >= 0); bm; bm &= bm - 1) {
       const int32_t t = __builtin_amdgcn_readlane(big, __builtin_ctzll(bm));
-      TriSetup T;
-      setup_triangle(tri + 3 * (int64_t)t, nvert, P, T);
-      const unsigned long long lbkey = depth_lower_key(T, (uint32_t)t);
+      TriSetup Tb;
+      setup_triangle(tri + 3 * (int64_t)t, nvert, P, Tb);
+      const unsigned long long lbkey = depth_lower_key(Tb, (uint32_t)t);
       for (int p = lane; p < B * B; p += 64) {
         const int i = x0 + (p % B), j = y0 + (p / B);
         if (i > x1 || j > y1) continue;
         double E[3];
-        edge_values(T, 256.0 * i + 128.0, 256.0 * j + 128.0, E);
-        if (E[0] >= T.th[0] && E[1] >= T.th[1] && E[2] >= T.th[2]) {
+        edge_values(Tb, 256.0 * i + 128.0, 256.0 * j + 128.0, E);
+        if (E[0] >= Tb.th[0] && E[1] >= Tb.th[1] && E[2] >= Tb.th[2]) {
           if (__hip_atomic_load(&tile[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) > lbkey)
-            atomicMin(&tile[p], (unsigned long long)depth_key(T, E[0], E[1], E[2], (uint32_t)t));
+            atomicMin(&tile[p], (unsigned long long)depth_key(Tb, E[0], E[1], E[2], (uint32_t)t));
           ++frags;
         }
+      }
+    }
+  };
+  // phase 1: front-facing entries (every entry of an overflowing bin, or with fragment counting)
+  for (uint32_t c0 = 0; c0 < n_front; c0 += kRasterThreads) {
+    const uint32_t c = c0 + tid;
+    draw(c < n_front ? (overflow ? (int32_t)c : lst[c]) : -1);
+  }
+  if (n_front < n) {   // uniform: back-facing entries follow
+    for (int s = tid; s < kNs * kNs; s += kRasterThreads) smax[s] = 0ull;
+    if (tid == 0) qn = 0;
+    __syncthreads();
+    for (int p = tid; p < B * B; p += kRasterThreads) {
+      const int sx = (p % B) / kSub, sy = (p / B) / kSub;
+      atomicMax(&smax[sy * kNs + sx], tile[p]);
+    }
+    __syncthreads();
+    // phase 2: each back-facing entry is tested from its record (box and depth bound) alone;
+    // the ones that may lower a key are queued in LDS and drawn 256 at a time, so that the
+    // skipped majority costs no vertex loads and leaves no idle lanes behind.
+    for (uint32_t c0 = n_front; c0 < n; c0 += kRasterThreads) {
+      const uint32_t c = c0 + tid;
+      bool keep = false;
+      int32_t t = 0;
+      if (c < n) {
+        t = lst[c];
+        const SpanRec r = srec[t];
+        int i0, i1, j0, j1;
+        unpack_box(r.box, i0, i1, j0, j1);
+        const unsigned long long lb = ((unsigned long long)r.zlo << 32) | (uint32_t)t;
+        const int ci0 = max(i0, x0), ci1 = min(i1, x1), cj0 = max(j0, y0), cj1 = min(j1, y1);
+        for (int sj = (cj0 - y0) / kSub; sj <= (cj1 - y0) / kSub; ++sj)
+          for (int si = (ci0 - x0) / kSub; si <= (ci1 - x0) / kSub; ++si)
+            keep = keep || smax[sj * kNs + si] > lb;
+      }
+      const uint64_t kb = __ballot(keep);
+      uint32_t base = 0;
+      if (lane == 0 && kb) base = atomicAdd(&qn, (uint32_t)__popcll(kb));
+      base = __builtin_amdgcn_readfirstlane(base);
+      if (keep) queue[base + (uint32_t)__popcll(kb & __lanemask_lt())] = t;
+      __syncthreads();
+      uint32_t q = qn;
+      const bool last = c0 + kRasterThreads >= n;
+      while (q >= kRasterThreads || (last && q > 0)) {   // uniform
+        draw(tid < (int)q ? queue[tid] : -1);
+        const uint32_t rest = q > kRasterThreads ? q - kRasterThreads : 0;
+        const int32_t moved = tid < (int)rest ? queue[kRasterThreads + tid] : 0;
+        __syncthreads();
+        if (tid < (int)rest) queue[tid] = moved;
+        if (tid == 0) qn = rest;
+        __syncthreads();
+        q = rest;
       }
     }
   }

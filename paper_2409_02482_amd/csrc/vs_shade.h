@@ -219,16 +219,18 @@ __global__ void __launch_bounds__(256) k_shade_fwd(const vs_view* __restrict__ v
 
 // Wavefront min / max without the LDS pipe: inclusive row scans with DPP
 // row shifts (row_shr:n moves lane i - n into lane i; lanes with no source
-// keep the identity), then the four row results from lanes 15, 31, 47, 63.
+// keep the identity), so lane 15 of each 16-lane row holds the row's result.
 // Call with every lane active.
+// Then row_bcast:15 (rows 1 and 3 take lane 15 / 47) and row_bcast:31 (rows 2 and 3
+// take lane 31) carry the row results to lane 63.
 __device__ inline int32_t wave_min(int32_t v) {
   v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x111, 0xf, 0xf, false));
   v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x112, 0xf, 0xf, false));
   v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x114, 0xf, 0xf, false));
   v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x118, 0xf, 0xf, false));
-  const int32_t a = __builtin_amdgcn_readlane(v, 15), b = __builtin_amdgcn_readlane(v, 31);
-  const int32_t c = __builtin_amdgcn_readlane(v, 47), d = __builtin_amdgcn_readlane(v, 63);
-  return min(min(a, b), min(c, d));
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x142, 0xa, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(INT32_MAX, v, 0x143, 0xc, 0xf, false));
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
 __device__ inline int32_t wave_max(int32_t v) {
@@ -236,9 +238,9 @@ __device__ inline int32_t wave_max(int32_t v) {
   v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x112, 0xf, 0xf, false));
   v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x114, 0xf, 0xf, false));
   v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x118, 0xf, 0xf, false));
-  const int32_t a = __builtin_amdgcn_readlane(v, 15), b = __builtin_amdgcn_readlane(v, 31);
-  const int32_t c = __builtin_amdgcn_readlane(v, 47), d = __builtin_amdgcn_readlane(v, 63);
-  return max(max(a, b), max(c, d));
+  v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x142, 0xa, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(INT32_MIN, v, 0x143, 0xc, 0xf, false));
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Orders this wavefront's LDS accesses (a wave's LDS instructions execute in order).
@@ -278,30 +280,34 @@ __device__ inline int32_t lane_xor4(int32_t v, bool bit2) {
   return bit2 ? down : up;
 }
 
-// Value of v in lane (lane + 2^STEP) for the lower lane of each pair (the only
-// reader); lanes whose source falls outside their row read 0.
+// v + (v of lane (lane ^ 2^STEP)) for the lower lane of a pair: xor 1 and xor 2 are quad
+// permutations; for xor 4 the lower lane (bit 2 clear) reads lane + 4 (row_shl:4).  The
+// caller runs this with exactly the lanes of merging pairs active, so every source lane
+// a lower lane reads is active; what an upper lane computes is discarded.
 template <int STEP>
-__device__ inline float from_upper(float v) {
+__device__ inline float add_upper(float v) {
   constexpr int ctrl = STEP == 0 ? 0xb1 : STEP == 1 ? 0x4e : 0x104;
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xf, 0xf, true));
+  return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xf, 0xf, false));
 }
 
 // One butterfly step of merging contributions by base texel: lanes (lane, lane ^ 2^step)
 // holding the same key combine their 16 values in the lower lane; the upper lane drops out.
-// The add is a fused multiply-add by 1 or 0 so that the lane exchange folds into it.
+// Runs with only the merging lanes active, so the lane exchange folds into the adds
+// (16 v_add_f32_dpp per step).
 template <int STEP>
 __device__ inline void merge_by_key(int32_t& key, float (&v)[16], int lane) {
   const bool bit = (lane >> STEP) & 1;
   const int32_t other = STEP == 0 ? lane_xor1(key) : STEP == 1 ? lane_xor2(key) : lane_xor4(key, bit);
   const bool same = key >= 0 && other == key;
-  const float take = (same && !bit) ? 1.0f : 0.0f;
+  if (same) {
 #pragma unroll
-  for (int q = 0; q < 16; ++q) v[q] = __builtin_fmaf(from_upper<STEP>(v[q]), take, v[q]);
+    for (int q = 0; q < 16; ++q) v[q] = add_upper<STEP>(v[q]);
+  }
   if (same && bit) key = -1;
 }
 
-// Backward: recompute the layers front to back (keeping T and the footprint
-// of each hit layer), form dL/d(RGB, A), then walk back to front:
+// Backward: recompute the layers front to back (keeping T in front of each hit layer and
+// its bilinear footprint), form dL/d(RGB, A), then walk back to front:
 //   dL/dc_l = g_rgb a_l T_l,  dL/da_l = T_l <g_rgb, c_l - S_l> + g_A T_l prod_{m>l}(1 - a_m),
 // S_l the colour blended behind layer l.  Division-free (a = 1 is fine).
 // Each of the 4 corner texels receives its bilinear weight times these.
@@ -311,19 +317,24 @@ __device__ inline void merge_by_key(int32_t& key, float (&v)[16], int lane) {
 // magnified), so the lanes of each 4 x 2 pixel group that share a base
 // texel first sum their 16 contributions in registers (DPP butterfly steps:
 // x +- 1, y +- 1, x +- 2).  The survivors add into an LDS texel window
-// (wrap-aware) with plain read-modify-writes, one lane per base texel and
-// round (an owner word per cell elects it), and the window is flushed with
-// global float atomics whose lanes cover consecutive floats.  A footprint
-// larger than the window is retried per half wavefront, then per quarter; a
-// quarter that still does not fit uses direct global atomics.
-// The window holds 384 texels: a wavefront whose footprint does not fit falls
-// back to 16 uncoalesced atomics per lane, which with 256 texels happened for
-// 4 % of the layer-wavefronts at 1024^2 views and 7 % at 800^2 and cost 12-20 %
-// of the kernel; 384 texels (30 KiB of LDS per block) fit five blocks per CU,
-// and up to 9 layers the register budget is held to that (the scatter is
-// latency bound: a few bytes of spill cost less than lost wavefronts).
+// (wrap-aware, relative to the first surviving lane's base texel) with plain
+// read-modify-writes, one lane per base texel and round (an owner word per
+// cell elects it); the window is then flushed with global float atomics whose
+// lanes cover consecutive floats, and zeroed by the same pass, so it starts
+// every use empty.  A window covers the base texels' bounding box plus one
+// column and one row: the second corner of a footprint is always the next
+// cell (wrapping happens when the window is mapped back to texels; a corner
+// that coincides with the base texel at a clamped edge was folded onto it and
+// adds zero).  A footprint larger than the window is retried per half
+// wavefront, then per quarter; a quarter that still does not fit uses direct
+// global atomics.
+// The window holds 384 texels: with 256 texels 4 % of the layer-wavefronts at
+// 1024^2 views and 7 % at 800^2 did not fit (and fell back to 16 uncoalesced
+// atomics per lane); 384 texels take 30 KiB of LDS per block, so five blocks fit a CU,
+// and the register budget is held to that (about twenty resident wavefronts per CU hide
+// the gather latency of the forward recompute; four blocks per CU measured 10 % slower).
 template <int KMAX>
-__global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 3) k_shade_bwd(const vs_view* __restrict__ views, int n_views,
+__global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 2) k_shade_bwd(const vs_view* __restrict__ views, int n_views,
                                                    const int32_t* __restrict__ tile_view, int64_t n_tiles,
                                                    LayerTable L, TexTable X, const ProjVert* __restrict__ proj,
                                                    int64_t vpv, const uint64_t* __restrict__ vis,
@@ -340,6 +351,10 @@ __global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 3) k_shade_bwd(const vs_v
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   float* win = win_all[tid >> 6];
+  float4* wg = reinterpret_cast<float4*>(win);                     // [cell] RGBA sums
+  int32_t* owner = reinterpret_cast<int32_t*>(win + kWaveWin * 4);  // [cell]
+  // the window is zero before its first use; every flush leaves it zero again
+  for (int e = lane; e < kWaveWin; e += 64) wg[e] = make_float4(0.f, 0.f, 0.f, 0.f);
   const vs_view& V = views[c.v];
   const int W = V.cam.width, H = V.cam.height;
   const int64_t P = (int64_t)W * H;
@@ -354,7 +369,8 @@ __global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 3) k_shade_bwd(const vs_v
   for (int l = 0; l < KMAX; ++l) keys[l] = (l < k && c.valid) ? vrow[l * P] : kEmpty;
   // Kept per hit layer for the backward walk: T in front of it and the footprint; the
   // sample itself is re-read there (four texels, still cache resident), which keeps the
-  // register count, and so the number of resident wavefronts, up.
+  // register count, and so the number of resident wavefronts, up: keeping the samples
+  // instead costs either spills (at five blocks per CU) or a block per CU.
   float Tl[KMAX], fxs[KMAX], fys[KMAX];
   int32_t ij[KMAX];   // packed (j0 << 16 | i0); i1, j1 follow from them
   uint32_t hitmask = 0;
@@ -409,16 +425,17 @@ __global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 3) k_shade_bwd(const vs_v
     if (l >= k) continue;  // uniform
     const bool hit = (hitmask >> l) & 1u;
     if (!__any(hit)) continue;  // uniform per wavefront
+    const int32_t Wt = X.w[l], Ht = X.h[l];
     float v[16];
-    int32_t key = -1, i0 = 0, i1 = 0, j0 = 0, j1 = 0;
+    int32_t key = -1, i0 = 0, j0 = 0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) v[q] = 0.0f;
     if (hit) {
       i0 = ij[l] & 0xffff; j0 = ij[l] >> 16;
-      i1 = next_index(i0, X.w[l], wrap); j1 = next_index(j0, X.h[l], wrap);
       Foot f;
-      f.i0 = i0; f.i1 = i1; f.j0 = j0; f.j1 = j1; f.fx = fxs[l]; f.fy = fys[l];
-      const float4 smp = bilinear(X.tex[l], X.w[l], f);   // the same sample as the forward walk
+      f.i0 = i0; f.j0 = j0; f.i1 = next_index(i0, Wt, wrap); f.j1 = next_index(j0, Ht, wrap);
+      f.fx = fxs[l]; f.fy = fys[l];
+      const float4 smp = bilinear(X.tex[l], Wt, f);   // the same sample as the forward walk
       const float a = smp.w, Tv = Tl[l];
       const float aT = a * Tv;
       float d[4];
@@ -428,32 +445,35 @@ __global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 3) k_shade_bwd(const vs_v
       Sg = a * smp.y + (1.0f - a) * Sg;
       Sb = a * smp.z + (1.0f - a) * Sb;
       Pm *= (1.0f - a);
-      const float fx = f.fx, fy = f.fy, gx = 1.0f - fx, gy = 1.0f - fy;
+      const float fx = fxs[l], fy = fys[l], gx = 1.0f - fx, gy = 1.0f - fy;
       const float wq[4] = {gx * gy, fx * gy, gx * fy, fx * fy};
 #pragma unroll
       for (int n = 0; n < 4; ++n) {
 #pragma unroll
         for (int ch = 0; ch < 4; ++ch) v[n * 4 + ch] = wq[n] * d[ch];
       }
-      // clamped at the last column or row, corners coincide: fold them onto the base texel's
-      // row or column (the window skips the folded corners; the direct path adds zeros)
-      if (i1 == i0) {
+      key = j0 * Wt + i0;
+    }
+    // Clamped at the last column or row (or a texture one texel wide or high), corners
+    // coincide: fold them onto the base texel's row or column, so that the corner
+    // after it receives zero.  Uniform test: never taken for repeat-wrapped textures
+    // wider and higher than one texel.
+    if (wrap == kWrapClamp || Wt == 1 || Ht == 1) {
+      if (hit && next_index(i0, Wt, wrap) == i0) {
 #pragma unroll
         for (int ch = 0; ch < 4; ++ch) { v[ch] += v[4 + ch]; v[4 + ch] = 0.f; v[8 + ch] += v[12 + ch]; v[12 + ch] = 0.f; }
       }
-      if (j1 == j0) {
+      if (hit && next_index(j0, Ht, wrap) == j0) {
 #pragma unroll
         for (int ch = 0; ch < 4; ++ch) { v[ch] += v[8 + ch]; v[8 + ch] = 0.f; v[4 + ch] += v[12 + ch]; v[12 + ch] = 0.f; }
       }
-      key = j0 * X.w[l] + i0;
     }
-    // all lanes take part in the exchanges (uniform control flow here)
     merge_by_key<0>(key, v, lane);
     merge_by_key<1>(key, v, lane);
     if (kMergeX2) merge_by_key<2>(key, v, lane);
     const bool live_all = key >= 0;
+    bool direct = false;   // a quarter wavefront whose footprint did not fit: direct atomics below
     float* G = X.grad[l];
-    const int32_t Wt = X.w[l], Ht = X.h[l];
     // A footprint larger than the window is retried per half wavefront (lanes
     // 0-31, then 32-63), a half that does not fit per quarter (16 lanes: an
     // 8 x 2 pixel block); a quarter that still does not fit uses direct atomics.
@@ -461,40 +481,31 @@ __global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 3) k_shade_bwd(const vs_v
       const bool live = live_all && (npass == 1 || (lane >> (npass == 2 ? 5 : 4)) == pass);
       const uint64_t live_bits = __ballot(live);
       if (live_bits == 0) continue;
-      // window relative to the base texel of the first surviving lane, wrap-aware; corners add +1
+      // window relative to the base texel of the first surviving lane, wrap-aware
       const int first = __builtin_ctzll(live_bits);
       const int32_t ri = __builtin_amdgcn_readlane(i0, first), rj = __builtin_amdgcn_readlane(j0, first);
-      int32_t di0 = 0, di1 = 0, dj0 = 0, dj1 = 0;
-      if (live) {
-        di0 = rel_index(i0, ri, Wt, wrap); di1 = rel_index(i1, ri, Wt, wrap);
-        dj0 = rel_index(j0, rj, Ht, wrap); dj1 = rel_index(j1, rj, Ht, wrap);
-      }
-      const int32_t dmin_i = wave_min(live ? min(di0, di1) : INT32_MAX);
-      const int32_t dmax_i = wave_max(live ? max(di0, di1) : INT32_MIN);
-      const int32_t dmin_j = wave_min(live ? min(dj0, dj1) : INT32_MAX);
-      const int32_t dmax_j = wave_max(live ? max(dj0, dj1) : INT32_MIN);
+      const int32_t di = live ? rel_index(i0, ri, Wt, wrap) : 0;
+      const int32_t dj = live ? rel_index(j0, rj, Ht, wrap) : 0;
+      const int32_t dmin_i = wave_min(live ? di : INT32_MAX);
+      const int32_t dmax_i = wave_max(live ? di : INT32_MIN) + 1;
+      const int32_t dmin_j = wave_min(live ? dj : INT32_MAX);
+      const int32_t dmax_j = wave_max(live ? dj : INT32_MIN) + 1;
       const int32_t ww = dmax_i - dmin_i + 1, wh = dmax_j - dmin_j + 1;
       if (ww * wh <= kWaveWin) {
-        float4* wg = reinterpret_cast<float4*>(win);                     // [cell] RGBA sums
-        int32_t* owner = reinterpret_cast<int32_t*>(win + kWaveWin * 4);  // [cell]
-        const int32_t ncell = ww * wh;
-        for (int e = lane; e < ncell; e += 64) wg[e] = make_float4(0.f, 0.f, 0.f, 0.f);
-        const int32_t x0 = di0 - dmin_i, x1 = di1 - dmin_i, y0 = dj0 - dmin_j, y1 = dj1 - dmin_j;
-        const int32_t cells[4] = {y0 * ww + x0, y0 * ww + x1, y1 * ww + x0, y1 * ww + x1};
-        // Corners that coincide (clamped at the last column or row) were folded onto the base
-        // texel's, so for each corner distinct base texels give distinct cells.  One owner word
-        // per base cell elects one lane per base texel and round; the winners then apply the four
+        const int32_t c00 = (dj - dmin_j) * ww + (di - dmin_i);
+        const int32_t cells[4] = {c00, c00 + 1, c00 + ww, c00 + ww + 1};
+        // For each corner, distinct base texels give distinct cells.  One owner word per
+        // base cell elects one lane per base texel and round; the winners then apply the four
         // corners' read-modify-writes one corner at a time.  A wave's LDS instructions complete
         // in order, so no atomics are needed; lanes that lost (equal base texel) retry.
-        const uint32_t skip = (i1 == i0 ? 0xau : 0u) | (j1 == j0 ? 0xcu : 0u);
         bool pend = live;
         while (__any(pend)) {
-          if (pend) owner[cells[0]] = lane;
+          if (pend) owner[c00] = lane;
           wave_lds_sync();
-          const bool mine = pend && owner[cells[0]] == lane;
+          const bool mine = pend && owner[c00] == lane;
 #pragma unroll
           for (int n = 0; n < 4; ++n) {
-            if (mine && !((skip >> n) & 1u)) {
+            if (mine) {
               float4 acc = wg[cells[n]];
               acc.x += v[n * 4 + 0]; acc.y += v[n * 4 + 1]; acc.z += v[n * 4 + 2]; acc.w += v[n * 4 + 3];
               wg[cells[n]] = acc;
@@ -504,32 +515,37 @@ __global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 3) k_shade_bwd(const vs_v
           pend = pend && !mine;
         }
         wave_lds_sync();
-        // flush: consecutive lanes take consecutive floats of a window row (so each atomic
-        // instruction covers whole texture row segments), several rows per instruction when
-        // rows are short.  Lane -> (row offset rr, float cc0); the quotients are of small
-        // integers, exact in correctly rounded FP32 division.
+        // flush and zero: consecutive lanes take consecutive floats of a window row (so each
+        // atomic instruction covers whole texture row segments), several rows per instruction
+        // when rows are short.  Lane -> (row offset rr, float cc0): rr = floor(lane / row) as
+        // (lane m) >> 16 with m in [2^16 / row, 2^16 / row + 1], exact for lane < 64, row <= 64.
         const int32_t row = ww * 4;
-        const int32_t R = row >= 64 ? 1 : (int32_t)(64.0f / (float)row);
-        const int32_t rr = row >= 64 ? 0 : (int32_t)((float)lane / (float)row);
+        const int32_t R = row >= 64 ? 1 : 64 / row;                       // uniform (scalar)
+        const uint32_t m = row >= 64 ? 0u : 65536u / (uint32_t)row + 1u;  // uniform (scalar)
+        const int32_t rr = row >= 64 ? 0 : (int32_t)(((uint32_t)lane * m) >> 16);
         const int32_t cc0 = row >= 64 ? lane : lane - rr * row;
-        const bool flat = ri + dmin_i >= 0 && ri + dmax_i < Wt && rj + dmin_j >= 0 && rj + dmax_j < Ht;
+        const int32_t bi = ri + dmin_i, bj = rj + dmin_j;   // texel of window cell (0, 0), unwrapped
+        const bool flat = bi >= 0 && bi + ww <= Wt && bj >= 0 && bj + wh <= Ht;
         if (rr < R) {
           if (flat) {   // the window does not wrap: plain strided addresses
-            float* gbase = G + ((int64_t)(rj + dmin_j) * Wt + (ri + dmin_i)) * 4;
+            float* gbase = G + ((int64_t)bj * Wt + bi) * 4;
             const int64_t gstride = (int64_t)Wt * 4;
             for (int32_t y = rr; y < wh; y += R)
-              for (int32_t c = cc0; c < row; c += 64) {
-                const float val = win[y * row + c];
-                if (val != 0.0f) unsafeAtomicAdd(gbase + y * gstride + c, val);
+              for (int32_t cc = cc0; cc < row; cc += 64) {
+                const float val = win[y * row + cc];
+                win[y * row + cc] = 0.0f;
+                if (val != 0.0f) unsafeAtomicAdd(gbase + y * gstride + cc, val);
               }
           } else {
+            // wrapped (repeat) or outside the texture (clamp: only zeros land there)
             for (int32_t y = rr; y < wh; y += R) {
               const int32_t tj = abs_index(rj, dmin_j + y, Ht, wrap);
-              for (int32_t c = cc0; c < row; c += 64) {
-                const float val = win[y * row + c];
+              for (int32_t cc = cc0; cc < row; cc += 64) {
+                const float val = win[y * row + cc];
+                win[y * row + cc] = 0.0f;
                 if (val != 0.0f) {
-                  const int32_t ti = abs_index(ri, dmin_i + (c >> 2), Wt, wrap);
-                  unsafeAtomicAdd(G + ((int64_t)tj * Wt + ti) * 4 + (c & 3), val);
+                  const int32_t ti = abs_index(ri, dmin_i + (cc >> 2), Wt, wrap);
+                  unsafeAtomicAdd(G + ((int64_t)tj * Wt + ti) * 4 + (cc & 3), val);
                 }
               }
             }
@@ -542,7 +558,15 @@ __global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 3) k_shade_bwd(const vs_v
       } else if (npass == 2) {
         npass = 4;      // this half again as two quarters, and the halves after it as quarters
         pass = 2 * pass - 1;
-      } else if (live) {
+      } else {
+        direct = direct || live;
+      }
+    }
+    // rare (minified texels, pole fans): kept out of the passes above so that its
+    // address arithmetic is not hoisted into the common path
+    if (__any(direct)) {
+      if (direct) {
+        const int32_t i1 = next_index(i0, Wt, wrap), j1 = next_index(j0, Ht, wrap);
         const int64_t q[4] = {((int64_t)j0 * Wt + i0) * 4, ((int64_t)j0 * Wt + i1) * 4,
                               ((int64_t)j1 * Wt + i0) * 4, ((int64_t)j1 * Wt + i1) * 4};
 #pragma unroll
