@@ -51,33 +51,93 @@ def byte_model(scene, n_views, P_v, U, fused=True):
     }
 
 
-def counter_traffic(workload: str, kernel: str):
-    """HBM bytes per launch of a kernel in a workload from the committed rocprofv3 counter summaries, if the
-    kernel sources are still the ones the counters were taken on."""
+def csrc_sha256() -> str:
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2409_02482_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def profile_record(name: str, workload: str, kernel: str):
+    """Record ``<workload>/<kernel>`` of the committed summary profiles/<name>, if the kernel sources are still
+    the ones the counters were taken on (else None)."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     try:
         rec = json.load(open(path)).get(f"{workload}/{kernel}")
     except Exception:
         return None
-    if not rec:
+    if not rec or rec.get("csrc_sha256") != csrc_sha256():
         return None
-    h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2409_02482_amd", "csrc"))):
-        h.update(open(os.path.join(ROOT, "paper_2409_02482_amd", "csrc", f), "rb").read())
-    if rec.get("csrc_sha256") != h.hexdigest():
-        return None
-    return rec.get("bytes_per_launch")
+    return rec
 
 
-def cpu_baseline(scene, n_threads, per_thread=3):
-    """The oracle as it stands, views spread over threads (ctypes releases the GIL)."""
+def counter_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of a kernel in a workload from the committed rocprofv3 counter summaries, if the
+    kernel sources are still the ones the counters were taken on."""
+    rec = profile_record("traffic.json", workload, kernel)
+    return None if rec is None else rec.get("bytes_per_launch")
+
+
+def issue_rate(workload: str, kernel: str):
+    """VALU issue share of a kernel from the committed SQ counter summary (same source rule as the traffic):
+    SQ_INSTS_VALU x 4 cycles / (kernel duration x 2.4 GHz x 1024 SIMDs), the share of the chip's VALU issue
+    cycles the kernel's instructions occupy at the nominal clock."""
+    rec = profile_record("sq_counters.json", workload, kernel)
+    if rec is None:
+        return None
+    return {"valu_insts_per_wave": rec["valu_insts_per_wave"], "valu_issue_frac": rec["valu_issue_frac"],
+            "formula": "SQ_INSTS_VALU*4/(duration*2.4e9*1024)"}
+
+
+def host_threads() -> int:
+    """Host cores this process may use, capped at 16 (the CPU share of one GPU on the benchmark hosts)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def measured_copy_peak(mib=1024, reps=5):
+    """Best device-to-device copy rate (read + write bytes per second, GB/s) of mib MiB, timed with events."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    best = 1e30
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    return 2.0 * n * 4 / (best * 1e-3) / 1e9
+
+
+def cpu_baseline(scene, n_threads, per_thread=2):
+    """The oracle as it stands: one view timed step by step on one thread, then views spread over n_threads
+    threads (ctypes releases the GIL)."""
     import concurrent.futures as cf
 
     import oracle as O
-    cams = scene.cameras[:n_threads * per_thread]
+    O.build(force=False)
+    cam = scene.cameras[0]
+    t0 = time.perf_counter()
+    vis = O.raster_layers(scene.layers, cam)
+    t1 = time.perf_counter()
+    O.shade(scene.layers, scene.textures, cam, vis)
+    t2 = time.perf_counter()
+    O.backward(scene.layers, scene.textures, cam, vis, target=scene.targets[0])
+    t3 = time.perf_counter()
+    single = {"raster_s": t1 - t0, "shade_s": t2 - t1, "backward_s": t3 - t2, "total_s": t3 - t0,
+              "px_layers": int((vis != np.uint64(0xFFFFFFFFFFFFFFFF)).sum())}
+    cams = scene.cameras[1:1 + n_threads * per_thread]
 
     def one(v):
         cam = scene.cameras[v]
@@ -86,14 +146,16 @@ def cpu_baseline(scene, n_threads, per_thread=3):
         O.backward(scene.layers, scene.textures, cam, vis, target=scene.targets[v])
         return int((vis != np.uint64(0xFFFFFFFFFFFFFFFF)).sum())
 
-    O.build(force=False)
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(n_threads) as ex:
-        covered = sum(ex.map(one, range(len(cams))))
+        covered = sum(ex.map(one, range(1, 1 + len(cams))))
     dt = time.perf_counter() - t0
     return {"value": covered / dt, "unit": "px*layers/s", "cores": n_threads, "kind": "oracle",
             "sample": f"{len(cams)} of the 64 views (full 1024x1024, k=7), raster+shade+adjoint (L2), "
-                      f"{per_thread} views per thread on {n_threads} threads, {dt:.1f} s wall"}
+                      f"{per_thread} views per thread on {n_threads} threads (the host cores available, at most "
+                      f"16), {dt:.1f} s wall",
+            "single_thread_per_view": single,
+            "single_thread_px_layers_per_s": single["px_layers"] / single["total_s"]}
 
 
 SH_METRIC = ("shaded px·layers/s fwd, baked SH degree 3 (k=7, 1024², 64 views, 8-bit 2048² mixed-resolution "
@@ -133,6 +195,83 @@ def calibration_copy(mib):
     torch.cuda.synchronize()
     log(f"[bench] calibration copy of {mib} MiB done")
     del a, b
+
+
+def calibration_gather(mib):
+    """Counter reference of a gather: mib MiB read once in a random order of 64-byte rows (index_select)
+    and written contiguously, plus 8 bytes of index per row."""
+    import torch
+    rows = mib * (1 << 20) // 64
+    a = torch.ones(rows, 16, dtype=torch.float32, device="cuda")
+    idx = torch.randperm(rows, device="cuda", generator=torch.Generator(device="cuda").manual_seed(3))
+    torch.cuda.synchronize()
+    b = torch.index_select(a, 0, idx)
+    torch.cuda.synchronize()
+    log(f"[bench] calibration gather of {mib} MiB ({rows} rows of 64 B) done")
+    del a, b, idx
+
+
+def small_configs(P, S, torch):
+    """Configurations 1-3 (one view each): latency per step, shaded px*layers/s, triangles/s (sum of k T over
+    the raster phase) and the algorithmic-byte share of the HBM peak, all timed with events."""
+    out = {}
+    for cid, bwd in ((1, False), (2, False), (3, True)):
+        sc = S.make_config(cid)
+        k = sc.k
+        layers = P.Layers(sc.layers)
+        views = P.Views(sc.cameras)
+        tex = [torch.from_numpy(t).cuda() for t in sc.textures]
+        vis = torch.empty(k * views.total_pixels, dtype=torch.int64, device="cuda")
+        ws = P.alloc_workspace(layers, views)
+        img = torch.empty(views.total_pixels, 4, dtype=torch.float32, device="cuda")
+        grads = [torch.zeros_like(t) for t in tex]
+        tgt = (torch.from_numpy(sc.targets[0].reshape(-1, 4)).cuda() if bwd else None)
+        ones = torch.ones(views.total_pixels, 4, dtype=torch.float32, device="cuda")
+
+        def step():
+            P.raster(layers, views, vis, ws)
+            if bwd:
+                P.render_backward(layers, tex, views, vis, ws, grad_tex=grads, target=tgt, out=img,
+                                  loss_scale=1.0 / views.total_pixels)
+            else:
+                P.render(layers, tex, views, vis, ws, out=img)
+
+        for _ in range(3):
+            step()
+        # texels a forward read touches = texels a unit upstream gradient reaches
+        g1 = P.render_backward(layers, tex, views, vis, ws, grad_rgba=ones)
+        U = [int((g != 0).any(dim=-1).sum().item()) for g in g1]
+        covered = int((vis != -1).sum().item())
+        reps = 20
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+        for r in range(reps):
+            ev[r][0].record()
+            P.raster(layers, views, vis, ws)
+            ev[r][1].record()
+            if bwd:
+                P.render_backward(layers, tex, views, vis, ws, grad_tex=grads, target=tgt, out=img,
+                                  loss_scale=1.0 / views.total_pixels)
+            else:
+                P.render(layers, tex, views, vis, ws, out=img)
+            ev[r][2].record()
+        torch.cuda.synchronize()
+        ph = np.array([[ev[r][0].elapsed_time(ev[r][1]), ev[r][1].elapsed_time(ev[r][2])] for r in range(reps)])
+        ms_r, ms_s = np.median(ph[:, 0]), np.median(ph[:, 1])
+        ms = ms_r + ms_s
+        bm = byte_model(sc, 1, views.total_pixels, U, fused=True)
+        alg = bm["raster"] + (bm["shade_bwd"] if bwd else
+                              8 * k * views.total_pixels + 16 * views.total_pixels + sum(16 * u for u in U))
+        out[f"cfg{cid}"] = {
+            "what": ("k=3 icosphere shells, 256^2, forward" if cid == 1 else
+                     "k=7 displaced shells (101,760 tris/layer), 1024^2, forward" if cid == 2 else
+                     "k=7 displaced shells, 1024^2, forward + adjoint of the RGB L2 loss"),
+            "latency_ms": float(ms), "raster_ms": float(ms_r), "shade_ms": float(ms_s),
+            "px_layers_per_s": covered / (ms * 1e-3), "covered_px_layers": covered,
+            "triangles_per_s": sum(m.n_tri for m in sc.layers) / (ms_r * 1e-3),
+            "alg_bytes": int(alg), "alg_frac_of_peak": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        log(f"[bench] cfg{cid}: {ms:.3f} ms")
+        del vis, ws, img, grads, tex, g1
+    return out
 
 
 def run_sh(args):
@@ -201,7 +340,7 @@ def run_sh(args):
     }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
-        n = max(1, min(args.cpu_threads, os.cpu_count() or 1, nv))
+        n = max(1, min(args.cpu_threads or host_threads(), nv))
         res["cpu_baseline"] = sh_cpu_baseline(scene, sh, n)
     print(json.dumps(res), flush=True)
 
@@ -508,7 +647,7 @@ def run_fit(args):
     }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
-        n = max(1, min(args.cpu_threads, os.cpu_count() or 1))
+        n = args.cpu_threads or host_threads()
         # seeded targets (the CPU timing takes no GPU output); 64 views keep the sample at seconds of CPU work
         tg = S.uniform_targets(5, sc.cameras[:64 if wl != "ngp" else 32])
         if wl == "ngp":
@@ -527,7 +666,8 @@ def main():
     ap.add_argument("--res", type=int, default=1024)
     ap.add_argument("--bin", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-threads", type=int, default=8)
+    ap.add_argument("--cpu-threads", type=int, default=0, help="0: the host cores available (at most 16)")
+    ap.add_argument("--no-small-configs", action="store_true", help="skip the configuration 1-3 measurements")
     ap.add_argument("--unfused", action="store_true", help="separate forward shading pass before the adjoint")
     ap.add_argument("--workload", default="metric", choices=["metric", "cfg4", "sh", "ksdf", "fit", "fit_l1q", "ngp"],
                     help="metric: k=7, 64 views at 1024^2; cfg4: k=9, 299,208 tris/layer, 64 mixed-size views; "
@@ -539,6 +679,8 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="pick the raster bin size with vs_autotune")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of this many MiB first (HBM counter calibration)")
+    ap.add_argument("--calibrate-gather", type=int, default=0, metavar="MIB",
+                    help="run one gather of this many MiB in 64-byte rows first (second counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this benchmark measures one GPU only; --gpus must be 1 (views would shard across GPUs, "
@@ -547,6 +689,8 @@ def main():
 
     if args.calibrate_copy:
         calibration_copy(args.calibrate_copy)
+    if args.calibrate_gather:
+        calibration_gather(args.calibrate_gather)
     if args.workload == "sh":
         return run_sh(args)
     if args.workload == "ksdf":
@@ -681,13 +825,20 @@ def main():
         "alg_bytes_per_step": int(sum(bm[n] for n in names)),
         "alg_frac_of_peak_step": sum(bm[n] for n in names) / (ms_wall * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(args.workload, dom_name)},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(args.workload, dom_name),
+                     "issue": issue_rate(args.workload, dom_name)},
     }
     if graph is not None:
         res["graph_ms_per_step"] = graph_ms
+    log("[bench] copy peak")
+    copy = measured_copy_peak()
+    res["roofline"]["measured_copy_peak"] = copy
+    res["roofline"]["frac_of_measured_copy"] = achieved / copy
+    if args.workload == "metric" and not args.no_small_configs:
+        res["configs"] = small_configs(P, S, torch)
     if not args.no_cpu_baseline and args.workload == "metric":
         log("[bench] cpu baseline (oracle)")
-        n = max(1, min(args.cpu_threads, os.cpu_count() or 1, nv))
+        n = args.cpu_threads or host_threads()
         res["cpu_baseline"] = cpu_baseline(scene, n)
     print(json.dumps(res), flush=True)
 
