@@ -101,10 +101,12 @@ vs_status build_layers(const vs_mesh* layers, int32_t k, vs::LayerTable& L) {
     L.n_tri[l] = m.n_tri;
     L.vert_off[l + 1] = L.vert_off[l] + m.n_vert;
     L.tri_off[l + 1] = L.tri_off[l] + m.n_tri;
+    L.tri_pad[l + 1] = L.tri_pad[l] + ((int64_t)m.n_tri + 63) / 64 * 64;
   }
   for (int l = k + 1; l <= VS_MAX_LAYERS; ++l) {
     L.vert_off[l] = L.vert_off[k];
     L.tri_off[l] = L.tri_off[k];
+    L.tri_pad[l] = L.tri_pad[k];
   }
   return VS_OK;
 }
@@ -276,7 +278,7 @@ vs_status vs_raster_layers(const vs_mesh* layers, int32_t k, const vs_views* vie
                      bin_view, lay.n_tiles_bin, slot);
   hipLaunchKernelGGL(vs::k_fill_u32, dim3(fill_grid), dim3(256), 0, s, count, lay.n_bins, 0u);
   hipLaunchKernelGGL(vs::k_fill_u32, dim3(fill_grid), dim3(256), 0, s, cursor, 2 * lay.n_bins, 0u);
-  const unsigned bin_blocks = (unsigned)vs::bin_grid_blocks(ntri, nv);
+  const unsigned bin_blocks = (unsigned)vs::bin_grid_blocks(L.tri_pad[k], nv);
   hipLaunchKernelGGL(vs::k_bin_count, dim3(bin_blocks), dim3(256), 0, s, views->dev, nv, L,
                      (const vs::ProjVert*)proj, vpv, B, slot, count, spans, status);
   hipLaunchKernelGGL(vs::k_scan_local, dim3((unsigned)lay.n_partial), dim3(256), 0, s, (const uint32_t*)count,

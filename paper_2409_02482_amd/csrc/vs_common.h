@@ -27,6 +27,7 @@ struct LayerTable {
   int32_t n_tri[kMaxLayers];
   int64_t vert_off[kMaxLayers + 1];  // prefix of n_vert: layer l's vertices in one view's projected block
   int64_t tri_off[kMaxLayers + 1];   // prefix of n_tri
+  int64_t tri_pad[kMaxLayers + 1];   // prefix of n_tri rounded up to 64: one layer per wavefront in per-triangle launches
   int32_t k;
 };
 
@@ -90,6 +91,17 @@ __device__ inline ProjVert project_vertex(const float* p, const vs_camera& c) {
   return o;
 }
 
+// One projected vertex as a single 16-byte load (so that the three vertices of
+// a triangle are requested together, not field by field behind the checks).
+__device__ inline ProjVert load_proj(const ProjVert* p) {
+  const int4 r = *reinterpret_cast<const int4*>(p);
+  ProjVert o;
+  o.X = r.x;
+  o.Y = r.y;
+  o.w = __hiloint2double(r.w, r.z);
+  return o;
+}
+
 // ------------------------------------------------------------------ step 2
 // Triangle after orientation normalisation.  Screen coordinates are integers
 // below 2^25 in magnitude, so every edge-function value (< 2^51) is exact in
@@ -112,19 +124,24 @@ __device__ inline bool top_left(double px, double py, double qx, double qy) {
 }
 
 // ids are the three vertex ids of the triangle; pv the projected vertices of
-// its layer in this view.
+// its layer in this view.  Branch-free until the status is chosen: the ids are
+// read as one 12-byte load and the three vertices as three 16-byte loads that
+// are all in flight together (an out-of-range id reads vertex 0 instead and
+// reports kTriBadIndex).
 __device__ inline int setup_triangle(const int32_t* ids, int32_t n_vert, const ProjVert* pv, TriSetup& T) {
-  int32_t id[3] = {ids[0], ids[1], ids[2]};
-  if ((uint32_t)id[0] >= (uint32_t)n_vert || (uint32_t)id[1] >= (uint32_t)n_vert ||
-      (uint32_t)id[2] >= (uint32_t)n_vert)
-    return kTriBadIndex;
-  ProjVert a = pv[id[0]], b = pv[id[1]], c = pv[id[2]];
-  if (a.X == kInvalidX || b.X == kInvalidX || c.X == kInvalidX) return kTriInvalid;
+  const int3 tid3 = *reinterpret_cast<const int3*>(ids);
+  int32_t id[3] = {tid3.x, tid3.y, tid3.z};
+  const bool bad = (uint32_t)id[0] >= (uint32_t)n_vert || (uint32_t)id[1] >= (uint32_t)n_vert ||
+                   (uint32_t)id[2] >= (uint32_t)n_vert;
+  ProjVert a = load_proj(pv + (bad ? 0 : id[0]));
+  ProjVert b = load_proj(pv + (bad ? 0 : id[1]));
+  ProjVert c = load_proj(pv + (bad ? 0 : id[2]));
+  const bool invalid = a.X == kInvalidX || b.X == kInvalidX || c.X == kInvalidX;
   double area2 = ((double)b.X - (double)a.X) * ((double)c.Y - (double)a.Y) -
                  ((double)b.Y - (double)a.Y) * ((double)c.X - (double)a.X);
-  if (area2 == 0.0) return kTriDegenerate;
-  T.orig_sign = area2 < 0.0 ? -1 : 1;
-  if (area2 < 0.0) {
+  const bool neg = area2 < 0.0;
+  T.orig_sign = neg ? -1 : 1;
+  if (neg) {   // selects, not a branch around loads: the vertices are already in registers
     const ProjVert t = b; b = c; c = t;
     const int32_t ti = id[1]; id[1] = id[2]; id[2] = ti;
     area2 = -area2;
@@ -137,7 +154,7 @@ __device__ inline int setup_triangle(const int32_t* ids, int32_t n_vert, const P
   T.th[0] = top_left(T.X[1], T.Y[1], T.X[2], T.Y[2]) ? 0.0 : 1.0;
   T.th[1] = top_left(T.X[2], T.Y[2], T.X[0], T.Y[0]) ? 0.0 : 1.0;
   T.th[2] = top_left(T.X[0], T.Y[0], T.X[1], T.Y[1]) ? 0.0 : 1.0;
-  return kTriOk;
+  return bad ? kTriBadIndex : invalid ? kTriInvalid : area2 == 0.0 ? kTriDegenerate : kTriOk;
 }
 
 // Edge functions at sample point (px, py) (1/256 px units):

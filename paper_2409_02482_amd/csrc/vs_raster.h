@@ -109,28 +109,34 @@ struct BinWork {
   int ntx;                  // tiles per row in this view
 };
 
-// Blocks of a count/scatter launch: per view, ceil(triangles of all layers / 256),
+// Blocks of a count/scatter launch: per view, ceil(padded triangles of all layers / 256)
+// (each layer's range rounded up to 64, so that a wavefront never spans two layers),
 // the total rounded up to a multiple of the XCD count.
-__host__ __device__ inline int64_t bin_grid_blocks(int64_t n_tri, int n_views) {
-  return ((n_tri + 255) / 256 * n_views + 7) / 8 * 8;
+__host__ __device__ inline int64_t bin_grid_blocks(int64_t n_tri_padded, int n_views) {
+  return ((n_tri_padded + 255) / 256 * n_views + 7) / 8 * 8;
 }
 
-// Which (view, layer, triangle) this thread of a count/scatter launch handles.
-// Blocks are dealt round-robin to the 8 XCDs; the remap gives each XCD a
-// contiguous range of (view, triangle block)s, so that triangles sharing
-// vertices share that XCD's L2.
+// Which (view, layer, triangle) this thread of a count/scatter launch handles; g is the
+// triangle's index over all layers of the view.  Blocks are dealt round-robin to the 8
+// XCDs; the remap gives each XCD a contiguous range of (view, triangle block)s, so that
+// triangles sharing vertices share that XCD's L2.  The layer is the same on every lane
+// of a wavefront, so its table entries are scalar loads.
 __device__ inline bool bin_thread(const LayerTable& L, int n_views, int& v, int& l, int32_t& t, int64_t& g) {
   const int k = L.k;
-  const int64_t per_view = (L.tri_off[k] + 255) / 256;
+  const int64_t per_view = (L.tri_pad[k] + 255) / 256;
   const int64_t chunk = (int64_t)gridDim.x / 8;
   const int64_t bid = ((int64_t)blockIdx.x % 8) * chunk + (int64_t)blockIdx.x / 8;
   v = (int)(bid / per_view);
   if (v >= n_views) return false;
-  g = (bid - (int64_t)v * per_view) * 256 + threadIdx.x;
-  if (g >= L.tri_off[k]) return false;
-  l = 0;
-  while (l + 1 < k && L.tri_off[l + 1] <= g) ++l;
-  t = (int32_t)(g - L.tri_off[l]);
+  const int64_t gp = (bid - (int64_t)v * per_view) * 256 + threadIdx.x;   // padded index
+  const int64_t gw = gp & ~(int64_t)63;                                   // the wavefront's first
+  int lw = 0;
+  while (lw + 1 < k && L.tri_pad[lw + 1] <= gw) ++lw;
+  l = __builtin_amdgcn_readfirstlane(lw);
+  if (gp >= L.tri_pad[k]) return false;
+  t = (int32_t)(gp - L.tri_pad[l]);
+  if (t >= L.n_tri[l]) return false;   // padding
+  g = L.tri_off[l] + t;
   return true;
 }
 
@@ -444,6 +450,13 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
       }
     }
   };
+  // The first two chunks of back-facing entries and their records are requested before the
+  // front-facing phase, so that their latency hides behind it.
+  const uint4* srec4 = reinterpret_cast<const uint4*>(srec);
+  const uint32_t cp0 = n_front + tid, cp1 = n_front + kRasterThreads + tid;
+  const int32_t pt0 = cp0 < n ? lst[cp0] : -1, pt1 = cp1 < n ? lst[cp1] : -1;
+  const uint4 pr0 = pt0 >= 0 ? srec4[pt0] : make_uint4(0u, 0u, 0u, 0u);
+  const uint4 pr1 = pt1 >= 0 ? srec4[pt1] : make_uint4(0u, 0u, 0u, 0u);
   // phase 1: front-facing entries (every entry of an overflowing bin, or with fragment counting)
   for (uint32_t c0 = 0; c0 < n_front; c0 += kRasterThreads) {
     const uint32_t c = c0 + tid;
@@ -461,16 +474,22 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
     // phase 2: each back-facing entry is tested from its record (box and depth bound) alone;
     // the ones that may lower a key are queued in LDS and drawn 256 at a time, so that the
     // skipped majority costs no vertex loads and leaves no idle lanes behind.
-    for (uint32_t c0 = n_front; c0 < n; c0 += kRasterThreads) {
+    for (uint32_t c0 = n_front, chunk = 0; c0 < n; c0 += kRasterThreads, ++chunk) {
       const uint32_t c = c0 + tid;
       bool keep = false;
       int32_t t = 0;
       if (c < n) {
-        t = lst[c];
-        const SpanRec r = srec[t];
+        uint4 r;
+        if (chunk < 2) {   // uniform
+          t = chunk == 0 ? pt0 : pt1;
+          r = chunk == 0 ? pr0 : pr1;
+        } else {
+          t = lst[c];
+          r = srec4[t];
+        }
         int i0, i1, j0, j1;
-        unpack_box(r.box, i0, i1, j0, j1);
-        const unsigned long long lb = ((unsigned long long)r.zlo << 32) | (uint32_t)t;
+        unpack_box((uint64_t)r.x | ((uint64_t)r.y << 32), i0, i1, j0, j1);
+        const unsigned long long lb = ((unsigned long long)r.z << 32) | (uint32_t)t;
         const int ci0 = max(i0, x0), ci1 = min(i1, x1), cj0 = max(j0, y0), cj1 = min(j1, y1);
         for (int sj = (cj0 - y0) / kSub; sj <= (cj1 - y0) / kSub; ++sj)
           for (int si = (ci0 - x0) / kSub; si <= (ci1 - x0) / kSub; ++si)
