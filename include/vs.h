@@ -150,14 +150,21 @@ typedef struct vs_raster_opts {
  *           VS_LOSS_L1: loss_scale * sum_p ||RGB_p - target_p||_1  (the
  *                       paper's texturing loss, Sec. 4.3; gradient sign(.),
  *                       0 at a tie)
- * loss_scale: multiplies the fused loss (e.g. 1/number of scalars). */
+ * loss_scale: multiplies the fused loss (e.g. 1/number of scalars).
+ * flags:  VS_SHADE_COUNT_PATHS makes vs_render_backward count, in the status
+ *         block, how each wavefront's texture-gradient scatter was done per
+ *         layer: through one LDS window for the whole wavefront, per half or
+ *         per quarter wavefront (footprints too large for one window), or by
+ *         direct atomics (a quarter still too large); costs a few atomics. */
 enum { VS_LOSS_L2 = 0, VS_LOSS_L1 = 1 };
+#define VS_SHADE_COUNT_PATHS 1
 typedef struct vs_shade_opts {
   float eps_T;
   int32_t wrap;
   const float* target;
   float loss_scale;
   int32_t loss;
+  int32_t flags;
 } vs_shade_opts;
 
 /* Status block counters (vs_read_status). */
@@ -168,7 +175,11 @@ enum {
   VS_STAT_FRAGMENTS = 3,        /* covered (triangle, pixel) pairs tested by the raster */
   VS_STAT_BAD_KEY = 4,          /* visibility keys naming a triangle id >= n_tri */
   VS_STAT_BIN_OVERFLOW = 5,     /* bins whose triangle list exceeded the workspace (still exact, slower) */
-  VS_STAT_COUNT = 8
+  VS_STAT_SCATTER_WAVE = 6,     /* with VS_SHADE_COUNT_PATHS: layer-wavefronts scattered through one window */
+  VS_STAT_SCATTER_HALF = 7,     /*   ... half wavefronts scattered through a window */
+  VS_STAT_SCATTER_QUARTER = 8,  /*   ... quarter wavefronts scattered through a window */
+  VS_STAT_SCATTER_DIRECT = 9,   /*   ... quarter wavefronts scattered by direct atomics */
+  VS_STAT_COUNT = 10
 };
 
 /* Library version string. */

@@ -21,8 +21,9 @@ VS_EMPTY = 0xFFFFFFFFFFFFFFFF
 VS_RASTER_COUNT_FRAGMENTS = 1
 VS_RASTER_DIRECT = 2
 STAT_NAMES = ["culled_invalid", "culled_degenerate", "bad_index", "fragments", "bad_key", "bin_overflow",
-              "reserved6", "reserved7"]
-VS_STAT_COUNT = 8
+              "scatter_wave", "scatter_half", "scatter_quarter", "scatter_direct"]
+VS_STAT_COUNT = 10
+VS_SHADE_COUNT_PATHS = 1
 VS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
@@ -56,7 +57,8 @@ class VsAdamOpts(ctypes.Structure):
 
 
 class VsShadeOpts(ctypes.Structure):
-    _fields_ = [("eps_T", c_f32), ("wrap", c_i32), ("target", c_vp), ("loss_scale", c_f32), ("loss", c_i32)]
+    _fields_ = [("eps_T", c_f32), ("wrap", c_i32), ("target", c_vp), ("loss_scale", c_f32), ("loss", c_i32),
+                ("flags", c_i32)]
 
 
 VS_LOSS = {"l2": 0, "l1": 1}

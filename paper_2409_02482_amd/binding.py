@@ -178,9 +178,9 @@ def raster(layers: Layers, views: Views, vis: Optional[torch.Tensor] = None, ws:
     return vis, ws
 
 
-def _shade_opts(eps_T=0.0, wrap=0, target=None, loss_scale=1.0, loss="l2"):
+def _shade_opts(eps_T=0.0, wrap=0, target=None, loss_scale=1.0, loss="l2", count_paths=False):
     return C.VsShadeOpts(float(eps_T), int(wrap), 0 if target is None else target.data_ptr(), float(loss_scale),
-                         C.VS_LOSS[loss])
+                         C.VS_LOSS[loss], C.VS_SHADE_COUNT_PATHS if count_paths else 0)
 
 
 def render(layers: Layers, textures, views: Views, vis: torch.Tensor, ws: torch.Tensor,
@@ -269,7 +269,7 @@ def render_backward(layers: Layers, textures, views: Views, vis: torch.Tensor, w
                     grad_rgba: Optional[torch.Tensor] = None, grad_tex: Optional[List[torch.Tensor]] = None,
                     target: Optional[torch.Tensor] = None, loss_scale: float = 1.0,
                     out: Optional[torch.Tensor] = None, sse: Optional[torch.Tensor] = None, wrap: int = 0,
-                    loss: str = "l2", eps_T: float = 0.0,
+                    loss: str = "l2", eps_T: float = 0.0, count_paths: bool = False,
                     stream=None) -> List[torch.Tensor]:
     """vs_render_backward: accumulates dL/dtexture into grad_tex (zeros if None) and returns it.
     With eps_T > 0 the layer walk stops where vs_render's does (the gradient of that image)."""
@@ -300,7 +300,7 @@ def render_backward(layers: Layers, textures, views: Views, vis: torch.Tensor, w
     if sse is not None:
         _dev(sse, torch.float64, "sse")
     gp = (ctypes.c_void_p * layers.k)(*[g.data_ptr() for g in grad_tex])
-    opts = _shade_opts(eps_T, wrap, target, loss_scale, loss)
+    opts = _shade_opts(eps_T, wrap, target, loss_scale, loss, count_paths)
     C.check(C.load().vs_render_backward(
         ctypes.addressof(layers.c), ctypes.addressof(tex), layers.k, ctypes.byref(views.c), vis.data_ptr(),
         ws.data_ptr(), ws.numel(), None if grad_rgba is None else grad_rgba.data_ptr(), ctypes.addressof(gp),

@@ -500,6 +500,8 @@ vs_status vs_render_backward(const vs_mesh* layers, const vs_texture* tex, int32
   if (loss != VS_LOSS_L2 && loss != VS_LOSS_L1) return fail(VS_ERR_UNSUPPORTED, "loss = %d", loss);
   const float eps = opts ? opts->eps_T : 0.0f;
   if (!(eps >= 0.0f && eps < 1.0f)) return fail(VS_ERR_ARG, "eps_T must be in [0, 1)");
+  const int sflags = opts ? opts->flags : 0;
+  if (sflags & ~VS_SHADE_COUNT_PATHS) return fail(VS_ERR_UNSUPPORTED, "shade flags = %d", sflags);
   const vs::WsLayout lay = ws_layout(L, views, 0);
   if ((st = check_ws(ws, ws_bytes, lay.proj + (size_t)views->n_views * L.vert_off[k] * sizeof(vs::ProjVert))))
     return st;
@@ -509,11 +511,12 @@ vs_status vs_render_backward(const vs_mesh* layers, const vs_texture* tex, int32
   hipStream_t s = (hipStream_t)stream;
   const int64_t tiles = total_tiles(views, vs::kShadeTileSlot);
   const auto* tile_view = (const int32_t*)(base + lay.tile_view);
+  const int count_paths = sflags & VS_SHADE_COUNT_PATHS;
   auto launch = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3((unsigned)vs::shade_grid_blocks(tiles)), dim3(256), 0, s, views->dev,
                        views->n_views, tile_view, tiles, L, X, proj,
                        L.vert_off[k], vis, (const float4*)grad_rgba, (const float4*)target, scale, loss,
-                       (float4*)out_rgba, target ? sse : nullptr, wrap, eps, status);
+                       (float4*)out_rgba, target ? sse : nullptr, wrap, eps, status, count_paths);
   };
   // per-layer state lives in registers, so the common layer counts get their own instantiation
   if (k <= 4) launch(vs::k_shade_bwd<4>);
@@ -604,7 +607,8 @@ extern "C" vs_status vs_autotune(const vs_mesh* layers, int32_t k, const vs_view
   unsigned long long ref_sum = 0;
   bool have_ref = false;
   const int64_t n_slots = (int64_t)k * views->host[views->n_views].pix_offset;
-  auto* sum_dev = (unsigned long long*)((char*)ws + 7 * sizeof(unsigned long long));  // status slot 7
+  // checksum scratch: the last 8 bytes of the 256-byte status slot (beyond the VS_STAT_COUNT counters)
+  auto* sum_dev = (unsigned long long*)((char*)ws + 31 * sizeof(unsigned long long));
   vs_status result = VS_OK;
   for (int ci = 0; ci < 4 && result == VS_OK; ++ci) {
     vs_raster_opts o = *inout;

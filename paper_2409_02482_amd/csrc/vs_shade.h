@@ -342,7 +342,8 @@ __global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 2) k_shade_bwd(const vs_v
                                                    const float4* __restrict__ target, float loss_scale,
                                                    int loss,
                                                    float4* __restrict__ out, double* __restrict__ sse, int wrap,
-                                                   float eps_T, unsigned long long* __restrict__ status) {
+                                                   float eps_T, unsigned long long* __restrict__ status,
+                                                   int count_paths) {
 #pragma clang fp contract(fast)
   __shared__ __align__(16) float win_all[4][kWaveWin * 5];   // per wave: RGBA sums, then the owner words
   __shared__ double sred[4];
@@ -420,6 +421,7 @@ __global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 2) k_shade_bwd(const vs_v
     if (out) out[gp] = make_float4(Cr, Cg, Cb, 1.0f - T);
   }
   float Sr = 0.f, Sg = 0.f, Sb = 0.f, Pm = 1.0f;
+  uint32_t n_path[4] = {0u, 0u, 0u, 0u};   // wavefront-uniform: window per wave / half / quarter, direct
 #pragma unroll
   for (int l = KMAX - 1; l >= 0; --l) {
     if (l >= k) continue;  // uniform
@@ -492,6 +494,7 @@ __global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 2) k_shade_bwd(const vs_v
       const int32_t dmax_j = wave_max(live ? dj : INT32_MIN) + 1;
       const int32_t ww = dmax_i - dmin_i + 1, wh = dmax_j - dmin_j + 1;
       if (ww * wh <= kWaveWin) {
+        ++n_path[npass == 1 ? 0 : npass == 2 ? 1 : 2];
         const int32_t c00 = (dj - dmin_j) * ww + (di - dmin_i);
         const int32_t cells[4] = {c00, c00 + 1, c00 + ww, c00 + ww + 1};
         // For each corner, distinct base texels give distinct cells.  One owner word per
@@ -560,6 +563,7 @@ __global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 2) k_shade_bwd(const vs_v
         pass = 2 * pass - 1;
       } else {
         direct = direct || live;
+        ++n_path[3];
       }
     }
     // rare (minified texels, pole fans): kept out of the passes above so that its
@@ -576,6 +580,11 @@ __global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 2) k_shade_bwd(const vs_v
         }
       }
     }
+  }
+  if (count_paths && lane == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (n_path[q]) atomicAdd(status + VS_STAT_SCATTER_WAVE + q, (unsigned long long)n_path[q]);
   }
   if (sse) {
     // block reduction of the squared error, one atomic per block

@@ -168,6 +168,11 @@ def test_render_validation_without_gpu(C):
     assert L.vs_render_backward(ctypes.addressof(meshes), ctypes.addressof(tex), 2, ctypes.byref(views), 0x5000,
                                 0x100000, need, 0x6000, ctypes.addressof(gp), None, None, None, None) == C.VS_ERR_ARG
     gp = (ctypes.c_void_p * 2)(0x7000, 0x8000)
+    # an unknown shading flag
+    odd = C.VsShadeOpts(0.0, 0, None, 1.0, 0, 6)
+    assert L.vs_render_backward(ctypes.addressof(meshes), ctypes.addressof(tex), 2, ctypes.byref(views), 0x5000,
+                                0x100000, need, 0x6000, ctypes.addressof(gp), None, None, ctypes.byref(odd),
+                                None) == C.VS_ERR_UNSUPPORTED
     # neither grad_rgba nor a target
     assert L.vs_render_backward(ctypes.addressof(meshes), ctypes.addressof(tex), 2, ctypes.byref(views), 0x5000,
                                 0x100000, need, None, ctypes.addressof(gp), None, None, None, None) == C.VS_ERR_ARG

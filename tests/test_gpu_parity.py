@@ -308,3 +308,32 @@ def test_layer_counts_up_to_the_maximum(torch_cuda, k):
     say(f"[gpu] k={k}: grad rel err {err:.2e}")
     assert err <= GRAD_RTOL
     assert all(np.abs(w).max() > 0 for w in want[:1])
+
+
+def test_scatter_retry_paths_are_taken_and_exact(torch_cuda):
+    """Texture sizes swept on one 256^2 view of the displaced shells, from magnified to strongly minified texels,
+    so that every scatter path of the adjoint occurs: the whole wavefront's LDS window, the half and quarter
+    wavefront retries, and direct atomics (counted in the status block with VS_SHADE_COUNT_PATHS).  Every
+    size's gradient is compared with the oracle's."""
+    torch = torch_cuda
+    base = small_mixed_scene(config=97, sizes=((256, 256),))
+    cam = base.cameras[0]
+    names = ["scatter_wave", "scatter_half", "scatter_quarter", "scatter_direct"]
+    seen = np.zeros(4, np.int64)
+    g = S.upstream_grad(97, cam)
+    flat = torch.from_numpy(g.reshape(-1, 4)).cuda()
+    for W in (64, 512, 1024, 2048):
+        textures = [S.uniform_texture(97, l, W, W, opaque=(l == base.k - 1)) for l in range(base.k)]
+        sc = S.Scene(base.name, base.layers, textures, base.cameras)
+        P, layers, views, vis, ws, rgba, tex = gpu_render(sc)
+        grads = P.render_backward(layers, tex, views, vis, ws, grad_rgba=flat, count_paths=True)
+        st = P.read_status(ws)
+        counts = np.array([st[n] for n in names])
+        got = [t.cpu().numpy().astype(np.float64) for t in grads]
+        want = O.backward(sc.layers, sc.textures, cam, oracle_vis(sc, views, vis, 0), grad_out=g.astype(np.float64))
+        err = grad_rel_err(got, want)
+        say(f"[gpu] scatter paths, {W}^2 textures: counts {dict(zip(names, counts.tolist()))}, grad rel err {err:.2e}")
+        assert err <= GRAD_RTOL
+        seen += counts
+        del grads, got, want, tex
+    assert (seen > 0).all(), f"scatter paths never taken: {[n for n, c in zip(names, seen) if c == 0]}"
