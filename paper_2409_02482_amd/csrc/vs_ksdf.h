@@ -298,10 +298,12 @@ __device__ inline int64_t ksdf_block() {
 
 // Two rays per wavefront, 32 lanes each: the 96 samples of the paper's
 // 64 + 32 fill three slots of 32 exactly (NSL = slots per lane, from the
-// sample count).  Blocks of 256 threads (8 rays), five per CU: the extra
-// wavefronts hide more of the gather and LDS latency than four blocks do.
+// sample count).  Blocks of 256 threads (8 rays), four per CU: the register
+// budget of four blocks holds the per-ray state without spilling to scratch
+// (five blocks per CU render as fast but spill, which writes gigabytes of
+// scratch traffic per launch).
 template <int NSL>
-__global__ void __launch_bounds__(256, 5) k_ksdf_render(const vs_view* __restrict__ views, int n_views, int64_t total,
+__global__ void __launch_bounds__(256, 4) k_ksdf_render(const vs_view* __restrict__ views, int n_views, int64_t total,
                                                      KsdfParams P, const uint32_t* __restrict__ occ,
                                                      float4* __restrict__ out, float4* __restrict__ layers,
                                                      double* __restrict__ samples) {
