@@ -278,17 +278,32 @@ vs_status vs_raster_layers(const vs_mesh* layers, int32_t k, const vs_views* vie
                      bin_view, lay.n_tiles_bin, slot);
   hipLaunchKernelGGL(vs::k_fill_u32, dim3(fill_grid), dim3(256), 0, s, count, lay.n_bins, 0u);
   hipLaunchKernelGGL(vs::k_fill_u32, dim3(fill_grid), dim3(256), 0, s, cursor, 2 * lay.n_bins, 0u);
-  const unsigned bin_blocks = (unsigned)vs::bin_grid_blocks(L.tri_pad[k], nv);
-  hipLaunchKernelGGL(vs::k_bin_count, dim3(bin_blocks), dim3(256), 0, s, views->dev, nv, L,
-                     (const vs::ProjVert*)proj, vpv, B, slot, count, spans, status);
+  const dim3 bin_grid(vs::bin_grid_x(L.tri_pad[k]), (unsigned)nv);
+  auto bin_count = [&](auto kern) {
+    hipLaunchKernelGGL(kern, bin_grid, dim3(256), 0, s, views->dev, L, (const vs::ProjVert*)proj, vpv, slot, count,
+                       spans, status);
+  };
+  auto bin_scatter = [&](auto kern) {
+    hipLaunchKernelGGL(kern, bin_grid, dim3(256), 0, s, views->dev, L, slot, (const vs::SpanRec*)spans,
+                       (const uint32_t*)count, (const uint64_t*)offset, cursor, list, lay.capacity);
+  };
+  switch (B) {
+    case 8: bin_count(vs::k_bin_count<8>); break;
+    case 16: bin_count(vs::k_bin_count<16>); break;
+    case 32: bin_count(vs::k_bin_count<32>); break;
+    default: bin_count(vs::k_bin_count<64>); break;
+  }
   hipLaunchKernelGGL(vs::k_scan_local, dim3((unsigned)lay.n_partial), dim3(256), 0, s, (const uint32_t*)count,
                      offset, partial, lay.n_bins);
   hipLaunchKernelGGL(vs::k_scan_partials, dim3(1), dim3(1024), 0, s, partial, lay.n_partial);
   hipLaunchKernelGGL(vs::k_scan_add, dim3(grid_1d(lay.n_bins, 256)), dim3(256), 0, s, offset,
                      (const uint64_t*)partial, lay.n_bins);
-  hipLaunchKernelGGL(vs::k_bin_scatter, dim3(bin_blocks), dim3(256), 0, s, views->dev, nv, L, B, slot,
-                     (const vs::SpanRec*)spans, (const uint32_t*)count, (const uint64_t*)offset, cursor, list,
-                     lay.capacity);
+  switch (B) {
+    case 8: bin_scatter(vs::k_bin_scatter<8>); break;
+    case 16: bin_scatter(vs::k_bin_scatter<16>); break;
+    case 32: bin_scatter(vs::k_bin_scatter<32>); break;
+    default: bin_scatter(vs::k_bin_scatter<64>); break;
+  }
   const unsigned nblk = (unsigned)((lay.n_bins + 7) / 8 * 8);
   auto raster = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(nblk), dim3(vs::kRasterThreads), 0, s, views->dev, (const int32_t*)bin_view,

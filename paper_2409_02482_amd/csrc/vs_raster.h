@@ -70,9 +70,6 @@ __device__ inline int cull_slot(int r) {
                                                                         : VS_STAT_BAD_INDEX;
 }
 
-// Bin index of (global tile g, layer l): bins of one tile are consecutive.
-__device__ inline int64_t bin_index(int64_t g, int l, int k) { return g * k + l; }
-
 // Record of one (view, layer, triangle) written by k_bin_count: its pixel
 // bounding box clipped to the view, packed in 64 bits,
 //   i0 | i1 << 13 | j0 << 26 | j1 << 39 | front << 52 | valid << 53,
@@ -100,39 +97,30 @@ __device__ inline void unpack_box(uint64_t b, int& i0, int& i1, int& j0, int& j1
   i0 = (int)(b & 8191); i1 = (int)((b >> 13) & 8191); j0 = (int)((b >> 26) & 8191); j1 = (int)((b >> 39) & 8191);
 }
 
-struct BinWork {
-  int v, l;
-  int32_t t;
-  int tx0, tx1, ty0, ty1;   // tile span (inclusive)
-  bool front;
-  int64_t g0;               // global tile index of the view's tile (0, 0)
-  int ntx;                  // tiles per row in this view
-};
-
-// Blocks of a count/scatter launch: per view, ceil(padded triangles of all layers / 256)
-// (each layer's range rounded up to 64, so that a wavefront never spans two layers),
-// the total rounded up to a multiple of the XCD count.
-__host__ __device__ inline int64_t bin_grid_blocks(int64_t n_tri_padded, int n_views) {
-  return ((n_tri_padded + 255) / 256 * n_views + 7) / 8 * 8;
+// Grid of a count/scatter launch: x = blocks of 256 padded triangles of one view
+// (each layer's range rounded up to 64, so that a wavefront never spans two
+// layers), rounded up to a multiple of the XCD count; y = view.
+__host__ __device__ inline uint32_t bin_grid_x(int64_t n_tri_padded) {
+  return (uint32_t)(((n_tri_padded + 255) / 256 + 7) / 8 * 8);
 }
 
-// Which (view, layer, triangle) this thread of a count/scatter launch handles; g is the
-// triangle's index over all layers of the view.  Blocks are dealt round-robin to the 8
-// XCDs; the remap gives each XCD a contiguous range of (view, triangle block)s, so that
-// triangles sharing vertices share that XCD's L2.  The layer is the same on every lane
-// of a wavefront, so its table entries are scalar loads.
-__device__ inline bool bin_thread(const LayerTable& L, int n_views, int& v, int& l, int32_t& t, int64_t& g) {
+// Which (layer, triangle) of view blockIdx.y this thread of a count/scatter
+// launch handles; g is the triangle's index over all layers of the view.
+// Blocks are dealt round-robin to the 8 XCDs, and gridDim.x is a multiple of
+// 8, so blockIdx.x % 8 is the XCD: the remap gives each XCD a contiguous
+// eighth of the view's triangles (triangles that share vertices share that
+// XCD's L2).  The layer is the same on every lane of a wavefront, so the
+// layer search and its table entries are scalar.
+__device__ inline bool bin_thread(const LayerTable& L, int& l, int32_t& t, int64_t& g) {
   const int k = L.k;
-  const int64_t per_view = (L.tri_pad[k] + 255) / 256;
-  const int64_t chunk = (int64_t)gridDim.x / 8;
-  const int64_t bid = ((int64_t)blockIdx.x % 8) * chunk + (int64_t)blockIdx.x / 8;
-  v = (int)(bid / per_view);
-  if (v >= n_views) return false;
-  const int64_t gp = (bid - (int64_t)v * per_view) * 256 + threadIdx.x;   // padded index
-  const int64_t gw = gp & ~(int64_t)63;                                   // the wavefront's first
+  const uint32_t chunk = gridDim.x >> 3;
+  const uint32_t bx = (blockIdx.x & 7u) * chunk + (blockIdx.x >> 3);
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t gw = (int64_t)bx * 256 + wave * 64;   // the wavefront's first padded index
   int lw = 0;
   while (lw + 1 < k && L.tri_pad[lw + 1] <= gw) ++lw;
-  l = __builtin_amdgcn_readfirstlane(lw);
+  l = lw;
+  const int64_t gp = gw + (threadIdx.x & 63);
   if (gp >= L.tri_pad[k]) return false;
   t = (int32_t)(gp - L.tri_pad[l]);
   if (t >= L.n_tri[l]) return false;   // padding
@@ -140,25 +128,36 @@ __device__ inline bool bin_thread(const LayerTable& L, int n_views, int& v, int&
   return true;
 }
 
+// Bins of one view: (tile, layer) pairs, tile-major, starting at
+// tile_offset[slot] * k in the counters of all views (so a view's bin index
+// fits 32 bits: at most 1024^2 tiles times 16 layers).
+__device__ inline int64_t view_bins_base(const vs_view& V, int slot, int k) {
+  return (int64_t)V.tile_offset[slot] * k;
+}
+
 // Count triangles per bin and record each triangle's box and depth bound.
-__global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ views, int n_views, LayerTable L,
-                                                   const ProjVert* __restrict__ proj, int64_t vpv, int B, int slot,
+template <int B>
+__global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ views, LayerTable L,
+                                                   const ProjVert* __restrict__ proj, int64_t vpv, int slot,
                                                    uint32_t* __restrict__ count, SpanRec* __restrict__ spans,
                                                    unsigned long long* __restrict__ status) {
-  int v = 0, l = 0;
+  int l = 0;
   int32_t t = 0;
   int64_t g = 0;
-  bool ok = bin_thread(L, n_views, v, l, t, g);
+  bool ok = bin_thread(L, l, t, g);
+  const int v = blockIdx.y;
   const int k = L.k;
-  BinWork w;
-  SpanRec span;
-  span.box = 0; span.zlo = 0; span.pad = 0;
+  const vs_view& V = views[v];
+  const int W = V.cam.width, H = V.cam.height;
+  const int ntx = (W + B - 1) / B;
+  uint32_t* cv = count + view_bins_base(V, slot, k);
+  int tx0 = 0, tx1 = 0, ty0 = 0, ty1 = 0;
   if (ok) {
-    const vs_view& V = views[v];
-    const int W = V.cam.width, H = V.cam.height;
     const ProjVert* P = proj + (int64_t)v * vpv + L.vert_off[l];
     TriSetup T;
     const int r = setup_triangle(L.tri[l] + 3 * (int64_t)t, L.n_vert[l], P, T);
+    SpanRec span;
+    span.box = 0; span.zlo = 0; span.pad = 0;
     if (r != kTriOk) {
       atomicAdd(status + cull_slot(r), 1ull);
       ok = false;
@@ -167,31 +166,32 @@ __global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ v
       if (pr.i0 > pr.i1 || pr.j0 > pr.j1) {
         ok = false;
       } else {
-        w.l = l; w.t = t;
-        w.tx0 = pr.i0 / B; w.tx1 = pr.i1 / B; w.ty0 = pr.j0 / B; w.ty1 = pr.j1 / B;
-        w.g0 = V.tile_offset[slot];
-        w.ntx = (W + B - 1) / B;
+        tx0 = pr.i0 / B; tx1 = pr.i1 / B; ty0 = pr.j0 / B; ty1 = pr.j1 / B;
         span.box = pack_box(pr.i0, pr.i1, pr.j0, pr.j1, T.orig_sign < 0);
         span.zlo = (uint32_t)(depth_lower_key(T, (uint32_t)t) >> 32);
       }
     }
     spans[(int64_t)v * L.tri_off[k] + g] = span;
   }
-  // first bin of every lane: aggregated across the wavefront
-  int64_t b0 = ok ? bin_index(w.g0 + (int64_t)w.ty0 * w.ntx + w.tx0, w.l, k) : -1;
+  // first bin of every lane: lanes with the same bin elect one lane (register
+  // exchanges only), and all elected lanes add in one atomic instruction
+  const int32_t b0 = ok ? (ty0 * ntx + tx0) * k + l : -1;
+  const int lane = (int)__lane_id();
   uint64_t active = __ballot(b0 >= 0);
+  uint32_t group = 0;
   while (active) {
-    const int leader = __ffsll((unsigned long long)active) - 1;
-    const int64_t lb = __shfl(b0, leader);
+    const int leader = (int)__builtin_ctzll(active);
+    const int32_t lb = __builtin_amdgcn_readlane(b0, leader);
     const uint64_t same = __ballot(b0 == lb);
-    if ((int)__lane_id() == leader) atomicAdd(count + lb, (uint32_t)__popcll(same));
+    if (lane == leader) group = (uint32_t)__popcll(same);
     active &= ~same;
   }
+  if (group) atomicAdd(cv + b0, group);
   if (!ok) return;
-  for (int ty = w.ty0; ty <= w.ty1; ++ty)
-    for (int tx = w.tx0; tx <= w.tx1; ++tx) {
-      if (ty == w.ty0 && tx == w.tx0) continue;
-      atomicAdd(count + bin_index(w.g0 + (int64_t)ty * w.ntx + tx, w.l, k), 1u);
+  for (int ty = ty0; ty <= ty1; ++ty)
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      if (ty == ty0 && tx == tx0) continue;
+      atomicAdd(cv + (ty * ntx + tx) * k + l, 1u);
     }
 }
 
@@ -263,59 +263,77 @@ __global__ void __launch_bounds__(256) k_scan_add(uint64_t* __restrict__ out, co
 // head of a bin's list, the others from its tail.  A bin whose list would end
 // past the capacity is left unwritten; the raster of that bin then scans every
 // triangle of its layer instead (slow but exact) and the overflow is counted.
-__global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__ views, int n_views, LayerTable L,
-                                                     int B, int slot,
+template <int B>
+__global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__ views, LayerTable L, int slot,
                                                      const SpanRec* __restrict__ spans,
                                                      const uint32_t* __restrict__ count,
                                                      const uint64_t* __restrict__ offset,
                                                      uint32_t* __restrict__ cursor, int32_t* __restrict__ list,
                                                      uint64_t capacity) {
-  int v = 0, l = 0;
+  int l = 0;
   int32_t t = 0;
   int64_t g = 0;
-  bool ok = bin_thread(L, n_views, v, l, t, g);
+  bool ok = bin_thread(L, l, t, g);
+  const int v = blockIdx.y;
   const int k = L.k;
+  const vs_view& V = views[v];
+  const int ntx = (V.cam.width + B - 1) / B;
+  const int64_t vb = view_bins_base(V, slot, k);
+  const uint32_t* cv = count + vb;
+  const uint64_t* ov = offset + vb;
+  uint32_t* uv = cursor + 2 * vb;   // per bin: [2 b] front entries from the head, [2 b + 1] the others from the tail
   const uint64_t span = ok ? spans[(int64_t)v * L.tri_off[k] + g].box : 0ull;
   ok = ok && (span & kSpanValid);
-  int tx0 = 0, tx1 = 0, ty0 = 0, ty1 = 0, ntx = 0;
-  int64_t g0 = 0;
-  bool front = false;
+  int tx0 = 0, tx1 = 0, ty0 = 0, ty1 = 0;
+  const bool front = (span & kSpanFront) != 0;
   if (ok) {
     int i0, i1, j0, j1;
     unpack_box(span, i0, i1, j0, j1);
     tx0 = i0 / B; tx1 = i1 / B; ty0 = j0 / B; ty1 = j1 / B;
-    front = (span & kSpanFront) != 0;
-    const vs_view& V = views[v];
-    g0 = V.tile_offset[slot];
-    ntx = (V.cam.width + B - 1) / B;
   }
-  // cursors: [2 b] counts front entries from the head, [2 b + 1] the others from the tail
-  const int64_t b0 = ok ? bin_index(g0 + (int64_t)ty0 * ntx + tx0, l, k) : -1;
-  const int64_t c0 = ok ? 2 * b0 + (front ? 0 : 1) : -1;
-  uint64_t active = __ballot(c0 >= 0);
+  // first bin of every lane: lanes with the same (bin, side) elect one lane,
+  // which reserves the group's entries; all elected lanes reserve in one
+  // atomic instruction, and the bins' list ranges are loaded meanwhile
+  const int32_t b0 = ok ? (ty0 * ntx + tx0) * k + l : -1;
+  const int32_t c0 = ok ? 2 * b0 + (front ? 0 : 1) : -1;
+  const int lane = (int)__lane_id();
   const uint64_t lt = __lanemask_lt();
+  uint64_t active = __ballot(c0 >= 0);
+  uint32_t group = 0, rank = 0;
+  int leader_of = lane;
   while (active) {
-    const int leader = __ffsll((unsigned long long)active) - 1;
-    const int64_t lc = __shfl(c0, leader);
+    const int leader = (int)__builtin_ctzll(active);
+    const int32_t lc = __builtin_amdgcn_readlane(c0, leader);
     const uint64_t same = __ballot(c0 == lc);
-    uint32_t base = 0;
-    if ((int)__lane_id() == leader) base = atomicAdd(cursor + lc, (uint32_t)__popcll(same));
-    base = __shfl(base, leader);
     if (c0 == lc) {
-      const uint32_t rank = base + (uint32_t)__popcll(same & lt);
-      const uint64_t end = offset[b0] + count[b0];
-      if (end <= capacity) list[front ? offset[b0] + rank : end - 1 - rank] = t;
+      leader_of = leader;
+      rank = (uint32_t)__popcll(same & lt);
     }
+    if (lane == leader) group = (uint32_t)__popcll(same);
     active &= ~same;
   }
+  uint64_t off = 0;
+  uint32_t cnt = 0;
+  if (ok) {
+    off = ov[b0];
+    cnt = cv[b0];
+  }
+  uint32_t base = 0;
+  if (group) base = atomicAdd(uv + c0, group);
+  base = __shfl(base, leader_of) + rank;
   if (!ok) return;
+  {
+    const uint64_t end = off + cnt;
+    if (end <= capacity) list[front ? off + base : end - 1 - base] = t;
+  }
   for (int ty = ty0; ty <= ty1; ++ty)
     for (int tx = tx0; tx <= tx1; ++tx) {
       if (ty == ty0 && tx == tx0) continue;
-      const int64_t b = bin_index(g0 + (int64_t)ty * ntx + tx, l, k);
-      const uint32_t rank = atomicAdd(cursor + 2 * b + (front ? 0 : 1), 1u);
-      const uint64_t end = offset[b] + count[b];
-      if (end <= capacity) list[front ? offset[b] + rank : end - 1 - rank] = t;
+      const int32_t b = (ty * ntx + tx) * k + l;
+      const uint64_t o = ov[b];
+      const uint64_t end = o + cv[b];
+      const uint32_t r = atomicAdd(uv + 2 * b + (front ? 0 : 1), 1u);
+      if (end <= capacity) list[front ? o + r : end - 1 - r] = t;
     }
 }
 
