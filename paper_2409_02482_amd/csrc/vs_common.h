@@ -91,17 +91,6 @@ __device__ inline ProjVert project_vertex(const float* p, const vs_camera& c) {
   return o;
 }
 
-// One projected vertex as a single 16-byte load (so that the three vertices of
-// a triangle are requested together, not field by field behind the checks).
-__device__ inline ProjVert load_proj(const ProjVert* p) {
-  const int4 r = *reinterpret_cast<const int4*>(p);
-  ProjVert o;
-  o.X = r.x;
-  o.Y = r.y;
-  o.w = __hiloint2double(r.w, r.z);
-  return o;
-}
-
 // ------------------------------------------------------------------ step 2
 // Triangle after orientation normalisation.  Screen coordinates are integers
 // below 2^25 in magnitude, so every edge-function value (< 2^51) is exact in
@@ -123,19 +112,41 @@ __device__ inline bool top_left(double px, double py, double qx, double qy) {
   return dy < 0.0 || (dy == 0.0 && dx > 0.0);
 }
 
-// ids are the three vertex ids of the triangle; pv the projected vertices of
-// its layer in this view.  Branch-free until the status is chosen: the ids are
-// read as one 12-byte load and the three vertices as three 16-byte loads that
-// are all in flight together (an out-of-range id reads vertex 0 instead and
-// reports kTriBadIndex).
-__device__ inline int setup_triangle(const int32_t* ids, int32_t n_vert, const ProjVert* pv, TriSetup& T) {
-  const int3 tid3 = *reinterpret_cast<const int3*>(ids);
-  int32_t id[3] = {tid3.x, tid3.y, tid3.z};
-  const bool bad = (uint32_t)id[0] >= (uint32_t)n_vert || (uint32_t)id[1] >= (uint32_t)n_vert ||
-                   (uint32_t)id[2] >= (uint32_t)n_vert;
-  ProjVert a = load_proj(pv + (bad ? 0 : id[0]));
-  ProjVert b = load_proj(pv + (bad ? 0 : id[1]));
-  ProjVert c = load_proj(pv + (bad ? 0 : id[2]));
+// The raw loads of one triangle's set-up: its three vertex ids (one 12-byte
+// load) and its three projected vertices (three 16-byte loads, all in flight
+// together).  An out-of-range id reads vertex 0 instead and marks the triangle
+// bad.  Split from the arithmetic so that a thread can have the loads of
+// several triangles in flight before it uses any of them.
+struct TriLoad {
+  int32_t id[3];
+  int4 a, b, c;
+  bool bad;
+};
+
+__device__ inline int3 load_ids(const int32_t* ids) { return *reinterpret_cast<const int3*>(ids); }
+
+__device__ inline void load_vertices(int3 ids, int32_t n_vert, const ProjVert* pv, TriLoad& r) {
+  r.id[0] = ids.x; r.id[1] = ids.y; r.id[2] = ids.z;
+  r.bad = (uint32_t)ids.x >= (uint32_t)n_vert || (uint32_t)ids.y >= (uint32_t)n_vert ||
+          (uint32_t)ids.z >= (uint32_t)n_vert;
+  r.a = *reinterpret_cast<const int4*>(pv + (r.bad ? 0 : ids.x));
+  r.b = *reinterpret_cast<const int4*>(pv + (r.bad ? 0 : ids.y));
+  r.c = *reinterpret_cast<const int4*>(pv + (r.bad ? 0 : ids.z));
+}
+
+__device__ inline ProjVert proj_of(int4 r) {
+  ProjVert o;
+  o.X = r.x;
+  o.Y = r.y;
+  o.w = __hiloint2double(r.w, r.z);
+  return o;
+}
+
+// Orientation normalisation and edge ownership of a loaded triangle.
+// Branch-free until the status is chosen.
+__device__ inline int setup_loaded(const TriLoad& q, TriSetup& T) {
+  ProjVert a = proj_of(q.a), b = proj_of(q.b), c = proj_of(q.c);
+  int32_t id[3] = {q.id[0], q.id[1], q.id[2]};
   const bool invalid = a.X == kInvalidX || b.X == kInvalidX || c.X == kInvalidX;
   double area2 = ((double)b.X - (double)a.X) * ((double)c.Y - (double)a.Y) -
                  ((double)b.Y - (double)a.Y) * ((double)c.X - (double)a.X);
@@ -154,7 +165,15 @@ __device__ inline int setup_triangle(const int32_t* ids, int32_t n_vert, const P
   T.th[0] = top_left(T.X[1], T.Y[1], T.X[2], T.Y[2]) ? 0.0 : 1.0;
   T.th[1] = top_left(T.X[2], T.Y[2], T.X[0], T.Y[0]) ? 0.0 : 1.0;
   T.th[2] = top_left(T.X[0], T.Y[0], T.X[1], T.Y[1]) ? 0.0 : 1.0;
-  return bad ? kTriBadIndex : invalid ? kTriInvalid : area2 == 0.0 ? kTriDegenerate : kTriOk;
+  return q.bad ? kTriBadIndex : invalid ? kTriInvalid : area2 == 0.0 ? kTriDegenerate : kTriOk;
+}
+
+// ids are the three vertex ids of the triangle; pv the projected vertices of
+// its layer in this view.
+__device__ inline int setup_triangle(const int32_t* ids, int32_t n_vert, const ProjVert* pv, TriSetup& T) {
+  TriLoad q;
+  load_vertices(load_ids(ids), n_vert, pv, q);
+  return setup_loaded(q, T);
 }
 
 // Edge functions at sample point (px, py) (1/256 px units):

@@ -97,29 +97,41 @@ __device__ inline void unpack_box(uint64_t b, int& i0, int& i1, int& j0, int& j1
   i0 = (int)(b & 8191); i1 = (int)((b >> 13) & 8191); j0 = (int)((b >> 26) & 8191); j1 = (int)((b >> 39) & 8191);
 }
 
-// Grid of a count/scatter launch: x = blocks of 256 padded triangles of one view
-// (each layer's range rounded up to 64, so that a wavefront never spans two
-// layers), rounded up to a multiple of the XCD count; y = view.
+// Triangles per thread in the count and scatter launches: each thread has the
+// loads of both in flight before it uses either (two halved the metric scene's
+// count time against one; four cost more registers than they hid latency).
+constexpr int kBinReps = 2;
+
+// Grid of a count/scatter launch: x = blocks of kBinReps x 256 padded triangles
+// of one view (each layer's range rounded up to 64, so that a wavefront never
+// spans two layers), rounded up to a multiple of the XCD count; y = view.
 __host__ __device__ inline uint32_t bin_grid_x(int64_t n_tri_padded) {
-  return (uint32_t)(((n_tri_padded + 255) / 256 + 7) / 8 * 8);
+  return (uint32_t)((((n_tri_padded + 255) / 256 + kBinReps - 1) / kBinReps + 7) / 8 * 8);
 }
 
-// Which (layer, triangle) of view blockIdx.y this thread of a count/scatter
-// launch handles; g is the triangle's index over all layers of the view.
+// Block of 256 padded triangles that repetition r of this block handles.
 // Blocks are dealt round-robin to the 8 XCDs, and gridDim.x is a multiple of
 // 8, so blockIdx.x % 8 is the XCD: the remap gives each XCD a contiguous
 // eighth of the view's triangles (triangles that share vertices share that
-// XCD's L2).  The layer is the same on every lane of a wavefront, so the
-// layer search and its table entries are scalar.
-__device__ inline bool bin_thread(const LayerTable& L, int& l, int32_t& t, int64_t& g) {
-  const int k = L.k;
+// XCD's L2).
+__device__ inline uint32_t bin_block(int r) {
   const uint32_t chunk = gridDim.x >> 3;
-  const uint32_t bx = (blockIdx.x & 7u) * chunk + (blockIdx.x >> 3);
+  return ((blockIdx.x & 7u) * chunk + (blockIdx.x >> 3)) * kBinReps + r;
+}
+
+// Which (layer, triangle) of view blockIdx.y this thread handles in block vb;
+// g is the triangle's index over all layers of the view.  The layer is the
+// same on every lane of a wavefront, so the layer search and its table
+// entries are scalar.
+__device__ inline bool bin_thread(const LayerTable& L, uint32_t vb, int& l, int32_t& t, int64_t& g) {
+  const int k = L.k;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t gw = (int64_t)bx * 256 + wave * 64;   // the wavefront's first padded index
+  const int64_t gw = (int64_t)vb * 256 + wave * 64;   // the wavefront's first padded index
   int lw = 0;
   while (lw + 1 < k && L.tri_pad[lw + 1] <= gw) ++lw;
   l = lw;
+  t = 0;
+  g = 0;
   const int64_t gp = gw + (threadIdx.x & 63);
   if (gp >= L.tri_pad[k]) return false;
   t = (int32_t)(gp - L.tri_pad[l]);
@@ -141,58 +153,83 @@ __global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ v
                                                    const ProjVert* __restrict__ proj, int64_t vpv, int slot,
                                                    uint32_t* __restrict__ count, SpanRec* __restrict__ spans,
                                                    unsigned long long* __restrict__ status) {
-  int l = 0;
-  int32_t t = 0;
-  int64_t g = 0;
-  bool ok = bin_thread(L, l, t, g);
+  constexpr int R = kBinReps;
   const int v = blockIdx.y;
   const int k = L.k;
   const vs_view& V = views[v];
   const int W = V.cam.width, H = V.cam.height;
   const int ntx = (W + B - 1) / B;
   uint32_t* cv = count + view_bins_base(V, slot, k);
-  int tx0 = 0, tx1 = 0, ty0 = 0, ty1 = 0;
-  if (ok) {
-    const ProjVert* P = proj + (int64_t)v * vpv + L.vert_off[l];
-    TriSetup T;
-    const int r = setup_triangle(L.tri[l] + 3 * (int64_t)t, L.n_vert[l], P, T);
-    SpanRec span;
-    span.box = 0; span.zlo = 0; span.pad = 0;
-    if (r != kTriOk) {
-      atomicAdd(status + cull_slot(r), 1ull);
-      ok = false;
-    } else {
-      const PixRange pr = pixel_range(T, W, H);
-      if (pr.i0 > pr.i1 || pr.j0 > pr.j1) {
-        ok = false;
-      } else {
-        tx0 = pr.i0 / B; tx1 = pr.i1 / B; ty0 = pr.j0 / B; ty1 = pr.j1 / B;
-        span.box = pack_box(pr.i0, pr.i1, pr.j0, pr.j1, T.orig_sign < 0);
-        span.zlo = (uint32_t)(depth_lower_key(T, (uint32_t)t) >> 32);
-      }
-    }
-    spans[(int64_t)v * L.tri_off[k] + g] = span;
+  const ProjVert* pview = proj + (int64_t)v * vpv;
+  SpanRec* sview = spans + (int64_t)v * L.tri_off[k];
+  bool ok[R];
+  int l[R];
+  int32_t t[R];
+  int64_t g[R];
+  int3 ids[R];
+  TriLoad q[R];
+  // ids of every repetition, then their vertices: all loads in flight before any use
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    ok[r] = bin_thread(L, bin_block(r), l[r], t[r], g[r]);
+    ids[r] = make_int3(0, 0, 0);
+    if (ok[r]) ids[r] = load_ids(L.tri[l[r]] + 3 * (int64_t)t[r]);
   }
-  // first bin of every lane: lanes with the same bin elect one lane (register
-  // exchanges only), and all elected lanes add in one atomic instruction
-  const int32_t b0 = ok ? (ty0 * ntx + tx0) * k + l : -1;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    // defined on every lane: left undefined, the records stay live across the
+    // divergent loads and cost about 16 more registers
+    q[r].a = q[r].b = q[r].c = make_int4(0, 0, 0, 0);
+    q[r].id[0] = q[r].id[1] = q[r].id[2] = 0;
+    q[r].bad = false;
+    if (ok[r]) load_vertices(ids[r], L.n_vert[l[r]], pview + L.vert_off[l[r]], q[r]);
+  }
   const int lane = (int)__lane_id();
-  uint64_t active = __ballot(b0 >= 0);
-  uint32_t group = 0;
-  while (active) {
-    const int leader = (int)__builtin_ctzll(active);
-    const int32_t lb = __builtin_amdgcn_readlane(b0, leader);
-    const uint64_t same = __ballot(b0 == lb);
-    if (lane == leader) group = (uint32_t)__popcll(same);
-    active &= ~same;
-  }
-  if (group) atomicAdd(cv + b0, group);
-  if (!ok) return;
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      if (ty == ty0 && tx == tx0) continue;
-      atomicAdd(cv + (ty * ntx + tx) * k + l, 1u);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    int tx0 = 0, tx1 = 0, ty0 = 0, ty1 = 0;
+    bool live = ok[r];
+    if (live) {
+      TriSetup T;
+      const int st = setup_loaded(q[r], T);
+      SpanRec span;
+      span.box = 0; span.zlo = 0; span.pad = 0;
+      if (st != kTriOk) {
+        atomicAdd(status + cull_slot(st), 1ull);
+        live = false;
+      } else {
+        const PixRange pr = pixel_range(T, W, H);
+        if (pr.i0 > pr.i1 || pr.j0 > pr.j1) {
+          live = false;
+        } else {
+          tx0 = pr.i0 / B; tx1 = pr.i1 / B; ty0 = pr.j0 / B; ty1 = pr.j1 / B;
+          span.box = pack_box(pr.i0, pr.i1, pr.j0, pr.j1, T.orig_sign < 0);
+          span.zlo = (uint32_t)(depth_lower_key(T, (uint32_t)t[r]) >> 32);
+        }
+      }
+      sview[g[r]] = span;
     }
+    // first bin of every lane: lanes with the same bin elect one lane (register
+    // exchanges only), and all elected lanes add in one atomic instruction
+    const int32_t b0 = live ? (ty0 * ntx + tx0) * k + l[r] : -1;
+    uint64_t active = __ballot(b0 >= 0);
+    uint32_t group = 0;
+    while (active) {
+      const int leader = (int)__builtin_ctzll(active);
+      const int32_t lb = __builtin_amdgcn_readlane(b0, leader);
+      const uint64_t same = __ballot(b0 == lb);
+      if (lane == leader) group = (uint32_t)__popcll(same);
+      active &= ~same;
+    }
+    if (group) atomicAdd(cv + b0, group);
+    if (live) {
+      for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) {
+          if (ty == ty0 && tx == tx0) continue;
+          atomicAdd(cv + (ty * ntx + tx) * k + l[r], 1u);
+        }
+    }
+  }
 }
 
 // Exclusive scan of the per-bin counts into 64-bit list offsets (the total
@@ -270,10 +307,7 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__
                                                      const uint64_t* __restrict__ offset,
                                                      uint32_t* __restrict__ cursor, int32_t* __restrict__ list,
                                                      uint64_t capacity) {
-  int l = 0;
-  int32_t t = 0;
-  int64_t g = 0;
-  bool ok = bin_thread(L, l, t, g);
+  constexpr int R = kBinReps;
   const int v = blockIdx.y;
   const int k = L.k;
   const vs_view& V = views[v];
@@ -282,59 +316,87 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__
   const uint32_t* cv = count + vb;
   const uint64_t* ov = offset + vb;
   uint32_t* uv = cursor + 2 * vb;   // per bin: [2 b] front entries from the head, [2 b + 1] the others from the tail
-  const uint64_t span = ok ? spans[(int64_t)v * L.tri_off[k] + g].box : 0ull;
-  ok = ok && (span & kSpanValid);
-  int tx0 = 0, tx1 = 0, ty0 = 0, ty1 = 0;
-  const bool front = (span & kSpanFront) != 0;
-  if (ok) {
-    int i0, i1, j0, j1;
-    unpack_box(span, i0, i1, j0, j1);
-    tx0 = i0 / B; tx1 = i1 / B; ty0 = j0 / B; ty1 = j1 / B;
-  }
-  // first bin of every lane: lanes with the same (bin, side) elect one lane,
-  // which reserves the group's entries; all elected lanes reserve in one
-  // atomic instruction, and the bins' list ranges are loaded meanwhile
-  const int32_t b0 = ok ? (ty0 * ntx + tx0) * k + l : -1;
-  const int32_t c0 = ok ? 2 * b0 + (front ? 0 : 1) : -1;
+  const SpanRec* sview = spans + (int64_t)v * L.tri_off[k];
   const int lane = (int)__lane_id();
   const uint64_t lt = __lanemask_lt();
-  uint64_t active = __ballot(c0 >= 0);
-  uint32_t group = 0, rank = 0;
-  int leader_of = lane;
-  while (active) {
-    const int leader = (int)__builtin_ctzll(active);
-    const int32_t lc = __builtin_amdgcn_readlane(c0, leader);
-    const uint64_t same = __ballot(c0 == lc);
-    if (c0 == lc) {
-      leader_of = leader;
-      rank = (uint32_t)__popcll(same & lt);
+  bool ok[R];
+  int l[R];
+  int32_t t[R];
+  int64_t g[R];
+  uint64_t span[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    ok[r] = bin_thread(L, bin_block(r), l[r], t[r], g[r]);
+    span[r] = ok[r] ? sview[g[r]].box : 0ull;
+  }
+  // per repetition: the first bin's (bin, side) class, the elected lane of each
+  // class and the lane's rank in it (register exchanges only)
+  int32_t b0[R], c0[R];
+  uint32_t group[R], rank[R];
+  int leader_of[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    ok[r] = ok[r] && (span[r] & kSpanValid);
+    b0[r] = -1;
+    if (ok[r]) {
+      int i0, i1, j0, j1;
+      unpack_box(span[r], i0, i1, j0, j1);
+      b0[r] = ((j0 / B) * ntx + i0 / B) * k + l[r];
     }
-    if (lane == leader) group = (uint32_t)__popcll(same);
-    active &= ~same;
-  }
-  uint64_t off = 0;
-  uint32_t cnt = 0;
-  if (ok) {
-    off = ov[b0];
-    cnt = cv[b0];
-  }
-  uint32_t base = 0;
-  if (group) base = atomicAdd(uv + c0, group);
-  base = __shfl(base, leader_of) + rank;
-  if (!ok) return;
-  {
-    const uint64_t end = off + cnt;
-    if (end <= capacity) list[front ? off + base : end - 1 - base] = t;
-  }
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      if (ty == ty0 && tx == tx0) continue;
-      const int32_t b = (ty * ntx + tx) * k + l;
-      const uint64_t o = ov[b];
-      const uint64_t end = o + cv[b];
-      const uint32_t r = atomicAdd(uv + 2 * b + (front ? 0 : 1), 1u);
-      if (end <= capacity) list[front ? o + r : end - 1 - r] = t;
+    c0[r] = ok[r] ? 2 * b0[r] + ((span[r] & kSpanFront) ? 0 : 1) : -1;
+    uint64_t active = __ballot(c0[r] >= 0);
+    group[r] = 0;
+    rank[r] = 0;
+    leader_of[r] = lane;
+    while (active) {
+      const int leader = (int)__builtin_ctzll(active);
+      const int32_t lc = __builtin_amdgcn_readlane(c0[r], leader);
+      const uint64_t same = __ballot(c0[r] == lc);
+      if (c0[r] == lc) {
+        leader_of[r] = leader;
+        rank[r] = (uint32_t)__popcll(same & lt);
+      }
+      if (lane == leader) group[r] = (uint32_t)__popcll(same);
+      active &= ~same;
     }
+  }
+  // the bins' list ranges and every elected lane's reservation, all in flight together
+  uint64_t off[R];
+  uint32_t cnt[R], base[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    off[r] = 0;
+    cnt[r] = 0;
+    if (ok[r]) {
+      off[r] = ov[b0[r]];
+      cnt[r] = cv[b0[r]];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    base[r] = 0;
+    if (group[r]) base[r] = atomicAdd(uv + c0[r], group[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t e = __shfl(base[r], leader_of[r]) + rank[r];
+    if (!ok[r]) continue;
+    const bool front = (span[r] & kSpanFront) != 0;
+    const uint64_t end = off[r] + cnt[r];
+    if (end <= capacity) list[front ? off[r] + e : end - 1 - e] = t[r];
+    int i0, i1, j0, j1;
+    unpack_box(span[r], i0, i1, j0, j1);
+    const int tx0 = i0 / B, tx1 = i1 / B, ty0 = j0 / B, ty1 = j1 / B;
+    for (int ty = ty0; ty <= ty1; ++ty)
+      for (int tx = tx0; tx <= tx1; ++tx) {
+        if (ty == ty0 && tx == tx0) continue;
+        const int32_t b = (ty * ntx + tx) * k + l[r];
+        const uint64_t o = ov[b];
+        const uint64_t bend = o + cv[b];
+        const uint32_t rr = atomicAdd(uv + 2 * b + (front ? 0 : 1), 1u);
+        if (bend <= capacity) list[front ? o + rr : bend - 1 - rr] = t[r];
+      }
+  }
 }
 
 // tile_view[g] = view owning tile g of the given tile-size slot.
