@@ -384,18 +384,50 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__
     const bool front = (span[r] & kSpanFront) != 0;
     const uint64_t end = off[r] + cnt[r];
     if (end <= capacity) list[front ? off[r] + e : end - 1 - e] = t[r];
+    // the span's other bins, four at a time: their list ranges and reservations
+    // are all in flight before any entry is written
     int i0, i1, j0, j1;
     unpack_box(span[r], i0, i1, j0, j1);
     const int tx0 = i0 / B, tx1 = i1 / B, ty0 = j0 / B, ty1 = j1 / B;
-    for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx) {
-        if (ty == ty0 && tx == tx0) continue;
-        const int32_t b = (ty * ntx + tx) * k + l[r];
-        const uint64_t o = ov[b];
-        const uint64_t bend = o + cv[b];
-        const uint32_t rr = atomicAdd(uv + 2 * b + (front ? 0 : 1), 1u);
-        if (bend <= capacity) list[front ? o + rr : bend - 1 - rr] = t[r];
+    int tx = tx0, ty = ty0;   // the bin before the next one to take
+    int left = (tx1 - tx0 + 1) * (ty1 - ty0 + 1) - 1;
+    while (left > 0) {
+      int32_t bq[4];
+      uint64_t oq[4];
+      uint32_t cq[4], rq[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        bq[e] = -1;
+        if (e < left) {
+          if (++tx > tx1) {
+            tx = tx0;
+            ++ty;
+          }
+          bq[e] = (ty * ntx + tx) * k + l[r];
+        }
       }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        oq[e] = 0;
+        cq[e] = 0;
+        rq[e] = 0;
+        if (bq[e] >= 0) {
+          oq[e] = ov[bq[e]];
+          cq[e] = cv[bq[e]];
+          rq[e] = atomicAdd(uv + 2 * bq[e] + (front ? 0 : 1), 1u);
+        }
+      }
+      // one wait for all four reservations (the empty statement uses them on every
+      // lane), so that the stores below issue back to back
+      __asm__ volatile("" ::"v"(rq[0]), "v"(rq[1]), "v"(rq[2]), "v"(rq[3]), "v"(cq[0]), "v"(cq[1]), "v"(cq[2]),
+                       "v"(cq[3]));
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint64_t bend = oq[e] + cq[e];
+        if (bq[e] >= 0 && bend <= capacity) list[front ? oq[e] + rq[e] : bend - 1 - rq[e]] = t[r];
+      }
+      left -= 4;
+    }
   }
 }
 
