@@ -465,7 +465,7 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
     unsigned long long* __restrict__ status, int count_frags) {
   constexpr int kSub = B < 8 ? B : 8;          // sub-tile edge of the depth bound
   constexpr int kNs = B / kSub;                // sub-tiles per row
-  __shared__ unsigned long long tile[B * B];
+  __shared__ __align__(16) unsigned long long tile[B * B];
   __shared__ unsigned long long smax[kNs * kNs];
   __shared__ int32_t queue[2 * kRasterThreads];   // back-facing triangles that may lower a key
   __shared__ uint32_t qn;
@@ -486,7 +486,8 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
   const int x0 = tx * B, y0 = ty * B;
   const int x1 = min(x0 + B, W) - 1, y1 = min(y0 + B, H) - 1;
   const int tid = threadIdx.x, lane = tid & 63;
-  for (int p = tid; p < B * B; p += kRasterThreads) tile[p] = kEmpty;
+  for (int p = tid; p < B * B / 2; p += kRasterThreads)   // 16-byte stores
+    reinterpret_cast<ulonglong2*>(tile)[p] = make_ulonglong2(kEmpty, kEmpty);
   const ProjVert* P = proj + (int64_t)v * vpv + L.vert_off[l];
   const int32_t* tri = L.tri[l];
   const int32_t nvert = L.n_vert[l];
@@ -575,12 +576,26 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
     draw(c < n_front ? (overflow ? (int32_t)c : lst[c]) : -1);
   }
   if (n_front < n) {   // uniform: back-facing entries follow
-    for (int s = tid; s < kNs * kNs; s += kRasterThreads) smax[s] = 0ull;
     if (tid == 0) qn = 0;
     __syncthreads();
-    for (int p = tid; p < B * B; p += kRasterThreads) {
-      const int sx = (p % B) / kSub, sy = (p / B) / kSub;
-      atomicMax(&smax[sy * kNs + sx], tile[p]);
+    {
+      // sub-tile maxima without LDS atomics: the kThr consecutive lanes of a sub-tile
+      // each take kPer of its keys (whole row pieces) and combine by lane exchange
+      constexpr int kPer = B * B >= kRasterThreads ? B * B / kRasterThreads : 1;   // keys per thread
+      constexpr int kThr = kSub * kSub / kPer;                                     // threads per sub-tile
+      if (tid < B * B / kPer) {   // whole wavefronts
+        const int sub = tid / kThr, u = tid % kThr;
+        const int sx = sub % kNs, sy = sub / kNs;
+        unsigned long long m = 0ull;
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+          const int kk = u * kPer + e;
+          m = max(m, tile[(sy * kSub + kk / kSub) * B + sx * kSub + kk % kSub]);
+        }
+#pragma unroll
+        for (int off = kThr / 2; off > 0; off >>= 1) m = max(m, (unsigned long long)__shfl_xor(m, off));
+        if (u == 0) smax[sub] = m;
+      }
     }
     __syncthreads();
     // phase 2: each back-facing entry is tested from its record (box and depth bound) alone;
