@@ -267,7 +267,14 @@ __device__ inline int32_t abs_index(int32_t r, int32_t d, int32_t n, int wrap) {
   return i;
 }
 
-constexpr int kWaveWin = 384;     // texels in each wavefront's LDS gradient window
+// Texels in each wavefront's LDS gradient window, and blocks per CU, by the
+// largest layer count of the instantiation: up to 8 layers the kernel fits 80
+// registers, so six blocks of 320-texel windows (25 KiB each) share a CU; with
+// more layers the registers allow five, and the window takes the LDS left.
+template <int KMAX> struct BwdShape {
+  static constexpr int win = KMAX <= 8 ? 320 : 384;
+  static constexpr int blocks = KMAX <= 8 ? 6 : KMAX <= 9 ? 5 : 2;
+};
 constexpr bool kMergeX2 = true;   // third butterfly step (x +- 2) before the window
 
 // Value of v in lane (lane ^ 1), (lane ^ 2) or (lane ^ 4), with DPP (no LDS):
@@ -328,13 +335,12 @@ __device__ inline void merge_by_key(int32_t& key, float (&v)[16], int lane) {
 // adds zero).  A footprint larger than the window is retried per half
 // wavefront, then per quarter; a quarter that still does not fit uses direct
 // global atomics.
-// The window holds 384 texels: with 256 texels 4 % of the layer-wavefronts at
-// 1024^2 views and 7 % at 800^2 did not fit (and fell back to 16 uncoalesced
-// atomics per lane); 384 texels take 30 KiB of LDS per block, so five blocks fit a CU,
-// and the register budget is held to that (about twenty resident wavefronts per CU hide
-// the gather latency of the forward recompute; four blocks per CU measured 10 % slower).
+// Window size against occupancy (k = 7, 64 views): 384 texels at five blocks per
+// CU took 7.86 ms at 1024^2 and 5.42 ms at 800^2; 320 texels at six blocks 7.32 and
+// 5.26 ms; 256 texels at six blocks 7.66 and 5.64 ms (more footprints overflow to the
+// half and quarter retries).  Four blocks per CU measured 10 % slower than five.
 template <int KMAX>
-__global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 2) k_shade_bwd(const vs_view* __restrict__ views, int n_views,
+__global__ void __launch_bounds__(256, BwdShape<KMAX>::blocks) k_shade_bwd(const vs_view* __restrict__ views, int n_views,
                                                    const int32_t* __restrict__ tile_view, int64_t n_tiles,
                                                    LayerTable L, TexTable X, const ProjVert* __restrict__ proj,
                                                    int64_t vpv, const uint64_t* __restrict__ vis,
@@ -345,6 +351,7 @@ __global__ void __launch_bounds__(256, KMAX <= 9 ? 5 : 2) k_shade_bwd(const vs_v
                                                    float eps_T, unsigned long long* __restrict__ status,
                                                    int count_paths) {
 #pragma clang fp contract(fast)
+  constexpr int kWaveWin = BwdShape<KMAX>::win;
   __shared__ __align__(16) float win_all[4][kWaveWin * 5];   // per wave: RGBA sums, then the owner words
   __shared__ double sred[4];
   const TileCoord c = shade_tile_coord(views, n_views, tile_view, n_tiles);
