@@ -338,7 +338,9 @@ __device__ inline void merge_by_key(int32_t& key, float (&v)[16], int lane) {
 // Window size against occupancy (k = 7, 64 views): 384 texels at five blocks per
 // CU took 7.86 ms at 1024^2 and 5.42 ms at 800^2; 320 texels at six blocks 7.32 and
 // 5.26 ms; 256 texels at six blocks 7.66 and 5.64 ms (more footprints overflow to the
-// half and quarter retries).  Four blocks per CU measured 10 % slower than five.
+// half and quarter retries); 272 texels at seven blocks (72 registers, 7 spilled) 7.29
+// and 5.44 ms; 240 texels at eight (64 registers, 13 spilled) 7.41 and 5.70 ms.  Four
+// blocks per CU measured 10 % slower than five.
 template <int KMAX>
 __global__ void __launch_bounds__(256, BwdShape<KMAX>::blocks) k_shade_bwd(const vs_view* __restrict__ views, int n_views,
                                                    const int32_t* __restrict__ tile_view, int64_t n_tiles,
