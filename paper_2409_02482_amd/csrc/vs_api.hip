@@ -278,13 +278,14 @@ vs_status vs_raster_layers(const vs_mesh* layers, int32_t k, const vs_views* vie
                      bin_view, lay.n_tiles_bin, slot);
   hipLaunchKernelGGL(vs::k_fill_u32, dim3(fill_grid), dim3(256), 0, s, count, lay.n_bins, 0u);
   hipLaunchKernelGGL(vs::k_fill_u32, dim3(fill_grid), dim3(256), 0, s, cursor, 2 * lay.n_bins, 0u);
-  const dim3 bin_grid(vs::bin_grid_x(L.tri_pad[k]), (unsigned)nv);
+  const dim3 count_grid(vs::bin_grid_x<vs::kCountReps>(L.tri_pad[k]), (unsigned)nv);
+  const dim3 scatter_grid(vs::bin_grid_x<vs::kScatterReps>(L.tri_pad[k]), (unsigned)nv);
   auto bin_count = [&](auto kern) {
-    hipLaunchKernelGGL(kern, bin_grid, dim3(256), 0, s, views->dev, L, (const vs::ProjVert*)proj, vpv, slot, count,
+    hipLaunchKernelGGL(kern, count_grid, dim3(256), 0, s, views->dev, L, (const vs::ProjVert*)proj, vpv, slot, count,
                        spans, status);
   };
   auto bin_scatter = [&](auto kern) {
-    hipLaunchKernelGGL(kern, bin_grid, dim3(256), 0, s, views->dev, L, slot, (const vs::SpanRec*)spans,
+    hipLaunchKernelGGL(kern, scatter_grid, dim3(256), 0, s, views->dev, L, slot, (const vs::SpanRec*)spans,
                        (const uint32_t*)count, (const uint64_t*)offset, cursor, list, lay.capacity);
   };
   switch (B) {

@@ -98,15 +98,21 @@ __device__ inline void unpack_box(uint64_t b, int& i0, int& i1, int& j0, int& j1
 }
 
 // Triangles per thread in the count and scatter launches: each thread has the
-// loads of both in flight before it uses either (two halved the metric scene's
-// count time against one; four cost more registers than they hid latency).
-constexpr int kBinReps = 2;
+// loads (and the scatter's reservations) of all of them in flight before it
+// uses any.  Count: two cut the metric scene's count time by 17 % against one;
+// four (97 registers) were slower.  Scatter, which waits on its returning
+// atomics: four (68 registers) took 0.87 ms against 0.94 ms for two (k = 9
+// scene: 2.20 against 2.57 ms).
+constexpr int kCountReps = 2;
+constexpr int kScatterReps = 4;
 
-// Grid of a count/scatter launch: x = blocks of kBinReps x 256 padded triangles
-// of one view (each layer's range rounded up to 64, so that a wavefront never
-// spans two layers), rounded up to a multiple of the XCD count; y = view.
+// Grid of a count/scatter launch with R triangles per thread: x = blocks of
+// R x 256 padded triangles of one view (each layer's range rounded up to 64,
+// so that a wavefront never spans two layers), rounded up to a multiple of
+// the XCD count; y = view.
+template <int R>
 __host__ __device__ inline uint32_t bin_grid_x(int64_t n_tri_padded) {
-  return (uint32_t)((((n_tri_padded + 255) / 256 + kBinReps - 1) / kBinReps + 7) / 8 * 8);
+  return (uint32_t)((((n_tri_padded + 255) / 256 + R - 1) / R + 7) / 8 * 8);
 }
 
 // Block of 256 padded triangles that repetition r of this block handles.
@@ -114,9 +120,10 @@ __host__ __device__ inline uint32_t bin_grid_x(int64_t n_tri_padded) {
 // 8, so blockIdx.x % 8 is the XCD: the remap gives each XCD a contiguous
 // eighth of the view's triangles (triangles that share vertices share that
 // XCD's L2).
+template <int R>
 __device__ inline uint32_t bin_block(int r) {
   const uint32_t chunk = gridDim.x >> 3;
-  return ((blockIdx.x & 7u) * chunk + (blockIdx.x >> 3)) * kBinReps + r;
+  return ((blockIdx.x & 7u) * chunk + (blockIdx.x >> 3)) * R + r;
 }
 
 // Which (layer, triangle) of view blockIdx.y this thread handles in block vb;
@@ -153,7 +160,7 @@ __global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ v
                                                    const ProjVert* __restrict__ proj, int64_t vpv, int slot,
                                                    uint32_t* __restrict__ count, SpanRec* __restrict__ spans,
                                                    unsigned long long* __restrict__ status) {
-  constexpr int R = kBinReps;
+  constexpr int R = kCountReps;
   const int v = blockIdx.y;
   const int k = L.k;
   const vs_view& V = views[v];
@@ -171,7 +178,7 @@ __global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ v
   // ids of every repetition, then their vertices: all loads in flight before any use
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    ok[r] = bin_thread(L, bin_block(r), l[r], t[r], g[r]);
+    ok[r] = bin_thread(L, bin_block<R>(r), l[r], t[r], g[r]);
     ids[r] = make_int3(0, 0, 0);
     if (ok[r]) ids[r] = load_ids(L.tri[l[r]] + 3 * (int64_t)t[r]);
   }
@@ -307,7 +314,7 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__
                                                      const uint64_t* __restrict__ offset,
                                                      uint32_t* __restrict__ cursor, int32_t* __restrict__ list,
                                                      uint64_t capacity) {
-  constexpr int R = kBinReps;
+  constexpr int R = kScatterReps;
   const int v = blockIdx.y;
   const int k = L.k;
   const vs_view& V = views[v];
@@ -326,7 +333,7 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__
   uint64_t span[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    ok[r] = bin_thread(L, bin_block(r), l[r], t[r], g[r]);
+    ok[r] = bin_thread(L, bin_block<R>(r), l[r], t[r], g[r]);
     span[r] = ok[r] ? sview[g[r]].box : 0ull;
   }
   // per repetition: the first bin's (bin, side) class, the elected lane of each
