@@ -110,7 +110,7 @@ typedef struct vs_camera {
 typedef struct vs_view {
   vs_camera cam;
   int64_t pix_offset;         /* sum_{u<v} W_u H_u */
-  int64_t tile_offset[4];     /* sum_{u<v} ceil(W_u/S) ceil(H_u/S) for S = 8, 16, 32, 64 */
+  int64_t tile_offset[4];     /* sum_{u<v} ceil(W_u/Sw) ceil(H_u/Sh) for Sw x Sh = 8x8, 16x16, 32x32, 64x56 */
 } vs_view;
 
 /* The views of one batched call: host and device copies of the same
@@ -121,8 +121,9 @@ typedef struct vs_views {
   int32_t n_views;
 } vs_views;
 
-/* Raster options.  bin: screen-tile edge in pixels, one of 8, 16, 32, 64, or
- * 0 for the library default; the result is bit-identical for every value.
+/* Raster options.  bin: screen-tile width in pixels, one of 8, 16, 32, 64, or
+ * 0 for the library default (64); tiles are square except the 64-pixel ones,
+ * which are 56 rows high.  The result is bit-identical for every value.
  * The workspace must have been sized for the same bin value.
  * flags: VS_RASTER_COUNT_FRAGMENTS counts covered (triangle, pixel) pairs in
  * the status block (costs extra atomics); VS_RASTER_DIRECT uses the unbinned

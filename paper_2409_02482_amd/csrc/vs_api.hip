@@ -47,7 +47,10 @@ vs_status check_launch(const char* what) {
   return VS_OK;
 }
 
-const int kTileSizes[4] = {8, 16, 32, 64};
+// Tile sizes of the four tile_offset slots: 16-pixel tiles shade, and the raster bins
+// of size B are B wide and vs::bin_rows(B) high.
+const int kTileW[4] = {8, 16, 32, 64};
+const int kTileH[4] = {vs::bin_rows(8), vs::bin_rows(16), vs::bin_rows(32), vs::bin_rows(64)};
 
 vs_status check_camera(const vs_camera& c, int v) {
   if (c.width < 1 || c.height < 1 || c.width > VS_MAX_VIEW_DIM || c.height > VS_MAX_VIEW_DIM)
@@ -77,10 +80,8 @@ vs_status check_views(const vs_views* views) {
     vs_status st = check_camera(r.cam, v);
     if (st) return st;
     pix += (int64_t)r.cam.width * r.cam.height;
-    for (int s = 0; s < 4; ++s) {
-      const int S = kTileSizes[s];
-      tiles[s] += (int64_t)((r.cam.width + S - 1) / S) * ((r.cam.height + S - 1) / S);
-    }
+    for (int s = 0; s < 4; ++s)
+      tiles[s] += (int64_t)((r.cam.width + kTileW[s] - 1) / kTileW[s]) * ((r.cam.height + kTileH[s] - 1) / kTileH[s]);
   }
   return VS_OK;
 }
@@ -209,10 +210,9 @@ vs_status vs_views_prepare(const vs_camera* cams, int32_t n_views, vs_view* out)
     for (int s = 0; s < 4; ++s) r.tile_offset[s] = tiles[s];
     if (v == n_views) break;
     pix += (int64_t)cams[v].width * cams[v].height;
-    for (int s = 0; s < 4; ++s) {
-      const int S = kTileSizes[s];
-      tiles[s] += (int64_t)((cams[v].width + S - 1) / S) * ((cams[v].height + S - 1) / S);
-    }
+    for (int s = 0; s < 4; ++s)
+      tiles[s] += (int64_t)((cams[v].width + kTileW[s] - 1) / kTileW[s]) *
+                  ((cams[v].height + kTileH[s] - 1) / kTileH[s]);
   }
   return ok();
 }

@@ -24,6 +24,11 @@
 namespace vs {
 
 constexpr int kRasterThreads = 256;
+
+// Bins are B pixels wide and bin_rows(B) high: 64-pixel bins are 56 rows high,
+// so that a block's 64-bit key tile (28 KiB) and back-face queue leave room for
+// five blocks per CU (a 64 x 64 tile alone, 32 KiB, fits only four).
+__host__ __device__ constexpr int bin_rows(int B) { return B == 64 ? 56 : B; }
 constexpr int kSmallSpan = 16384;   // small-triangle path: bbox extents <= 64 px, so edge values fit int32
 constexpr int kSmallArea = 256;     // ... and at most this many candidate pixels in the tile
 
@@ -161,6 +166,7 @@ __global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ v
                                                    uint32_t* __restrict__ count, SpanRec* __restrict__ spans,
                                                    unsigned long long* __restrict__ status) {
   constexpr int R = kCountReps;
+  constexpr int BH = bin_rows(B);
   const int v = blockIdx.y;
   const int k = L.k;
   const vs_view& V = views[v];
@@ -209,7 +215,7 @@ __global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ v
         if (pr.i0 > pr.i1 || pr.j0 > pr.j1) {
           live = false;
         } else {
-          tx0 = pr.i0 / B; tx1 = pr.i1 / B; ty0 = pr.j0 / B; ty1 = pr.j1 / B;
+          tx0 = pr.i0 / B; tx1 = pr.i1 / B; ty0 = pr.j0 / BH; ty1 = pr.j1 / BH;
           span.box = pack_box(pr.i0, pr.i1, pr.j0, pr.j1, T.orig_sign < 0);
           span.zlo = (uint32_t)(depth_lower_key(T, (uint32_t)t[r]) >> 32);
         }
@@ -315,6 +321,7 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__
                                                      uint32_t* __restrict__ cursor, int32_t* __restrict__ list,
                                                      uint64_t capacity) {
   constexpr int R = kScatterReps;
+  constexpr int BH = bin_rows(B);
   const int v = blockIdx.y;
   const int k = L.k;
   const vs_view& V = views[v];
@@ -348,7 +355,7 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__
     if (ok[r]) {
       int i0, i1, j0, j1;
       unpack_box(span[r], i0, i1, j0, j1);
-      b0[r] = ((j0 / B) * ntx + i0 / B) * k + l[r];
+      b0[r] = ((j0 / BH) * ntx + i0 / B) * k + l[r];
     }
     c0[r] = ok[r] ? 2 * b0[r] + ((span[r] & kSpanFront) ? 0 : 1) : -1;
     uint64_t active = __ballot(c0[r] >= 0);
@@ -395,7 +402,7 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__
     // are all in flight before any entry is written
     int i0, i1, j0, j1;
     unpack_box(span[r], i0, i1, j0, j1);
-    const int tx0 = i0 / B, tx1 = i1 / B, ty0 = j0 / B, ty1 = j1 / B;
+    const int tx0 = i0 / B, tx1 = i1 / B, ty0 = j0 / BH, ty1 = j1 / BH;
     int tx = tx0, ty = ty0;   // the bin before the next one to take
     int left = (tx1 - tx0 + 1) * (ty1 - ty0 + 1) - 1;
     while (left > 0) {
@@ -449,7 +456,7 @@ __global__ void __launch_bounds__(256) k_tile_view_slot(const vs_view* __restric
 // One block per bin.  Small triangles (bounding box <= 64 px on each side and
 // few candidate pixels) are walked by one lane with exact int32 edge values;
 // larger ones are tested by the lane's whole wavefront, each lane owning
-// B*B/64 pixels, with exact FP64 edge values.  Wavefronts work independently
+// B*bin_rows(B)/64 pixels, with exact FP64 edge values.  Wavefronts work independently
 // on the LDS tile (64-bit atomic minimum).
 //
 // The bin's list holds its front-facing triangles first.  They are drawn
@@ -470,10 +477,12 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
     const uint64_t* __restrict__ offset, const uint32_t* __restrict__ cursor, const int32_t* __restrict__ list,
     const SpanRec* __restrict__ spans, uint64_t capacity, unsigned long long* __restrict__ vis,
     unsigned long long* __restrict__ status, int count_frags) {
+  constexpr int BH = bin_rows(B);              // bin rows
   constexpr int kSub = B < 8 ? B : 8;          // sub-tile edge of the depth bound
   constexpr int kNs = B / kSub;                // sub-tiles per row
-  __shared__ __align__(16) unsigned long long tile[B * B];
-  __shared__ unsigned long long smax[kNs * kNs];
+  constexpr int kNsY = BH / kSub;              // sub-tile rows
+  __shared__ __align__(16) unsigned long long tile[B * BH];
+  __shared__ unsigned long long smax[kNs * kNsY];
   __shared__ int32_t queue[2 * kRasterThreads];   // back-facing triangles that may lower a key
   __shared__ uint32_t qn;
   const int k = L.k;
@@ -490,10 +499,10 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
   const int ntx = (W + B - 1) / B;
   const int64_t tl = g - V.tile_offset[slot];
   const int ty = (int)(tl / ntx), tx = (int)(tl - (int64_t)ty * ntx);
-  const int x0 = tx * B, y0 = ty * B;
-  const int x1 = min(x0 + B, W) - 1, y1 = min(y0 + B, H) - 1;
+  const int x0 = tx * B, y0 = ty * BH;
+  const int x1 = min(x0 + B, W) - 1, y1 = min(y0 + BH, H) - 1;
   const int tid = threadIdx.x, lane = tid & 63;
-  for (int p = tid; p < B * B / 2; p += kRasterThreads)   // 16-byte stores
+  for (int p = tid; p < B * BH / 2; p += kRasterThreads)   // 16-byte stores
     reinterpret_cast<ulonglong2*>(tile)[p] = make_ulonglong2(kEmpty, kEmpty);
   const ProjVert* P = proj + (int64_t)v * vpv + L.vert_off[l];
   const int32_t* tri = L.tri[l];
@@ -557,7 +566,7 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
       TriSetup Tb;
       setup_triangle(tri + 3 * (int64_t)t, nvert, P, Tb);
       const unsigned long long lbkey = depth_lower_key(Tb, (uint32_t)t);
-      for (int p = lane; p < B * B; p += 64) {
+      for (int p = lane; p < B * BH; p += 64) {
         const int i = x0 + (p % B), j = y0 + (p / B);
         if (i > x1 || j > y1) continue;
         double E[3];
@@ -588,9 +597,11 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
     {
       // sub-tile maxima without LDS atomics: the kThr consecutive lanes of a sub-tile
       // each take kPer of its keys (whole row pieces) and combine by lane exchange
-      constexpr int kPer = B * B >= kRasterThreads ? B * B / kRasterThreads : 1;   // keys per thread
-      constexpr int kThr = kSub * kSub / kPer;                                     // threads per sub-tile
-      if (tid < B * B / kPer) {   // whole wavefronts
+      constexpr int kSubs = kNs * kNsY;
+      constexpr int kThr = kSubs * 64 <= kRasterThreads ? 64 : kSubs * 16 <= kRasterThreads ? 16 : 4;   // per sub-tile
+      constexpr int kPer = kSub * kSub / kThr;                                                          // keys per thread
+      static_assert(kSubs * kThr <= kRasterThreads && kSub * kSub % kThr == 0, "sub-tile reduction shape");
+      if (tid < kSubs * kThr) {   // whole wavefronts
         const int sub = tid / kThr, u = tid % kThr;
         const int sx = sub % kNs, sy = sub / kNs;
         unsigned long long m = 0ull;
@@ -652,7 +663,7 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
   __syncthreads();
   // coalesced store of the finished tile
   unsigned long long* plane = vis + (int64_t)k * V.pix_offset + (int64_t)l * W * H;
-  for (int p = tid; p < B * B; p += kRasterThreads) {
+  for (int p = tid; p < B * BH; p += kRasterThreads) {
     const int i = x0 + (p % B), j = y0 + (p / B);
     if (i <= x1 && j <= y1) plane[(int64_t)j * W + i] = tile[p];
   }

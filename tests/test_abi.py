@@ -82,7 +82,8 @@ def test_views_prepare_offsets(C):
         assert out[v].pix_offset == pix
         assert list(out[v].tile_offset) == tiles
         pix += w * h
-        tiles = [t + (-(-w // s)) * (-(-h // s)) for t, s in zip(tiles, (8, 16, 32, 64))]
+        # tiles of the four slots: 8x8, 16x16, 32x32 and the 64 x 56 raster bins
+        tiles = [t + (-(-w // sw)) * (-(-h // sh)) for t, sw, sh in zip(tiles, (8, 16, 32, 64), (8, 16, 32, 56))]
     assert out[0].cam.width == 512 and abs(out[3].cam.fy - cams[3].fy) == 0
 
 
