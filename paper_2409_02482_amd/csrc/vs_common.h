@@ -52,7 +52,7 @@ struct alignas(16) ProjVert {
 struct WsLayout {
   size_t status;     // VS_STAT_COUNT u64 counters
   size_t tile_view;  // int32 [16-pixel tiles of all views]: owning view (shading)
-  size_t bin_view;   // int32 [B-pixel tiles of all views]: owning view (raster bins)
+  size_t bin_view;   // int32 [raster bin tiles of all views]: owning view
   size_t proj;       // ProjVert [n_views][sum n_vert]
   size_t count;      // u32 [n_bins] triangles per bin
   size_t offset;     // u64 [n_bins] exclusive prefix of count

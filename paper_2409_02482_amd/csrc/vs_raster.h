@@ -4,7 +4,7 @@
 // Binned pipeline (one call of vs_raster_layers):
 //   k_project      snapped screen positions and w = 1/z for every (view, layer, vertex)
 //   k_bin_count    per triangle: setup, cull, bounding box -> screen tiles of
-//                  B x B pixels; count triangles per bin = (view, tile, layer)
+//                  B x bin_rows(B) pixels; count triangles per bin = (view, tile, layer)
 //                  and record the triangle's packed tile span
 //   k_scan_*       exclusive prefix sum of the counts -> list offsets
 //   k_bin_scatter  write triangle ids into the bin lists (front faces first)
