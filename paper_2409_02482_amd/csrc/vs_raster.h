@@ -665,11 +665,25 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
     }
   }
   __syncthreads();
-  // coalesced store of the finished tile
+  // coalesced store of the finished tile: pairs of keys as 16-byte stores when
+  // every row of the bin starts 16-byte aligned (even view width and plane
+  // start; x0 is even), single keys otherwise
   unsigned long long* plane = vis + (int64_t)k * V.pix_offset + (int64_t)l * W * H;
-  for (int p = tid; p < B * BH; p += kRasterThreads) {
-    const int i = x0 + (p % B), j = y0 + (p / B);
-    if (i <= x1 && j <= y1) plane[(int64_t)j * W + i] = tile[p];
+  if (B >= 2 && (W & 1) == 0 && (reinterpret_cast<uintptr_t>(plane) & 15) == 0) {   // uniform
+    const ulonglong2* tile2 = reinterpret_cast<const ulonglong2*>(tile);
+    for (int p = tid; p < B * BH / 2; p += kRasterThreads) {
+      const int i = x0 + (2 * p) % B, j = y0 + (2 * p) / B;
+      if (j > y1) continue;
+      const ulonglong2 kv = tile2[p];
+      unsigned long long* dst = plane + (int64_t)j * W + i;
+      if (i + 1 <= x1) *reinterpret_cast<ulonglong2*>(dst) = kv;   // x1 - x0 + 1 is even unless W ends the row
+      else if (i <= x1) dst[0] = kv.x;
+    }
+  } else {
+    for (int p = tid; p < B * BH; p += kRasterThreads) {
+      const int i = x0 + (p % B), j = y0 + (p / B);
+      if (i <= x1 && j <= y1) plane[(int64_t)j * W + i] = tile[p];
+    }
   }
   if (count_frags) {
     for (int off = 32; off > 0; off >>= 1) frags += __shfl_xor(frags, off);
