@@ -74,17 +74,19 @@ enum {
 #define VS_MAX_LAYERS 16
 #define VS_MAX_VIEW_DIM 8192
 #define VS_MAX_TEX_DIM 16384
+#define VS_MAX_LAYER_ELEMS (1 << 28)   /* vertices, and triangles, of one layer (32-bit byte offsets) */
 #define VS_EMPTY 0xFFFFFFFFFFFFFFFFull
 
 /* One shell.  Device pointers.  xyz f32 [n_vert][3] world positions,
- * uv f32 [n_vert][2], tri i32 [n_tri][3] vertex ids.  1 <= n_tri < 2^31 and
- * n_vert >= 1: a layer without triangles or vertices is rejected (VS_ERR_SIZE). */
+ * uv f32 [n_vert][2], tri i32 [n_tri][3] vertex ids.  1 <= n_vert, n_tri <=
+ * VS_MAX_LAYER_ELEMS: an empty layer, or a larger one, is rejected
+ * (VS_ERR_SIZE). */
 typedef struct vs_mesh {
   const float* xyz;
   const float* uv;
   const int32_t* tri;
-  int32_t n_vert;
-  int32_t n_tri;
+  int32_t n_vert;             /* 1..VS_MAX_LAYER_ELEMS */
+  int32_t n_tri;              /* 1..VS_MAX_LAYER_ELEMS */
 } vs_mesh;
 
 /* One layer texture.  Device pointer, f32 [height][width][4] straight RGBA. */

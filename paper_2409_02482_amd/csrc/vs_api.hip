@@ -95,6 +95,8 @@ vs_status build_layers(const vs_mesh* layers, int32_t k, vs::LayerTable& L) {
     const vs_mesh& m = layers[l];
     if (!m.xyz || !m.uv || !m.tri) return fail(VS_ERR_ARG, "layer %d: null mesh pointer", l);
     if (m.n_vert < 1 || m.n_tri < 1) return fail(VS_ERR_SIZE, "layer %d: empty mesh", l);
+    if (m.n_vert > VS_MAX_LAYER_ELEMS || m.n_tri > VS_MAX_LAYER_ELEMS)
+      return fail(VS_ERR_SIZE, "layer %d: more than %d vertices or triangles", l, VS_MAX_LAYER_ELEMS);
     L.xyz[l] = m.xyz;
     L.uv[l] = m.uv;
     L.tri[l] = m.tri;

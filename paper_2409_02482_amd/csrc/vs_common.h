@@ -123,12 +123,24 @@ struct TriLoad {
   bool bad;
 };
 
-__device__ inline int3 load_ids(const int32_t* ids) { return *reinterpret_cast<const int3*>(ids); }
+// Element e of a per-layer array, addressed as a 32-bit byte offset from the
+// (uniform) array base: a layer holds at most VS_MAX_LAYER_ELEMS (2^28)
+// vertices and triangles, so 16-byte vertex records and 12-byte triangles stay
+// below 2^32 bytes, and the loads need no per-lane 64-bit address arithmetic.
+template <typename T>
+__device__ inline T elem_at(const void* base, uint32_t e) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (size_t)(e * (uint32_t)sizeof(T)));
+}
+
+// The three vertex ids of triangle t of a layer.
+__device__ inline int3 load_ids(const int32_t* tri, uint32_t t) { return elem_at<int3>(tri, t); }
 
 __device__ inline void load_vertices(int3 ids, int32_t n_vert, const ProjVert* pv, TriLoad& r) {
   r.id[0] = ids.x; r.id[1] = ids.y; r.id[2] = ids.z;
   r.bad = (uint32_t)ids.x >= (uint32_t)n_vert || (uint32_t)ids.y >= (uint32_t)n_vert ||
           (uint32_t)ids.z >= (uint32_t)n_vert;
+  // (64-bit addressing here: with 32-bit offsets the bin count kernel, which keeps
+  // two triangles' records live, needed 66 instead of 50 registers)
   r.a = *reinterpret_cast<const int4*>(pv + (r.bad ? 0 : ids.x));
   r.b = *reinterpret_cast<const int4*>(pv + (r.bad ? 0 : ids.y));
   r.c = *reinterpret_cast<const int4*>(pv + (r.bad ? 0 : ids.z));
@@ -168,11 +180,11 @@ __device__ inline int setup_loaded(const TriLoad& q, TriSetup& T) {
   return q.bad ? kTriBadIndex : invalid ? kTriInvalid : area2 == 0.0 ? kTriDegenerate : kTriOk;
 }
 
-// ids are the three vertex ids of the triangle; pv the projected vertices of
-// its layer in this view.
-__device__ inline int setup_triangle(const int32_t* ids, int32_t n_vert, const ProjVert* pv, TriSetup& T) {
+// Triangle t of a layer (tri: its triangles); pv the projected vertices of
+// the layer in this view.
+__device__ inline int setup_triangle(const int32_t* tri, uint32_t t, int32_t n_vert, const ProjVert* pv, TriSetup& T) {
   TriLoad q;
-  load_vertices(load_ids(ids), n_vert, pv, q);
+  load_vertices(load_ids(tri, t), n_vert, pv, q);
   return setup_loaded(q, T);
 }
 

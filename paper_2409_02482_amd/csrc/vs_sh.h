@@ -59,7 +59,7 @@ __device__ inline float sigmoidf(float x) { return 1.0f / (1.0f + __expf(-x)); }
 // Unit face normal of triangle t (world space), dotted with the unit ray d: |d.n|.
 __device__ inline float abs_cos_face(const float* __restrict__ xyz, const int32_t* __restrict__ tri, uint32_t t,
                                      float dx, float dy, float dz) {
-  const Tri3 id = reinterpret_cast<const Tri3*>(tri)[t];
+  const Tri3 id = elem_at<Tri3>(tri, t);
   const float ax = xyz[3 * id.a], ay = xyz[3 * id.a + 1], az = xyz[3 * id.a + 2];
   const float e1x = xyz[3 * id.b] - ax, e1y = xyz[3 * id.b + 1] - ay, e1z = xyz[3 * id.b + 2] - az;
   const float e2x = xyz[3 * id.c] - ax, e2y = xyz[3 * id.c + 1] - ay, e2z = xyz[3 * id.c + 2] - az;

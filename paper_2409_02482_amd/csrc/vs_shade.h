@@ -53,12 +53,26 @@ __device__ inline int32_t next_index(int32_t i0, int32_t n, int wrap) {
   return wrap == kWrapClamp ? (i0 + 1 < n ? i0 + 1 : n - 1) : (i0 + 1 == n ? 0 : i0 + 1);
 }
 
+// Texel idx of a texture and float idx of a gradient plane, addressed as 32-bit
+// byte offsets from the (uniform) plane base, so that the loads and atomics use
+// a scalar base register and no per-lane 64-bit address arithmetic: a texture
+// has at most 16384^2 texels, whose 16-byte texels and 4-byte gradient floats
+// both stay below 2^32 bytes.
+__device__ inline float4 texel_at(const float4* __restrict__ tex, uint32_t idx) {
+  return *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(tex) + (size_t)(idx << 4));
+}
+
+__device__ inline void grad_add(float* G, uint32_t fidx, float val) {
+  unsafeAtomicAdd(reinterpret_cast<float*>(reinterpret_cast<char*>(G) + (size_t)(fidx << 2)), val);
+}
+
 __device__ inline float4 bilinear(const float4* __restrict__ tex, int32_t W, const Foot& f) {
 #pragma clang fp contract(fast)
-  const float4 t00 = tex[f.j0 * W + f.i0];
-  const float4 t01 = tex[f.j0 * W + f.i1];
-  const float4 t10 = tex[f.j1 * W + f.i0];
-  const float4 t11 = tex[f.j1 * W + f.i1];
+  const uint32_t w = (uint32_t)W, r0 = (uint32_t)f.j0 * w, r1 = (uint32_t)f.j1 * w;
+  const float4 t00 = texel_at(tex, r0 + (uint32_t)f.i0);
+  const float4 t01 = texel_at(tex, r0 + (uint32_t)f.i1);
+  const float4 t10 = texel_at(tex, r1 + (uint32_t)f.i0);
+  const float4 t11 = texel_at(tex, r1 + (uint32_t)f.i1);
   const float gx = 1.0f - f.fx, gy = 1.0f - f.fy;
   const float w00 = gx * gy, w01 = f.fx * gy, w10 = gx * f.fy, w11 = f.fx * f.fy;
   float4 r;
@@ -85,14 +99,16 @@ __device__ inline bool slot_uv(const int32_t* __restrict__ tri, int32_t n_tri, i
     atomicAdd(status + VS_STAT_BAD_KEY, 1ull);
     return false;
   }
-  const Tri3 id = reinterpret_cast<const Tri3*>(tri)[t];
+  const Tri3 id = elem_at<Tri3>(tri, t);
   if ((uint32_t)id.a >= (uint32_t)n_vert || (uint32_t)id.b >= (uint32_t)n_vert ||
       (uint32_t)id.c >= (uint32_t)n_vert) {
     atomicAdd(status + VS_STAT_BAD_KEY, 1ull);
     return false;
   }
-  const ProjVert a = P[id.a], b = P[id.b], c = P[id.c];
-  const float2 ua = uv[id.a], ub = uv[id.b], uc = uv[id.c];
+  const ProjVert a = elem_at<ProjVert>(P, (uint32_t)id.a), b = elem_at<ProjVert>(P, (uint32_t)id.b),
+                 c = elem_at<ProjVert>(P, (uint32_t)id.c);
+  const float2 ua = elem_at<float2>(uv, (uint32_t)id.a), ub = elem_at<float2>(uv, (uint32_t)id.b),
+               uc = elem_at<float2>(uv, (uint32_t)id.c);
   const double ax = a.X, ay = a.Y, bx = b.X, by = b.Y, cx = c.X, cy = c.Y;
   const double E0 = (cx - bx) * (py - by) - (cy - by) * (px - bx);
   const double E1 = (ax - cx) * (py - cy) - (ay - cy) * (px - cx);
@@ -540,13 +556,13 @@ __global__ void __launch_bounds__(256, BwdShape<KMAX>::blocks) k_shade_bwd(const
         const bool flat = bi >= 0 && bi + ww <= Wt && bj >= 0 && bj + wh <= Ht;
         if (rr < R) {
           if (flat) {   // the window does not wrap: plain strided addresses
-            float* gbase = G + ((int64_t)bj * Wt + bi) * 4;
-            const int64_t gstride = (int64_t)Wt * 4;
+            const uint32_t gbase = ((uint32_t)bj * (uint32_t)Wt + (uint32_t)bi) * 4u;
+            const uint32_t gstride = (uint32_t)Wt * 4u;
             for (int32_t y = rr; y < wh; y += R)
               for (int32_t cc = cc0; cc < row; cc += 64) {
                 const float val = win[y * row + cc];
                 win[y * row + cc] = 0.0f;
-                if (val != 0.0f) unsafeAtomicAdd(gbase + y * gstride + cc, val);
+                if (val != 0.0f) grad_add(G, gbase + (uint32_t)y * gstride + (uint32_t)cc, val);
               }
           } else {
             // wrapped (repeat) or outside the texture (clamp: only zeros land there)
@@ -557,7 +573,7 @@ __global__ void __launch_bounds__(256, BwdShape<KMAX>::blocks) k_shade_bwd(const
                 win[y * row + cc] = 0.0f;
                 if (val != 0.0f) {
                   const int32_t ti = abs_index(ri, dmin_i + (cc >> 2), Wt, wrap);
-                  unsafeAtomicAdd(G + ((int64_t)tj * Wt + ti) * 4 + (cc & 3), val);
+                  grad_add(G, ((uint32_t)tj * (uint32_t)Wt + (uint32_t)ti) * 4u + (uint32_t)(cc & 3), val);
                 }
               }
             }
@@ -580,12 +596,13 @@ __global__ void __launch_bounds__(256, BwdShape<KMAX>::blocks) k_shade_bwd(const
     if (__any(direct)) {
       if (direct) {
         const int32_t i1 = next_index(i0, Wt, wrap), j1 = next_index(j0, Ht, wrap);
-        const int64_t q[4] = {((int64_t)j0 * Wt + i0) * 4, ((int64_t)j0 * Wt + i1) * 4,
-                              ((int64_t)j1 * Wt + i0) * 4, ((int64_t)j1 * Wt + i1) * 4};
+        const uint32_t w = (uint32_t)Wt;
+        const uint32_t q[4] = {((uint32_t)j0 * w + (uint32_t)i0) * 4u, ((uint32_t)j0 * w + (uint32_t)i1) * 4u,
+                               ((uint32_t)j1 * w + (uint32_t)i0) * 4u, ((uint32_t)j1 * w + (uint32_t)i1) * 4u};
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
 #pragma unroll
-          for (int ch = 0; ch < 4; ++ch) unsafeAtomicAdd(G + q[n] + ch, v[n * 4 + ch]);
+          for (int ch = 0; ch < 4; ++ch) grad_add(G, q[n] + (uint32_t)ch, v[n * 4 + ch]);
         }
       }
     }

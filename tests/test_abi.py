@@ -145,6 +145,13 @@ def test_raster_validation_without_gpu(C):
                                   None) == C.VS_ERR_SIZE
         assert b"layer 0: empty mesh" in L.vs_last_error()
         meshes[0].n_tri, meshes[0].n_vert = 5, 10
+    # more than 2^28 vertices or triangles in a layer (the kernels address them with 32-bit byte offsets)
+    for field in ("n_tri", "n_vert"):
+        setattr(meshes[0], field, (1 << 28) + 1)
+        assert L.vs_raster_layers(ctypes.addressof(meshes), 2, ctypes.byref(views), 0x5000, 0x100000, need, None,
+                                  None) == C.VS_ERR_SIZE
+        assert b"more than 268435456 vertices or triangles" in L.vs_last_error()
+        meshes[0].n_tri, meshes[0].n_vert = 5, 10
     # a tampered view table
     host[1].pix_offset += 1
     assert L.vs_raster_layers(ctypes.addressof(meshes), 2, ctypes.byref(views), 0x5000, 0x100000, need, None,
