@@ -135,15 +135,25 @@ __device__ inline T elem_at(const void* base, uint32_t e) {
 // The three vertex ids of triangle t of a layer.
 __device__ inline int3 load_ids(const int32_t* tri, uint32_t t) { return elem_at<int3>(tri, t); }
 
+// OFF32: the vertices are addressed as 32-bit byte offsets from pv (a scalar base
+// register, no per-lane 64-bit address arithmetic), else with 64-bit pointer
+// arithmetic.  The raster kernel takes the former (1-3 % faster); the bin count
+// kernel, which keeps two triangles' records live, the latter (with 32-bit
+// offsets it needed 66 instead of 50 registers and ran slower).
+template <bool OFF32 = false>
 __device__ inline void load_vertices(int3 ids, int32_t n_vert, const ProjVert* pv, TriLoad& r) {
   r.id[0] = ids.x; r.id[1] = ids.y; r.id[2] = ids.z;
   r.bad = (uint32_t)ids.x >= (uint32_t)n_vert || (uint32_t)ids.y >= (uint32_t)n_vert ||
           (uint32_t)ids.z >= (uint32_t)n_vert;
-  // (64-bit addressing here: with 32-bit offsets the bin count kernel, which keeps
-  // two triangles' records live, needed 66 instead of 50 registers)
-  r.a = *reinterpret_cast<const int4*>(pv + (r.bad ? 0 : ids.x));
-  r.b = *reinterpret_cast<const int4*>(pv + (r.bad ? 0 : ids.y));
-  r.c = *reinterpret_cast<const int4*>(pv + (r.bad ? 0 : ids.z));
+  if (OFF32) {
+    r.a = elem_at<int4>(pv, r.bad ? 0u : (uint32_t)ids.x);
+    r.b = elem_at<int4>(pv, r.bad ? 0u : (uint32_t)ids.y);
+    r.c = elem_at<int4>(pv, r.bad ? 0u : (uint32_t)ids.z);
+  } else {
+    r.a = *reinterpret_cast<const int4*>(pv + (r.bad ? 0 : ids.x));
+    r.b = *reinterpret_cast<const int4*>(pv + (r.bad ? 0 : ids.y));
+    r.c = *reinterpret_cast<const int4*>(pv + (r.bad ? 0 : ids.z));
+  }
 }
 
 __device__ inline ProjVert proj_of(int4 r) {
@@ -182,9 +192,10 @@ __device__ inline int setup_loaded(const TriLoad& q, TriSetup& T) {
 
 // Triangle t of a layer (tri: its triangles); pv the projected vertices of
 // the layer in this view.
+template <bool OFF32 = false>
 __device__ inline int setup_triangle(const int32_t* tri, uint32_t t, int32_t n_vert, const ProjVert* pv, TriSetup& T) {
   TriLoad q;
-  load_vertices(load_ids(tri, t), n_vert, pv, q);
+  load_vertices<OFF32>(load_ids(tri, t), n_vert, pv, q);
   return setup_loaded(q, T);
 }
 

@@ -525,7 +525,7 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
   auto draw = [&](int32_t tq) {
     int32_t big = -1;   // a triangle for the whole wavefront
     TriSetup T;
-    if (tq >= 0 && setup_triangle(tri, (uint32_t)tq, nvert, P, T) == kTriOk) {
+    if (tq >= 0 && setup_triangle<true>(tri, (uint32_t)tq, nvert, P, T) == kTriOk) {
       const int32_t t = tq;
       PixRange pr = pixel_range(T, W, H);
       const int ci0 = max(pr.i0, x0), ci1 = min(pr.i1, x1), cj0 = max(pr.j0, y0), cj1 = min(pr.j1, y1);
@@ -568,7 +568,7 @@ __global__ void __launch_bounds__(kRasterThreads) k_raster_bins(
     for (uint64_t bm = __ballot(big >= 0); bm; bm &= bm - 1) {
       const int32_t t = __builtin_amdgcn_readlane(big, __builtin_ctzll(bm));
       TriSetup Tb;
-      setup_triangle(tri, (uint32_t)t, nvert, P, Tb);
+      setup_triangle<true>(tri, (uint32_t)t, nvert, P, Tb);
       const unsigned long long lbkey = depth_lower_key(Tb, (uint32_t)t);
       for (int p = lane; p < B * BH; p += 64) {
         const int i = x0 + (p % B), j = y0 + (p / B);
