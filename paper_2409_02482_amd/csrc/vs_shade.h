@@ -284,12 +284,14 @@ __device__ inline int32_t abs_index(int32_t r, int32_t d, int32_t n, int wrap) {
 }
 
 // Texels in each wavefront's LDS gradient window, and blocks per CU, by the
-// largest layer count of the instantiation: up to 8 layers the kernel fits 80
-// registers, so six blocks of 320-texel windows (25 KiB each) share a CU; with
-// more layers the registers allow five, and the window takes the LDS left.
+// largest layer count of the instantiation: up to 9 layers the kernel is held
+// to 80 registers, so six blocks of 320-texel windows (25 KiB each) share a CU
+// (9 layers spill 4 registers there and still run 2.3 % faster than at five
+// blocks of 384-texel windows: 7.76 against 7.94 ms on the k = 9 scene); the
+// 16-layer instantiation runs two blocks.
 template <int KMAX> struct BwdShape {
-  static constexpr int win = KMAX <= 8 ? 320 : 384;
-  static constexpr int blocks = KMAX <= 8 ? 6 : KMAX <= 9 ? 5 : 2;
+  static constexpr int win = KMAX <= 9 ? 320 : 384;
+  static constexpr int blocks = KMAX <= 9 ? 6 : 2;
 };
 constexpr bool kMergeX2 = true;   // third butterfly step (x +- 2) before the window
 
