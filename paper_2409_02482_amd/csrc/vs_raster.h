@@ -105,13 +105,15 @@ __device__ inline void unpack_box(uint64_t b, int& i0, int& i1, int& j0, int& j1
   i0 = (int)(b & 8191); i1 = (int)((b >> 13) & 8191); j0 = (int)((b >> 26) & 8191); j1 = (int)((b >> 39) & 8191);
 }
 
-// Triangles per thread in the count and scatter launches: each thread has the
-// loads (and the scatter's reservations) of all of them in flight before it
-// uses any.  Count: two cut the metric scene's count time by 17 % against one;
-// four (97 registers) were slower.  Scatter, which waits on its returning
-// atomics: four (68 registers) took 0.87 ms against 0.94 ms for two (k = 9
-// scene: 2.20 against 2.57 ms).
-constexpr int kCountReps = 2;
+// Triangles per thread in the count and scatter launches.  Count: the vertex
+// ids of all four are requested first, then the vertex records two at a time,
+// the next one's loads issued as soon as a record slot is free (0.78 ms on the
+// metric scene against 0.85 ms for two triangles with both records loaded up
+// front; four records loaded up front needed 97 registers and were slower).
+// Scatter, which waits on its returning atomics, has the span reads and
+// reservations of all four in flight together: 0.87 ms against 0.94 ms for
+// two (k = 9 scene: 2.20 against 2.57 ms; eight per thread: no gain).
+constexpr int kCountReps = 4;
 constexpr int kScatterReps = 4;
 
 // Grid of a count/scatter launch with R triangles per thread: x = blocks of
@@ -183,31 +185,34 @@ __global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ v
   int32_t t[R];
   int64_t g[R];
   int3 ids[R];
-  TriLoad q[R];
-  // ids of every repetition, then their vertices: all loads in flight before any use
+  // ids of every repetition first (small); vertex records two at a time, the
+  // next record's loads issued as soon as a record slot is free
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     ok[r] = bin_thread(L, bin_block<R>(r), l[r], t[r], g[r]);
     ids[r] = make_int3(0, 0, 0);
     if (ok[r]) ids[r] = load_ids(L.tri[l[r]], (uint32_t)t[r]);
   }
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
+  auto fetch = [&](int r, TriLoad& q) {
     // defined on every lane: left undefined, the records stay live across the
     // divergent loads and cost about 16 more registers
-    q[r].a = q[r].b = q[r].c = make_int4(0, 0, 0, 0);
-    q[r].id[0] = q[r].id[1] = q[r].id[2] = 0;
-    q[r].bad = false;
-    if (ok[r]) load_vertices(ids[r], L.n_vert[l[r]], pview + L.vert_off[l[r]], q[r]);
-  }
+    q.a = q.b = q.c = make_int4(0, 0, 0, 0);
+    q.id[0] = q.id[1] = q.id[2] = 0;
+    q.bad = false;
+    if (ok[r]) load_vertices(ids[r], L.n_vert[l[r]], pview + L.vert_off[l[r]], q);
+  };
+  TriLoad qa, qb;
+  fetch(0, qa);
+  if (R > 1) fetch(1, qb);
   const int lane = (int)__lane_id();
 #pragma unroll
   for (int r = 0; r < R; ++r) {
+    TriLoad& qr = (r & 1) ? qb : qa;
     int tx0 = 0, tx1 = 0, ty0 = 0, ty1 = 0;
     bool live = ok[r];
     if (live) {
       TriSetup T;
-      const int st = setup_loaded(q[r], T);
+      const int st = setup_loaded(qr, T);
       SpanRec span;
       span.box = 0; span.zlo = 0; span.pad = 0;
       if (st != kTriOk) {
@@ -225,6 +230,7 @@ __global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ v
       }
       sview[g[r]] = span;
     }
+    if (r + 2 < R) fetch(r + 2, qr);   // this record slot is free now
     // first bin of every lane: lanes with the same bin elect one lane (register
     // exchanges only), and all elected lanes add in one atomic instruction
     const int32_t b0 = live ? (ty0 * ntx + tx0) * k + l[r] : -1;
