@@ -284,7 +284,7 @@ vs_status vs_raster_layers(const vs_mesh* layers, int32_t k, const vs_views* vie
   const dim3 scatter_grid(vs::bin_grid_x<vs::kScatterReps>(L.tri_pad[k]), (unsigned)nv);
   auto bin_count = [&](auto kern) {
     hipLaunchKernelGGL(kern, count_grid, dim3(256), 0, s, views->dev, L, (const vs::ProjVert*)proj, vpv, slot, count,
-                       spans, status);
+                       cursor, spans, status);
   };
   auto bin_scatter = [&](auto kern) {
     hipLaunchKernelGGL(kern, scatter_grid, dim3(256), 0, s, views->dev, L, slot, (const vs::SpanRec*)spans,
@@ -296,8 +296,8 @@ vs_status vs_raster_layers(const vs_mesh* layers, int32_t k, const vs_views* vie
     case 32: bin_count(vs::k_bin_count<32>); break;
     default: bin_count(vs::k_bin_count<64>); break;
   }
-  hipLaunchKernelGGL(vs::k_scan_local, dim3((unsigned)lay.n_partial), dim3(256), 0, s, (const uint32_t*)count,
-                     offset, partial, lay.n_bins);
+  hipLaunchKernelGGL(vs::k_scan_local, dim3((unsigned)lay.n_partial), dim3(256), 0, s, count,
+                     (const uint32_t*)cursor, offset, partial, lay.n_bins);
   hipLaunchKernelGGL(vs::k_scan_partials, dim3(1), dim3(1024), 0, s, partial, lay.n_partial);
   hipLaunchKernelGGL(vs::k_scan_add, dim3(grid_1d(lay.n_bins, 256)), dim3(256), 0, s, offset,
                      (const uint64_t*)partial, lay.n_bins);

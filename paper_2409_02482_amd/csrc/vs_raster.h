@@ -4,9 +4,10 @@
 // Binned pipeline (one call of vs_raster_layers):
 //   k_project      snapped screen positions and w = 1/z for every (view, layer, vertex)
 //   k_bin_count    per triangle: setup, cull, bounding box -> screen tiles of
-//                  B x bin_rows(B) pixels; count triangles per bin = (view, tile, layer)
-//                  and record the triangle's packed tile span
-//   k_scan_*       exclusive prefix sum of the counts -> list offsets
+//                  B x bin_rows(B) pixels; reserve the triangle's place in its
+//                  first bin = (view, tile, layer), count it in its other bins,
+//                  and record its packed tile span and place
+//   k_scan_*       exclusive prefix sum of the bins' entry counts -> list offsets
 //   k_bin_scatter  write triangle ids into the bin lists (front faces first)
 //   k_raster_bins  one block per bin: an LDS tile of keys starts EMPTY, the
 //                  bin's triangles take 64-bit LDS minima, and the finished
@@ -93,7 +94,7 @@ constexpr uint64_t kSpanFront = 1ull << 52;
 struct alignas(16) SpanRec {
   uint64_t box;
   uint32_t zlo;    // high word of the triangle's depth lower-bound key
-  uint32_t pad;
+  uint32_t rank;   // entries of the same side of its first bin reserved before it
 };
 
 __device__ inline uint64_t pack_box(int i0, int i1, int j0, int j1, bool front) {
@@ -107,12 +108,13 @@ __device__ inline void unpack_box(uint64_t b, int& i0, int& i1, int& j0, int& j1
 
 // Triangles per thread in the count and scatter launches.  Count: the vertex
 // ids of all four are requested first, then the vertex records two at a time,
-// the next one's loads issued as soon as a record slot is free (0.78 ms on the
-// metric scene against 0.85 ms for two triangles with both records loaded up
-// front; four records loaded up front needed 97 registers and were slower).
-// Scatter, which waits on its returning atomics, has the span reads and
-// reservations of all four in flight together: 0.87 ms against 0.94 ms for
-// two (k = 9 scene: 2.20 against 2.57 ms; eight per thread: no gain).
+// the next one's loads issued as soon as a record slot is free (four records
+// loaded up front needed 97 registers and were slower); the four first-bin
+// reservations are in flight together and the records are written once they
+// return.  Scatter: the records and first-bin list ranges of all four are read
+// together; only a triangle's other bins still take a returning atomic there.
+// Eight per thread in the scatter: 102 registers, metric raster phase 5.00
+// against 4.98 ms, k = 9 scene 7.96 against 7.67 ms.
 constexpr int kCountReps = 4;
 constexpr int kScatterReps = 4;
 
@@ -164,11 +166,13 @@ __device__ inline int64_t view_bins_base(const vs_view& V, int slot, int k) {
   return (int64_t)V.tile_offset[slot] * k;
 }
 
-// Count triangles per bin and record each triangle's box and depth bound.
+// Count triangles per bin and record each triangle's box, depth bound and
+// place among the entries of its side (front-facing or not) in its first bin.
 template <int B>
 __global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ views, LayerTable L,
                                                    const ProjVert* __restrict__ proj, int64_t vpv, int slot,
-                                                   uint32_t* __restrict__ count, SpanRec* __restrict__ spans,
+                                                   uint32_t* __restrict__ count, uint32_t* __restrict__ cursor,
+                                                   SpanRec* __restrict__ spans,
                                                    unsigned long long* __restrict__ status) {
   constexpr int R = kCountReps;
   constexpr int BH = bin_rows(B);
@@ -178,6 +182,7 @@ __global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ v
   const int W = V.cam.width, H = V.cam.height;
   const int ntx = (W + B - 1) / B;
   uint32_t* cv = count + view_bins_base(V, slot, k);
+  uint32_t* uv = cursor + 2 * view_bins_base(V, slot, k);   // per bin: front, other side
   const ProjVert* pview = proj + (int64_t)v * vpv;
   SpanRec* sview = spans + (int64_t)v * L.tri_off[k];
   bool ok[R];
@@ -205,16 +210,21 @@ __global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ v
   fetch(0, qa);
   if (R > 1) fetch(1, qb);
   const int lane = (int)__lane_id();
+  const uint64_t lt = __lanemask_lt();
+  uint64_t boxes[R];   // the records' box and bound words (zero for a culled or off-screen triangle),
+  uint32_t zlos[R];    // written once the places are known
+  uint32_t base[R], rank[R];
+  int leader_of[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     TriLoad& qr = (r & 1) ? qb : qa;
     int tx0 = 0, tx1 = 0, ty0 = 0, ty1 = 0;
-    bool live = ok[r];
+    bool live = ok[r], front = false;
     if (live) {
       TriSetup T;
       const int st = setup_loaded(qr, T);
       SpanRec span;
-      span.box = 0; span.zlo = 0; span.pad = 0;
+      span.box = 0; span.zlo = 0; span.rank = 0;
       if (st != kTriOk) {
         atomicAdd(status + cull_slot(st), 1ull);
         live = false;
@@ -224,26 +234,38 @@ __global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ v
           live = false;
         } else {
           tx0 = pr.i0 / B; tx1 = pr.i1 / B; ty0 = pr.j0 / BH; ty1 = pr.j1 / BH;
-          span.box = pack_box(pr.i0, pr.i1, pr.j0, pr.j1, T.orig_sign < 0);
+          front = T.orig_sign < 0;
+          span.box = pack_box(pr.i0, pr.i1, pr.j0, pr.j1, front);
           span.zlo = (uint32_t)(depth_lower_key(T, (uint32_t)t[r]) >> 32);
         }
       }
-      sview[g[r]] = span;
+      boxes[r] = span.box;
+      zlos[r] = span.zlo;
     }
     if (r + 2 < R) fetch(r + 2, qr);   // this record slot is free now
-    // first bin of every lane: lanes with the same bin elect one lane (register
-    // exchanges only), and all elected lanes add in one atomic instruction
+    // first bin of every lane, and its side: lanes of the same (bin, side) class
+    // elect one lane (register exchanges only), which reserves their places
+    // among the bin's entries of that side (the scan adds these reservations to
+    // the bin's count); every lane's place is the reservation plus its rank
     const int32_t b0 = live ? (ty0 * ntx + tx0) * k + l[r] : -1;
-    uint64_t active = __ballot(b0 >= 0);
+    const int32_t c0 = live ? 2 * b0 + (front ? 0 : 1) : -1;
+    uint64_t active = __ballot(c0 >= 0);
     uint32_t group = 0;
+    rank[r] = 0;
+    leader_of[r] = lane;
     while (active) {
       const int leader = (int)__builtin_ctzll(active);
-      const int32_t lb = __builtin_amdgcn_readlane(b0, leader);
-      const uint64_t same = __ballot(b0 == lb);
+      const int32_t lc = __builtin_amdgcn_readlane(c0, leader);
+      const uint64_t same = __ballot(c0 == lc);
+      if (c0 == lc) {
+        leader_of[r] = leader;
+        rank[r] = (uint32_t)__popcll(same & lt);
+      }
       if (lane == leader) group = (uint32_t)__popcll(same);
       active &= ~same;
     }
-    if (group) atomicAdd(cv + b0, group);
+    base[r] = 0;
+    if (group) base[r] = atomicAdd(uv + c0, group);
     if (live) {
       for (int ty = ty0; ty <= ty1; ++ty)
         for (int tx = tx0; tx <= tx1; ++tx) {
@@ -252,14 +274,32 @@ __global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ v
         }
     }
   }
+  // the reservations of every repetition were in flight together; each record
+  // is written once (a 16-byte store), with its place
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t e = __shfl(base[r], leader_of[r]) + rank[r];
+    if (ok[r]) {
+      SpanRec span;
+      span.box = boxes[r];
+      span.zlo = zlos[r];
+      span.rank = e;
+      sview[g[r]] = span;
+    }
+  }
 }
 
-// Exclusive scan of the per-bin counts into 64-bit list offsets (the total
-// can pass 2^32 when triangles cover many bins; a bin's own count stays below
-// 2^30 because n_views * triangles does).
-// Pass 1: each block scans 1024 counts, writes local prefixes and its total.
-__global__ void __launch_bounds__(256) k_scan_local(const uint32_t* __restrict__ in, uint64_t* __restrict__ out,
-                                                    uint64_t* __restrict__ partial, int64_t n) {
+// Exclusive scan of the per-bin entry counts into 64-bit list offsets (the
+// total can pass 2^32 when triangles cover many bins; a bin's own count stays
+// below 2^30 because n_views * triangles does).
+// Pass 1: each block takes 1024 bins.  A bin's entries are those counted in
+// count (triangles for which it is not the first bin) plus the places its
+// first-bin triangles reserved on both sides (first[2 b], first[2 b + 1]);
+// the sum is written back to count, then the local prefixes and the block's
+// total.
+__global__ void __launch_bounds__(256) k_scan_local(uint32_t* __restrict__ count, const uint32_t* __restrict__ first,
+                                                    uint64_t* __restrict__ out, uint64_t* __restrict__ partial,
+                                                    int64_t n) {
   __shared__ uint64_t s[256];
   const int tid = threadIdx.x;
   const int64_t base = (int64_t)blockIdx.x * 1024 + tid * 4;
@@ -267,7 +307,8 @@ __global__ void __launch_bounds__(256) k_scan_local(const uint32_t* __restrict__
   uint64_t sum = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    v[q] = base + q < n ? in[base + q] : 0u;
+    v[q] = base + q < n ? count[base + q] + first[2 * (base + q)] + first[2 * (base + q) + 1] : 0u;
+    if (base + q < n) count[base + q] = v[q];
     sum += v[q];
   }
   s[tid] = sum;
@@ -319,7 +360,10 @@ __global__ void __launch_bounds__(256) k_scan_add(uint64_t* __restrict__ out, co
 }
 
 // Write triangle ids into the bin lists: front-facing triangles from the
-// head of a bin's list, the others from its tail.  A bin whose list would end
+// head of a bin's list, the others from its tail.  A triangle's place in its
+// first bin (most triangles have only one) was reserved by the count, so it
+// takes no atomic here; its other bins are reserved here, after every
+// first-bin entry of the same side.  A bin whose list would end
 // past the capacity is left unwritten; the raster of that bin then scans every
 // triangle of its layer instead (slow but exact) and the overflow is counted.
 template <int B>
@@ -340,73 +384,45 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const vs_view* __restrict__
   const uint64_t* ov = offset + vb;
   uint32_t* uv = cursor + 2 * vb;   // per bin: [2 b] front entries from the head, [2 b + 1] the others from the tail
   const SpanRec* sview = spans + (int64_t)v * L.tri_off[k];
-  const int lane = (int)__lane_id();
-  const uint64_t lt = __lanemask_lt();
   bool ok[R];
   int l[R];
   int32_t t[R];
   int64_t g[R];
   uint64_t span[R];
+  uint32_t rank[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     ok[r] = bin_thread(L, bin_block<R>(r), l[r], t[r], g[r]);
-    span[r] = ok[r] ? sview[g[r]].box : 0ull;
+    uint4 rec = make_uint4(0u, 0u, 0u, 0u);
+    if (ok[r]) rec = reinterpret_cast<const uint4*>(sview)[g[r]];
+    span[r] = (uint64_t)rec.x | ((uint64_t)rec.y << 32);
+    rank[r] = rec.w;
   }
-  // per repetition: the first bin's (bin, side) class, the elected lane of each
-  // class and the lane's rank in it (register exchanges only)
-  int32_t b0[R], c0[R];
-  uint32_t group[R], rank[R];
-  int leader_of[R];
+  // the first bins' list ranges, all in flight together
+  int32_t b0[R];
+  uint64_t off[R];
+  uint32_t cnt[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     ok[r] = ok[r] && (span[r] & kSpanValid);
     b0[r] = -1;
+    off[r] = 0;
+    cnt[r] = 0;
     if (ok[r]) {
       int i0, i1, j0, j1;
       unpack_box(span[r], i0, i1, j0, j1);
       b0[r] = ((j0 / BH) * ntx + i0 / B) * k + l[r];
-    }
-    c0[r] = ok[r] ? 2 * b0[r] + ((span[r] & kSpanFront) ? 0 : 1) : -1;
-    uint64_t active = __ballot(c0[r] >= 0);
-    group[r] = 0;
-    rank[r] = 0;
-    leader_of[r] = lane;
-    while (active) {
-      const int leader = (int)__builtin_ctzll(active);
-      const int32_t lc = __builtin_amdgcn_readlane(c0[r], leader);
-      const uint64_t same = __ballot(c0[r] == lc);
-      if (c0[r] == lc) {
-        leader_of[r] = leader;
-        rank[r] = (uint32_t)__popcll(same & lt);
-      }
-      if (lane == leader) group[r] = (uint32_t)__popcll(same);
-      active &= ~same;
-    }
-  }
-  // the bins' list ranges and every elected lane's reservation, all in flight together
-  uint64_t off[R];
-  uint32_t cnt[R], base[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    off[r] = 0;
-    cnt[r] = 0;
-    if (ok[r]) {
       off[r] = ov[b0[r]];
       cnt[r] = cv[b0[r]];
     }
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    base[r] = 0;
-    if (group[r]) base[r] = atomicAdd(uv + c0[r], group[r]);
-  }
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t e = __shfl(base[r], leader_of[r]) + rank[r];
     if (!ok[r]) continue;
     const bool front = (span[r] & kSpanFront) != 0;
     const uint64_t end = off[r] + cnt[r];
-    if (end <= capacity) list[front ? off[r] + e : end - 1 - e] = t[r];
+    // first bin: the place reserved by the count
+    if (end <= capacity) list[front ? off[r] + rank[r] : end - 1 - rank[r]] = t[r];
     // the span's other bins, four at a time: their list ranges and reservations
     // are all in flight before any entry is written
     int i0, i1, j0, j1;
