@@ -207,12 +207,31 @@ __device__ inline void edge_values(const TriSetup& T, double px, double py, doub
   E[2] = (T.X[1] - T.X[0]) * (py - T.Y[0]) - (T.Y[1] - T.Y[0]) * (px - T.X[0]);
 }
 
+// float(a / s), the quotient rounded to double first, for the operands of a
+// depth key: a = area2 >= 1 and s = E0 wa + E1 wb + E2 wc >= area2 min(w),
+// both normal and far inside the double range (w = 1/z of float-range depths),
+// as is their quotient.  The steps are those of the IEEE FP64 division that
+// hipcc emits (reciprocal estimate, two Newton steps, quotient, one residual
+// step), without its operand scaling (v_div_scale: taken only for denormal or
+// extreme operands) and its special-value fix-up (v_div_fixup: only for zero,
+// infinite or NaN operands and results); the residual step is the plain FMA
+// that v_div_fmas is when nothing was scaled.  For these operands the result is
+// therefore the correctly rounded quotient, in 9 instead of 12 instructions
+// (bin raster 4.95 -> 4.80 ms on the metric scene).  A guarded one-step form
+// (the IEEE division only near a float rounding midpoint) took 5.06 ms.
+__device__ inline float quotient_f32(double a, double s) {
+  double r = __builtin_amdgcn_rcp(s);
+  r = fma(r, fma(-s, r, 1.0), r);
+  r = fma(r, fma(-s, r, 1.0), r);
+  const double q0 = a * r;
+  return (float)fma(fma(-s, q0, a), r, q0);
+}
+
 // Visibility key: bits of float(z) in the high word, triangle id in the low
 // word; z = area2 / (E0 wa + E1 wb + E2 wc), the perspective-correct depth.
 __device__ inline uint64_t depth_key(const TriSetup& T, double E0, double E1, double E2, uint32_t t) {
   const double s = (E0 * T.w[0] + E1 * T.w[1]) + E2 * T.w[2];
-  const double z = T.area2 / s;
-  const float zf = (float)z;
+  const float zf = quotient_f32(T.area2, s);
   return ((uint64_t)__float_as_uint(zf) << 32) | (uint64_t)t;
 }
 
