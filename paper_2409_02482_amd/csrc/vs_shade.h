@@ -545,39 +545,37 @@ __global__ void __launch_bounds__(256, BwdShape<KMAX>::blocks) k_shade_bwd(const
           pend = pend && !mine;
         }
         wave_lds_sync();
-        // flush and zero: consecutive lanes take consecutive floats of a window row (so each
-        // atomic instruction covers whole texture row segments), several rows per instruction
-        // when rows are short.  Lane -> (row offset rr, float cc0): rr = floor(lane / row) as
-        // (lane m) >> 16 with m in [2^16 / row, 2^16 / row + 1], exact for lane < 64, row <= 64.
+        // flush and zero: the window's wh rows of row = 4 ww floats are taken 64 consecutive
+        // floats per step (flat index p = y row + cc, so an atomic instruction covers one or
+        // two pieces of texture rows, and no lane idles at a row's end); y = floor(p / row) is
+        // the high word of p m with m = ceil(2^32 / row), exact since p (m row - 2^32) < 2^32
+        // for p < 4 kWaveWin and row <= 4 kWaveWin.
         const int32_t row = ww * 4;
-        const int32_t R = row >= 64 ? 1 : 64 / row;                       // uniform (scalar)
-        const uint32_t m = row >= 64 ? 0u : 65536u / (uint32_t)row + 1u;  // uniform (scalar)
-        const int32_t rr = row >= 64 ? 0 : (int32_t)(((uint32_t)lane * m) >> 16);
-        const int32_t cc0 = row >= 64 ? lane : lane - rr * row;
+        const int32_t nf = wh * row;                                // floats in the window
+        const uint32_t m = 0xffffffffu / (uint32_t)row + 1u;       // uniform (scalar)
         const int32_t bi = ri + dmin_i, bj = rj + dmin_j;   // texel of window cell (0, 0), unwrapped
         const bool flat = bi >= 0 && bi + ww <= Wt && bj >= 0 && bj + wh <= Ht;
-        if (rr < R) {
-          if (flat) {   // the window does not wrap: plain strided addresses
-            const uint32_t gbase = ((uint32_t)bj * (uint32_t)Wt + (uint32_t)bi) * 4u;
-            const uint32_t gstride = (uint32_t)Wt * 4u;
-            for (int32_t y = rr; y < wh; y += R)
-              for (int32_t cc = cc0; cc < row; cc += 64) {
-                const float val = win[y * row + cc];
-                win[y * row + cc] = 0.0f;
-                if (val != 0.0f) grad_add(G, gbase + (uint32_t)y * gstride + (uint32_t)cc, val);
-              }
-          } else {
-            // wrapped (repeat) or outside the texture (clamp: only zeros land there)
-            for (int32_t y = rr; y < wh; y += R) {
+        if (flat) {   // the window does not wrap: plain strided addresses
+          const uint32_t gbase = ((uint32_t)bj * (uint32_t)Wt + (uint32_t)bi) * 4u;
+          const uint32_t gstride = (uint32_t)Wt * 4u;
+          for (int32_t p = lane; p < nf; p += 64) {
+            const uint32_t y = __umulhi((uint32_t)p, m);
+            const uint32_t cc = (uint32_t)p - y * (uint32_t)row;
+            const float val = win[p];
+            win[p] = 0.0f;
+            if (val != 0.0f) grad_add(G, gbase + y * gstride + cc, val);
+          }
+        } else {
+          // wrapped (repeat) or outside the texture (clamp: only zeros land there)
+          for (int32_t p = lane; p < nf; p += 64) {
+            const int32_t y = (int32_t)__umulhi((uint32_t)p, m);
+            const int32_t cc = p - y * row;
+            const float val = win[p];
+            win[p] = 0.0f;
+            if (val != 0.0f) {
               const int32_t tj = abs_index(rj, dmin_j + y, Ht, wrap);
-              for (int32_t cc = cc0; cc < row; cc += 64) {
-                const float val = win[y * row + cc];
-                win[y * row + cc] = 0.0f;
-                if (val != 0.0f) {
-                  const int32_t ti = abs_index(ri, dmin_i + (cc >> 2), Wt, wrap);
-                  grad_add(G, ((uint32_t)tj * (uint32_t)Wt + (uint32_t)ti) * 4u + (uint32_t)(cc & 3), val);
-                }
-              }
+              const int32_t ti = abs_index(ri, dmin_i + (cc >> 2), Wt, wrap);
+              grad_add(G, ((uint32_t)tj * (uint32_t)Wt + (uint32_t)ti) * 4u + (uint32_t)(cc & 3), val);
             }
           }
         }
