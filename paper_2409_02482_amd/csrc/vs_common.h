@@ -54,10 +54,12 @@ struct WsLayout {
   size_t tile_view;  // int32 [16-pixel tiles of all views]: owning view (shading)
   size_t bin_view;   // int32 [raster bin tiles of all views]: owning view
   size_t proj;       // ProjVert [n_views][sum n_vert]
-  size_t count;      // u32 [n_bins] triangles per bin
+  size_t count;      // u32 [n_bins] entries per bin (before the scan: only those of triangles
+                     //   for which the bin is not the first; the scan adds the reservations)
   size_t offset;     // u64 [n_bins] exclusive prefix of count
-  size_t cursor;     // u32 [2 n_bins] scatter cursors (front from the head, others from the tail)
-  size_t spans;      // SpanRec [n_views][sum n_tri]: box and depth bound of every triangle
+  size_t cursor;     // u32 [2 n_bins] per bin and side (front from the head, others from the
+                     //   tail): first-bin places reserved by the count, then the scatter's
+  size_t spans;      // SpanRec [n_views][sum n_tri]: box, depth bound and first-bin place of every triangle
   size_t partial;    // u64 [ceil(n_bins / 1024)] scan block totals
   size_t list;       // int32 [capacity] triangle ids of all bins
   int64_t n_tiles16, n_tiles_bin, n_bins, n_partial;

@@ -16,8 +16,8 @@
 //                  tile's key skips the exact FP64 depth, and a back-facing
 //                  triangle whose bound loses everywhere in its bounding box
 //                  is skipped whole
-// Atomics on bin counters are aggregated per wavefront: lanes that hit the
-// same bin elect one lane that adds the whole group.
+// First-bin reservations are aggregated per wavefront: lanes whose first bin
+// and side agree elect one lane that reserves for the whole group.
 #pragma once
 
 #include "vs_common.h"
