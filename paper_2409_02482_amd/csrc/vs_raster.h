@@ -166,8 +166,9 @@ __device__ inline int64_t view_bins_base(const vs_view& V, int slot, int k) {
   return (int64_t)V.tile_offset[slot] * k;
 }
 
-// Count triangles per bin and record each triangle's box, depth bound and
-// place among the entries of its side (front-facing or not) in its first bin.
+// Per triangle: reserve its place among the entries of its side (front-facing
+// or not) in its first bin, count it in its other bins, and record its box,
+// depth bound and that place.
 template <int B>
 __global__ void __launch_bounds__(256) k_bin_count(const vs_view* __restrict__ views, LayerTable L,
                                                    const ProjVert* __restrict__ proj, int64_t vpv, int slot,
