@@ -272,6 +272,34 @@ def test_every_bin_size_is_bit_exact(torch_cuda, bin):
     _check_scene(sc, f"bin{bin}", bin=bin)
 
 
+def _soup_layer(rng, n, x0, x1, y0, y1, radius, cam):
+    """n random triangles (random winding) with vertices within `radius` px of centres in
+    [x0, x1) x [y0, y1) px, at random depths in [1, 3], for a camera at the origin looking down +z."""
+    c = np.stack([rng.uniform(x0, x1, n), rng.uniform(y0, y1, n)], 1)
+    px = c[:, None, :] + rng.uniform(-radius, radius, (n, 3, 2))
+    z = rng.uniform(1.0, 3.0, (n, 3))
+    xyz = np.stack([(px[..., 0] - cam.cx) * z / cam.fx, (px[..., 1] - cam.cy) * z / cam.fy, z], -1)
+    uv = rng.uniform(0.0, 1.0, (n * 3, 2))
+    return S.Mesh(xyz.reshape(-1, 3).astype(np.float32), uv.astype(np.float32),
+                  np.arange(n * 3, dtype=np.int32).reshape(n, 3))
+
+
+@pytest.mark.parametrize("bin", [8, 64])
+def test_crowded_bin_both_sides(torch_cuda, bin):
+    """20,000 small triangles per layer of both windings inside one 64 x 56 bin (hundreds of
+    wavefronts reserving places on the same two list sides), plus larger triangles across the
+    bin edges (places in their other bins taken after the first-bin ones): bit-exact."""
+    rng = np.random.default_rng(4242 + bin)
+    cam = S.Camera(160, 120, 100.0, 100.0, 80.0, 60.0, np.eye(3), np.zeros(3))
+    crowded = [_soup_layer(rng, 20000, 2, 62, 2, 54, 3.0, cam) for _ in range(2)]
+    wide = _soup_layer(rng, 3000, 0, 160, 0, 120, 20.0, cam)
+    layers = [S.Mesh(np.concatenate([m.xyz, wide.xyz]), np.concatenate([m.uv, wide.uv]),
+                     np.concatenate([m.tri, wide.tri + m.xyz.shape[0]])) for m in crowded]
+    tex = [S.uniform_texture(5, l, 16, 16, opaque=(l == 1)) for l in range(2)]
+    sc = S.Scene("crowded", layers, tex, [cam])
+    _check_scene(sc, f"crowded bin{bin}", bin=bin)
+
+
 def test_direct_raster_equals_binned(torch_cuda):
     """Two independent GPU rasterisers (binned LDS tiles, direct global atomics) agree bit for bit."""
     sc = S.make_config(2, resolution=(512, 384))
